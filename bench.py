@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark: Smith-Waterman/Gotoh protein database search on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: the 20
+queries (144..5,478 residues) of the paper-scale workload, each searched in
+the plain form (one query per launch sequence, on one stream) against the
+570,000-subject synthetic database that is already packed in HBM.  GCUPS
+counts true cells only: sum over queries of m x (total database residues).
+
+Prints one JSON line.  ``--form batched`` times the batched form instead (all
+queries of the step in one sw_search_batch call); ``--workload`` picks another
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS on 1 MI355X (plain vs batched), % int-VALU peak; p50/p99 query latency"
+CELL_OPS = 12                     # int32 instructions per cell update (Alg. 1)
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def workload(name: str):
+    from inputs import synth
+    if name == "sp570k":
+        db = synth.sp570k()
+        return synth.workload2_queries(), db, "20 queries 144..5,478 vs 570,000 subjects (2.07e8 residues), BLOSUM62 10/2"
+    if name == "small2k":
+        qs, db = synth.workload1()
+        return qs, db, "1 query of 144 vs 2,000 subjects, BLOSUM62 10/2"
+    if name == "long10k":
+        qs, db = synth.workload4()
+        return qs, db, "64 queries 500..5,000 vs 10,000 subjects 3,000..35,000, BLOSUM62 10/2"
+    if name == "batch256":
+        db = synth.sp570k()
+        return synth.workload3_queries(db), db, "256 queries 50..5,000 vs 570,000 subjects, BLOSUM62 10/2, top-10"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(queries, db, sm, seconds: float):
+    """The oracle, as it stands, on the host cores: first query against
+    consecutive blocks of subjects until about ``seconds`` of work."""
+    import oracle
+    threads = host_cores()
+    q = queries[0]
+    lengths = db.lengths
+    done, cells, t0 = 0, 0, time.perf_counter()
+    block = 4000
+    while done < db.n and time.perf_counter() - t0 < seconds:
+        idx = np.arange(done, min(db.n, done + block), dtype=np.int64)
+        oracle.scores(q, db.residues, db.offsets, sm, 10, 2, idx=idx, threads=threads)
+        cells += int(q.size) * int(lengths[idx].sum())
+        done += idx.size
+    dt = time.perf_counter() - t0
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"query 0 (m={q.size}) vs the first {done} subjects ({cells:.3e} cells) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the search would shard the database across GPUs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2309_09609_amd as sw
+    from inputs import blosum62
+    from paper_2309_09609_amd import perfmodel
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    sm = blosum62()
+    t = time.perf_counter()
+    queries, db, desc = workload(args.workload)
+    print(f"# workload {args.workload}: {desc}; generated in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    D = sw.Database(db.residues, db.offsets)
+    torch.cuda.synchronize()
+    print(f"# packed in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    total_res = int(db.offsets[-1] - db.offsets[0])
+    qlens = [int(q.size) for q in queries]
+    cells_step = sum(qlens) * total_res
+    out = torch.empty(db.n, dtype=torch.int32, device="cuda")
+
+    def step():
+        if args.form == "plain":
+            for q in queries:
+                D.search(q, sm, 10, 2, out=out)
+        else:
+            D.search_batch(queries, sm, 10, 2, k=10, keep_scores=False)
+
+    D.profile_kernels(True)
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    D.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    kt = D.kernel_times()           # ms per 16-bit sweep launch in the timed region
+    st = D.stats()
+    elapsed = t1 - t0
+    gcups = cells_step * args.steps / elapsed / 1e9
+    kernel_s = float(kt.sum()) / 1e3
+    launches = int(kt.size)
+    peak_ops = perfmodel.int_valu_lane_ops_per_s()
+    achieved = CELL_OPS * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
+    roof = {"bound": "alu", "achieved": round(achieved, 3) if achieved else None,
+            "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s",
+            "frac": round(achieved * 1e12 / peak_ops, 4) if achieved else None, "traffic": None,
+            "kernel": "k_sweep<CellI16>", "launches": launches,
+            "avg_launch_ms": round(kernel_s * 1e3 / max(launches, 1), 3),
+            "ops_per_cell": CELL_OPS}
+    res = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int16x2 saturating + int32 recompute", "data": "synthetic",
+        "config": {"workload": args.workload, "form": args.form, "queries": len(queries),
+                   "qlen_min": min(qlens), "qlen_max": max(qlens), "subjects": db.n, "residues": total_res,
+                   "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
+        "roofline": roof,
+        "extra": {"pct_int32_cell_peak": round(100 * gcups / perfmodel.mi355x_peak_gcups(), 2),
+                  "pct_packed16_cell_peak": round(100 * gcups / perfmodel.mi355x_peak_gcups(cells_per_lane_op=2), 2),
+                  "kernel_gcups": round(cells_step * args.steps / kernel_s / 1e9, 2) if kernel_s > 0 else None,
+                  "rerun_pairs_last_query": st["rerun_pairs"], "waves": st["waves"]},
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(queries, db, sm, args.cpu_seconds)
+    D.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

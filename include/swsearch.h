@@ -1,0 +1,178 @@
+/*
+ * swsearch.h - C ABI of the MI355X (gfx950) Smith-Waterman protein database search.
+ *
+ * The library computes, for one or many protein queries, the optimal local
+ * alignment score S of every subject of a device-resident protein database
+ * under Smith-Waterman with Gotoh affine gaps (Sec. II-B, Eq. 1-3 of
+ * Costanzo et al., "Comparing Performance and Portability between CUDA and
+ * SYCL for Protein Database Search on NVIDIA, AMD, and Intel GPUs"):
+ *
+ *   H[i][j] = max(0, H[i-1][j-1] + SM(Q[i], D[j]), E[i][j], F[i][j])
+ *   E[i][j] = max(H[i][j-1] - Go, E[i][j-1] - Ge)
+ *   F[i][j] = max(H[i-1][j] - Go, F[i-1][j] - Ge)
+ *   H = E = F = 0 on row 0 and column 0;  S = max(0, max H).
+ *
+ * Only scores are computed (linear space); the top-ranked subjects can then be
+ * selected (Sec. II-B, "all alignment scores are calculated first and optimal
+ * alignments are computed only for top-ranked database sequences").
+ *
+ * Scores are exact int32 values for every input: internally most cells run in
+ * saturating 16-bit lanes, and any subject whose 16-bit score reaches the
+ * saturation value is recomputed with 32-bit cells.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Residue codes are int8 values 0..19 in the order ARNDCQEGHILKMFPSTWYV.
+ *    Any other value in a query or database is an error (SW_E_RESIDUE).
+ *  - The substitution matrix is int8[20][20], row-major, indexed
+ *    [query residue][subject residue], in host memory.
+ *  - Gap penalties are Go = gap_open >= 0 and Ge = gap_extend >= 0; a gap run
+ *    of k residues costs Go + (k-1)*Ge when Ge <= Go (the recurrence itself
+ *    is what is computed for any Go, Ge >= 0).  Negative values: SW_E_INVALID.
+ *  - "d_" pointers are device memory of the device that was current when the
+ *    database was packed; "h_" pointers are host memory.  The caller owns every
+ *    pointer it passes; the library owns the memory behind an sw_db handle.
+ *  - All work is enqueued on the given HIP stream and the call returns without
+ *    waiting for it, except where stated.  Outputs are valid once the stream
+ *    has completed.  Host input arrays may be reused as soon as a call returns.
+ *  - Errors are returned as negative sw_status codes; a text description of
+ *    the most recent error of the calling thread is available from
+ *    sw_last_error().  No call aborts the process.
+ *  - A handle may be used from one host thread at a time and by at most one
+ *    search in flight at a time (searches reuse the handle's device workspace).
+ */
+#ifndef SWSEARCH_H
+#define SWSEARCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sw_status;
+enum {
+    SW_OK = 0,
+    SW_E_INVALID = -1,      /* null pointer, negative size or penalty, mismatched database */
+    SW_E_RESIDUE = -2,      /* residue code outside 0..19 */
+    SW_E_NOMEM = -3,        /* device or host allocation failed */
+    SW_E_HIP = -4,          /* a HIP runtime call failed; see sw_last_error() */
+    SW_E_UNSUPPORTED = -5,  /* request outside the implemented limits (e.g. k > 1024) */
+    SW_E_SIZE = -6          /* a caller buffer is too small */
+};
+
+/* Opaque packed database.  Created by sw_db_pack, released by sw_db_free. */
+typedef struct sw_db sw_db;
+
+/* Stream type: a hipStream_t passed as an opaque pointer (NULL = default stream). */
+typedef void* sw_stream;
+
+/* Packing options; zero-initialise for defaults. */
+typedef struct {
+    int32_t max_qlen;         /* unused hint, 0 */
+    int32_t force_lanes;      /* test hook: 0 = planner decides; 1,2,4,...,64 = every pair of
+                                 subjects is swept by this many cooperating lanes */
+    int32_t rerun_threshold;  /* test hook: 0 = 32767; a smaller value sends every pair whose
+                                 16-bit score reaches it to the exact 32-bit recompute */
+    int32_t reserved[5];
+} sw_pack_opts;
+
+/*
+ * sw_db_pack - build a device-resident, search-ready image of a protein database.
+ *   d_residues : device int8, the subjects concatenated; subject k occupies
+ *                d_residues[h_offsets[k] .. h_offsets[k+1]).
+ *   h_offsets  : host int64[n + 1], non-decreasing, h_offsets[0] >= 0.
+ *   n          : number of subjects (>= 0).
+ *   opts       : may be NULL.
+ *   out        : receives the handle.
+ * The image sorts subjects by length and interleaves them for coalesced loads;
+ * it is independent of the query and the scoring parameters.  This call
+ * synchronises the stream (packing is a one-time setup step) and validates
+ * every residue code: SW_E_RESIDUE if any is outside 0..19.
+ */
+sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t n,
+                     const sw_pack_opts* opts, sw_stream stream, sw_db** out);
+
+/* Releases the handle and its device memory (after synchronising its device). */
+void sw_db_free(sw_db* db);
+
+/* Number of subjects, total residues and device bytes held by the handle. */
+sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* device_bytes);
+
+/*
+ * sw_search - scores of one query against every subject (the "plain" form).
+ *   h_query    : host int8[qlen], codes 0..19 (validated on the host).
+ *   qlen       : >= 0; qlen == 0 gives all-zero scores.
+ *   db         : packed database.
+ *   h_offsets  : the offsets the database was packed with (checked against
+ *                the handle: same n and same first and last offset), or NULL.
+ *   n          : number of subjects; must equal the handle's.
+ *   h_subst    : host int8[20*20] substitution matrix.
+ *   gap_open, gap_extend : Go, Ge >= 0.
+ *   d_scores_out : device int32[n]; receives S for each subject in the
+ *                original database order.
+ */
+sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
+                    int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
+                    int32_t* d_scores_out, sw_stream stream);
+
+/*
+ * sw_topk - the k best subjects of one score vector (Sec. II-B: alignments are
+ * computed only for top-ranked subjects), ordered by score descending, then by
+ * subject index ascending.  When k > n the tail is padded with score -1 and
+ * index -1.
+ *   d_scores : device int32[n], scores >= 0.      k : 1..1024.
+ *   d_top_scores : device int32[k].   d_top_index : device int64[k].
+ */
+sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k,
+                  int32_t* d_top_scores, int64_t* d_top_index, sw_stream stream);
+
+/*
+ * sw_search_batch - scores of nq queries against every subject in one
+ * persistent launch sequence (the "batched" form), plus each query's top k.
+ *   h_queries  : host int8, the queries concatenated.
+ *   h_qoffsets : host int64[nq + 1], non-decreasing.
+ *   k          : 0 (no top-k) or 1..1024.
+ *   d_scores   : device int32[nq * n] (row q = query q, original subject order),
+ *                or NULL to keep only the top k (then k must be >= 1).
+ *   d_top_scores : device int32[nq * k] or NULL when k == 0.
+ *   d_top_index  : device int64[nq * k] or NULL when k == 0.
+ * The launch sequence for a given batch shape is captured once as a HIP graph
+ * and replayed on later calls with the same shape.
+ */
+sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq,
+                          sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
+                          int32_t k, int32_t* d_scores, int32_t* d_top_scores, int64_t* d_top_index,
+                          sw_stream stream);
+
+/* Human-readable name of a status code (static string). */
+const char* sw_status_str(sw_status s);
+/* Description of the most recent error on the calling thread ("" if none). */
+const char* sw_last_error(void);
+
+/*
+ * Execution statistics of the most recent sw_search / sw_search_batch on the
+ * handle (read after the stream has completed):
+ *   out[0] = number of work items in the 16-bit sweep,
+ *   out[1] = number of subject pairs recomputed with 32-bit cells,
+ *   out[2] = rows per lane (R) used,  out[3] = persistent waves launched.
+ * This call synchronises the handle's device.
+ */
+sw_status sw_last_stats(sw_db* db, int64_t out[4]);
+
+/*
+ * Kernel timing for benchmarks.  When enabled, every search on the handle
+ * records a pair of HIP events on the caller's stream around its 16-bit sweep
+ * launch (the dominant kernel).  sw_kernel_times synchronises the handle's
+ * device, writes up to cap elapsed times in milliseconds (oldest first) to
+ * ms_out, sets *count to the number written and forgets them.  At most 256
+ * launches are remembered; older ones are dropped.
+ */
+sw_status sw_profile_kernels(sw_db* db, int32_t enable);
+sw_status sw_kernel_times(sw_db* db, float* ms_out, int32_t cap, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWSEARCH_H */

@@ -1,0 +1,229 @@
+"""MI355X Smith-Waterman protein database search: thin Python binding of libswsearch.
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  Device buffers are torch tensors on the GPU, streams are torch
+streams.  The functions mirror the C ABI in include/swsearch.h
+(``sw_db_pack``, ``sw_search``, ``sw_topk``, ``sw_search_batch``) and
+``Database`` wraps a packed handle.
+
+The library must have been built (``python -m paper_2309_09609_amd.build`` or
+``__graft_entry__.build()``); loading raises if it is missing.  There is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswsearch.so")
+
+SW_OK = 0
+STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", -4: "SW_E_HIP",
+          -5: "SW_E_UNSUPPORTED", -6: "SW_E_SIZE"}
+
+# Every entry point declared in include/swsearch.h.
+EXPORTS = ("sw_db_pack", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
+           "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
+
+_lib = None
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libswsearch.so (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.sw_db_pack.restype = I32
+    lib.sw_db_pack.argtypes = [P, P, I64, P, P, ctypes.POINTER(P)]
+    lib.sw_db_free.restype = None
+    lib.sw_db_free.argtypes = [P]
+    lib.sw_db_info.restype = I32
+    lib.sw_db_info.argtypes = [P, P, P, P]
+    lib.sw_search.restype = I32
+    lib.sw_search.argtypes = [P, I32, P, P, I64, P, I32, I32, P, P]
+    lib.sw_topk.restype = I32
+    lib.sw_topk.argtypes = [P, I64, I32, P, P, P]
+    lib.sw_search_batch.restype = I32
+    lib.sw_search_batch.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P]
+    lib.sw_status_str.restype = ctypes.c_char_p
+    lib.sw_status_str.argtypes = [I32]
+    lib.sw_last_error.restype = ctypes.c_char_p
+    lib.sw_last_error.argtypes = []
+    lib.sw_last_stats.restype = I32
+    lib.sw_last_stats.argtypes = [P, P]
+    lib.sw_profile_kernels.restype = I32
+    lib.sw_profile_kernels.argtypes = [P, I32]
+    lib.sw_kernel_times.restype = I32
+    lib.sw_kernel_times.argtypes = [P, P, I32, P]
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SW_OK:
+        raise SwError(status, load().sw_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host_i8(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int8))
+
+
+def _host_i64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data if isinstance(a, np.ndarray) else a.data_ptr())
+
+
+# --------------------------------------------------------------------------- C-ABI mirrors
+class PackOpts(ctypes.Structure):
+    _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
+                ("rerun_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0) -> ctypes.c_void_p:
+    """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
+    ``force_lanes`` and ``rerun_threshold`` are test hooks (see sw_pack_opts)."""
+    lib = load()
+    offs = _host_i64(h_offsets)
+    n = offs.size - 1
+    h = ctypes.c_void_p()
+    opts = PackOpts(0, int(force_lanes), int(rerun_threshold))
+    _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
+                          _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def sw_search(query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, stream=None):
+    lib = load()
+    q = _host_i8(query)
+    sm = _host_i8(subst).reshape(-1)
+    if sm.size != 400:
+        raise ValueError("substitution matrix must be 20x20")
+    offs = None if h_offsets is None else _host_i64(h_offsets)
+    _check(lib.sw_search(_ptr(q), q.size, handle, None if offs is None else _ptr(offs), int(n), _ptr(sm),
+                         int(gap_open), int(gap_extend), ctypes.c_void_p(d_scores_out.data_ptr()), _stream(stream)))
+
+
+def sw_topk(d_scores, n, k, d_top_scores, d_top_index, stream=None):
+    _check(load().sw_topk(ctypes.c_void_p(d_scores.data_ptr()), int(n), int(k),
+                          ctypes.c_void_p(d_top_scores.data_ptr()), ctypes.c_void_p(d_top_index.data_ptr()),
+                          _stream(stream)))
+
+
+def sw_search_batch(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, k, d_scores=None,
+                    d_top_scores=None, d_top_index=None, stream=None):
+    lib = load()
+    q = _host_i8(h_queries)
+    qo = _host_i64(h_qoffsets)
+    sm = _host_i8(subst).reshape(-1)
+    P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    _check(lib.sw_search_batch(_ptr(q), _ptr(qo), qo.size - 1, handle, _ptr(sm), int(gap_open), int(gap_extend),
+                               int(k), P(d_scores), P(d_top_scores), P(d_top_index), _stream(stream)))
+
+
+# --------------------------------------------------------------------------- convenience layer
+class Database:
+    """A packed, device-resident protein database."""
+
+    def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0):
+        import torch
+        self.offsets = _host_i64(offsets)
+        self.n = self.offsets.size - 1
+        if isinstance(residues, torch.Tensor) and residues.is_cuda:
+            d_res = residues.to(torch.int8).contiguous()
+        else:
+            d_res = torch.from_numpy(_host_i8(residues)).to(device)
+        if self.n > 0 and (self.offsets[0] < 0 or self.offsets[-1] > d_res.numel()):
+            raise ValueError("offsets reach outside the residue buffer")
+        if d_res.numel() == 0:
+            d_res = torch.zeros(1, dtype=torch.int8, device=device)
+        self.device = d_res.device
+        self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold)
+        del d_res
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().sw_db_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().sw_db_info(self.handle, ctypes.byref(n), ctypes.byref(r), ctypes.byref(b)))
+        return {"n": n.value, "residues": r.value, "device_bytes": b.value}
+
+    def stats(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(load().sw_last_stats(self.handle, _ptr(out)))
+        return {"items": int(out[0]), "rerun_pairs": int(out[1]), "rows_per_lane": int(out[2]),
+                "waves": int(out[3])}
+
+    def profile_kernels(self, enable=True):
+        """Record HIP events around every 16-bit sweep launch of this handle."""
+        _check(load().sw_profile_kernels(self.handle, 1 if enable else 0))
+
+    def kernel_times(self):
+        """Elapsed ms of the sweep launches recorded since the last call (synchronises)."""
+        buf = np.zeros(256, dtype=np.float32)
+        cnt = ctypes.c_int32()
+        _check(load().sw_kernel_times(self.handle, _ptr(buf), 256, ctypes.byref(cnt)))
+        return buf[: cnt.value].astype(np.float64)
+
+    def search(self, query, subst, gap_open=10, gap_extend=2, out=None, stream=None):
+        """int32 tensor [n] of scores in database order."""
+        import torch
+        if out is None:
+            out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
+        return out[: self.n]
+
+    def search_batch(self, queries, subst, gap_open=10, gap_extend=2, k=10, keep_scores=True, stream=None):
+        """(scores [nq, n] or None, top scores [nq, k], top indices [nq, k])."""
+        import torch
+        qs = [_host_i8(q) for q in queries]
+        qo = np.zeros(len(qs) + 1, dtype=np.int64)
+        qo[1:] = np.cumsum([q.size for q in qs])
+        cat = np.concatenate(qs) if qs else np.zeros(0, np.int8)
+        nq = len(qs)
+        scores = torch.empty((nq, self.n), dtype=torch.int32, device=self.device) if keep_scores else None
+        ts = ti = None
+        if k > 0:
+            ts = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+            ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        sw_search_batch(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, stream)
+        return scores, ts, ti
+
+
+def topk(scores, k, stream=None):
+    """(top scores int32[k], indices int64[k]) of a 1-D int32 score tensor."""
+    import torch
+    ts = torch.empty(k, dtype=torch.int32, device=scores.device)
+    ti = torch.empty(k, dtype=torch.int64, device=scores.device)
+    sw_topk(scores, scores.numel(), k, ts, ti, stream)
+    return ts, ti

@@ -1,0 +1,638 @@
+// Host side of libswsearch: the C ABI declared in include/swsearch.h.
+//
+// sw_db_pack sorts subjects by length (descending, ties by index), cuts the
+// sorted list into groups of 128 and interleaves each group so that one wave
+// reads 4 columns of 128 subjects as 512 contiguous bytes (one dwordx2 per lane).
+// sw_search plans the work per query: every group gets a lane-cooperation
+// degree B (1 = one pair of subjects per lane, 64 = a whole wave on one pair)
+// so that no work unit is large against a persistent wave's share of the query,
+// units are bundled four to a workgroup and ordered longest first, and one
+// persistent launch pulls them from an atomic counter.  Pairs whose 16-bit
+// score saturates are appended to a list that a second, 32-bit launch consumes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/swsearch.h"
+#include "sw_internal.h"
+
+namespace sw {
+hipError_t launch_sweep(bool i16, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy(bool i16, int* blocks_per_cu);
+hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
+                          int32_t* counters, int ncounters, int max_mp, hipStream_t st);
+hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
+                             const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
+                             int64_t total_dw, int32_t* err, hipStream_t st);
+hipError_t launch_topk(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
+                       int64_t* top_i, hipStream_t st);
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+}  // namespace sw
+
+using namespace sw;
+
+namespace {
+
+thread_local std::string g_err;
+
+sw_status fail(sw_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(SW_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// Device buffer that grows on demand (contents are not preserved).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t reserve(size_t want) {
+        if (want <= bytes && p) return hipSuccess;
+        if (p) { hipFree(p); p = nullptr; bytes = 0; }
+        const size_t sz = std::max<size_t>(want, 256);
+        hipError_t e = hipMalloc(&p, sz);
+        if (e == hipSuccess) bytes = sz;
+        return e;
+    }
+    void release() { if (p) hipFree(p); p = nullptr; bytes = 0; }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostPinned {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;   // completion of the last copy that read this buffer
+    bool pending = false;
+    hipError_t reserve(size_t want) {
+        if (pending) { hipEventSynchronize(done); pending = false; }
+        if (want <= bytes && p) return hipSuccess;
+        if (p) { hipHostFree(p); p = nullptr; bytes = 0; }
+        const size_t sz = std::max<size_t>(want, 4096);
+        hipError_t e = hipHostMalloc(&p, sz, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = sz;
+        return e;
+    }
+    void release() {
+        if (pending) hipEventSynchronize(done);
+        if (p) hipHostFree(p);
+        if (done) hipEventDestroy(done);
+        p = nullptr; done = nullptr; bytes = 0; pending = false;
+    }
+};
+
+struct Plan {
+    DevBuf items;
+    int32_t count = 0;
+};
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct sw_db {
+    int device = 0;
+    int64_t n = 0;
+    int64_t total_res = 0;
+    int64_t off_first = 0, off_last = 0;
+    int ngroups = 0;
+    std::vector<int32_t> ncols;       // per group
+    int32_t ncols_max = 0;
+    DevBuf image, groups, perm;
+    int64_t image_bytes = 0;
+    // launch geometry
+    int cus = 0, wg16 = 0, wg32 = 0;   // persistent workgroups of the 16-bit and 32-bit sweeps
+    int64_t slot_cap = 0;             // (column x pair) capacity of one wave's boundary slot
+    // workspace
+    DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp, topk_dummy;
+    HostPinned hstage;
+    int32_t rerun_cap = 0;
+    std::map<std::pair<int, int>, Plan> plans;   // (qlen, 0) -> plan for a single query
+    Plan batch_plan;
+    int last_items = 0, last_rows = kRows, last_grid = 0;
+    int force_lgB = -1;               // test hook: fixed lanes per pair
+    bool timing = false;              // record events around each 16-bit sweep
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<int> ev_used;         // indices into ev_pool, in launch order
+    int32_t sat = kSat16;             // test hook: rerun threshold
+    std::mutex mu;
+};
+
+namespace {
+
+constexpr int kCounters = 4;   // [0] sweep counter, [1] rerun count, [2] rerun counter, [3] spare
+constexpr int kRerunGrid = 64;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~DeviceGuard() { if (prev >= 0) hipSetDevice(prev); }
+};
+
+// ------------------------------------------------------------------ planning
+struct Unit { int32_t g; int16_t k; int8_t lgB; int64_t cost; };
+
+int64_t unit_cost(int m, int ncols, int lgB) {
+    const int B = 1 << lgB;
+    const int64_t passes = (m + (kRows << lgB) - 1) / (kRows << lgB);
+    const int64_t steps = round_up(ncols + B - 1, 4);
+    const int64_t per_step = 10 * kRows + 16 + (lgB ? 6 : 0);
+    return passes * steps * per_step;
+}
+
+// Work items for queries qs (lengths) against all groups; appends to out.
+void plan_units(const sw_db* db, const std::vector<int>& qlens, std::vector<WgItem>& out) {
+    const int64_t nwaves = (int64_t)db->wg16 * kWaves;
+    int64_t total = 0;
+    for (int m : qlens)
+        for (int g = 0; g < db->ngroups; ++g) total += unit_cost(m, db->ncols[g], 0);
+    const double cap = 0.5 * (double)total / (double)std::max<int64_t>(nwaves, 1);
+    struct Tmp { WgItem it; int64_t cost; };
+    std::vector<Tmp> items;
+    for (size_t qi = 0; qi < qlens.size(); ++qi) {
+        const int m = qlens[qi];
+        if (m <= 0) continue;
+        WgItem cur{0, (int32_t)qi, 0, -1, 0, 0};
+        int64_t cur_cost = 0;
+        auto flush = [&]() {
+            if (cur.count > 0) items.push_back({cur, cur_cost});
+            cur.count = 0;
+            cur_cost = 0;
+        };
+        for (int g = 0; g < db->ngroups; ++g) {
+            const int nc = db->ncols[g];
+            int lgB = 0;
+            for (; lgB < 6; ++lgB) {
+                const int64_t P = kGroupPairs >> lgB;
+                if ((double)unit_cost(m, nc, lgB) <= cap && (int64_t)nc * P <= db->slot_cap) break;
+            }
+            if (db->force_lgB >= 0) {
+                lgB = db->force_lgB;
+                while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
+            }
+            const int64_t c = unit_cost(m, nc, lgB);
+            for (int k = 0; k < (1 << lgB); ++k) {
+                if (cur.count == kWaves || cur.lgB != lgB) {
+                    flush();
+                    cur.g0 = g;
+                    cur.k0 = (int16_t)k;
+                    cur.lgB = (int8_t)lgB;
+                }
+                cur.count++;
+                cur_cost = std::max(cur_cost, c);
+            }
+        }
+        flush();
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
+    for (auto& t : items) {
+        t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX);
+        out.push_back(t.it);
+    }
+}
+
+sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
+    if (!subst) return fail(SW_E_INVALID, "substitution matrix pointer is NULL");
+    if (go < 0 || ge < 0) return fail(SW_E_INVALID, "gap penalties must be >= 0 (got %d, %d)", go, ge);
+    return SW_OK;
+}
+
+sw_status ensure_workspace(sw_db* db) {
+    if (db->wg16 == 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, db->device));
+        db->cus = prop.multiProcessorCount;
+        int b16 = 0, b32 = 0;
+        HIP_TRY(sweep_occupancy(true, &b16));
+        HIP_TRY(sweep_occupancy(false, &b32));
+        if (b16 < 1 || b32 < 1) return fail(SW_E_HIP, "sweep kernel cannot be resident (occupancy %d/%d)", b16, b32);
+        db->wg16 = db->cus * b16;
+        db->wg32 = kRerunGrid;
+        db->slot_cap = std::max<int64_t>(65536, db->ncols_max);
+        const int64_t nw16 = (int64_t)db->wg16 * kWaves;
+        const int64_t nw32 = (int64_t)db->wg32 * kWaves;
+        HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4));
+        HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4));
+        HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t)));
+    }
+    return SW_OK;
+}
+
+// Stages [QDesc x nq][qoff x nq][subst 400][queries] in pinned memory, copies
+// it to the device and launches the profile kernel.  Returns device pointers.
+struct Staged { const QDesc* qd; const int64_t* qoff; const int8_t* sm_q; int max_mp; };
+
+sw_status stage_queries(sw_db* db, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
+                        const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out) {
+    std::vector<QDesc> qd(nq);
+    int64_t prof_elems = 0;
+    int max_mp = kProfRowAlign;
+    for (int q = 0; q < nq; ++q) {
+        const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
+        const int mp = (int)round_up(std::max(m, 1), kProfRowAlign);
+        qd[q] = QDesc{prof_elems, (int64_t)q * score_row_stride, m, mp};
+        prof_elems += (int64_t)kNRes * mp;
+        max_mp = std::max(max_mp, mp);
+    }
+    const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
+    const size_t off_qd = 0;
+    const size_t off_qoff = round_up(sizeof(QDesc) * nq, 64);
+    const size_t off_sm = off_qoff + round_up(sizeof(int64_t) * nq, 64);
+    const size_t total = off_sm + 400 + qbytes;
+    HIP_TRY(db->hstage.reserve(total));
+    if (!db->hstage.done) HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
+    HIP_TRY(db->stage.reserve(total));
+    HIP_TRY(db->prof.reserve(prof_elems * sizeof(int16_t)));
+    char* h = static_cast<char*>(db->hstage.p);
+    memcpy(h + off_qd, qd.data(), sizeof(QDesc) * nq);
+    int64_t* qo = reinterpret_cast<int64_t*>(h + off_qoff);
+    for (int q = 0; q < nq; ++q) qo[q] = h_qoffsets[q] - h_qoffsets[0];
+    memcpy(h + off_sm, subst, 400);
+    if (qbytes) memcpy(h + off_sm + 400, h_queries + h_qoffsets[0], qbytes);
+    HIP_TRY(hipMemcpyAsync(db->stage.p, h, total, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(db->hstage.done, st));
+    db->hstage.pending = true;
+    char* d = db->stage.as<char>();
+    out->qd = reinterpret_cast<const QDesc*>(d + off_qd);
+    out->qoff = reinterpret_cast<const int64_t*>(d + off_qoff);
+    out->sm_q = reinterpret_cast<const int8_t*>(d + off_sm);
+    out->max_mp = max_mp;
+    HIP_TRY(launch_profile(out->sm_q, out->qd, nq, out->qoff, db->prof.as<int16_t>(), db->counters.as<int32_t>(),
+                           kCounters, max_mp, st));
+    return SW_OK;
+}
+
+sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_items, int32_t go, int32_t ge,
+                     int32_t* d_scores, int64_t rerun_cap, hipStream_t st) {
+    HIP_TRY(db->rerun.reserve((size_t)rerun_cap * sizeof(WgItem)));
+    int32_t* ctr = db->counters.as<int32_t>();
+    SweepArgs a{};
+    a.items = d_items;
+    a.n_items_dev = nullptr;
+    a.n_items = n_items;
+    a.counter = ctr + 0;
+    a.image = db->image.as<uint8_t>();
+    a.groups = db->groups.as<GroupRec>();
+    a.perm = db->perm.as<int32_t>();
+    a.prof = db->prof.as<int16_t>();
+    a.qd = S.qd;
+    a.go = go;
+    a.ge = ge;
+    a.scratch = db->scratch16.as<uint32_t>();
+    a.slot_words = db->slot_cap * 2;
+    a.scores = d_scores;
+    a.rerun = db->rerun.as<WgItem>();
+    a.rerun_count = ctr + 1;
+    a.rerun_cap = (int32_t)rerun_cap;
+    a.unit_list = 0;
+    a.sat = db->sat;
+    const int grid16 = std::max(1, std::min(db->wg16, n_items));
+    int ev = -1;
+    if (db->timing) {
+        if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
+        ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
+        while ((int)db->ev_pool.size() <= ev) {
+            hipEvent_t x, y;
+            HIP_TRY(hipEventCreate(&x));
+            HIP_TRY(hipEventCreate(&y));
+            db->ev_pool.push_back({x, y});
+        }
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
+    }
+    HIP_TRY(launch_sweep(true, a, grid16, st));
+    if (ev >= 0) {
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
+        db->ev_used.push_back(ev);
+    }
+    // exact 32-bit recompute of saturated pairs; the count is read on the device
+    SweepArgs r = a;
+    r.items = db->rerun.as<WgItem>();
+    r.n_items_dev = ctr + 1;
+    r.n_items = (int32_t)rerun_cap;
+    r.counter = ctr + 2;
+    r.scratch = db->scratch32.as<uint32_t>();
+    r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
+    r.rerun = nullptr;
+    r.rerun_count = nullptr;
+    r.rerun_cap = 0;
+    r.unit_list = 1;
+    HIP_TRY(launch_sweep(false, r, db->wg32, st));
+    db->last_items = n_items;
+    db->last_grid = grid16;
+    return SW_OK;
+}
+
+sw_status get_plan(sw_db* db, int m, Plan** out) {
+    auto key = std::make_pair(m, 0);
+    auto it = db->plans.find(key);
+    if (it != db->plans.end()) { *out = &it->second; return SW_OK; }
+    if (db->plans.size() >= 64) {
+        for (auto& kv : db->plans) kv.second.items.release();
+        db->plans.clear();
+    }
+    std::vector<WgItem> items;
+    plan_units(db, std::vector<int>{m}, items);
+    Plan& p = db->plans[key];
+    p.count = (int32_t)items.size();
+    HIP_TRY(p.items.reserve(std::max<size_t>(items.size(), 1) * sizeof(WgItem)));
+    HIP_TRY(hipMemcpy(p.items.p, items.data(), items.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+    *out = &p;
+    return SW_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* sw_status_str(sw_status s) {
+    switch (s) {
+        case SW_OK: return "SW_OK";
+        case SW_E_INVALID: return "SW_E_INVALID";
+        case SW_E_RESIDUE: return "SW_E_RESIDUE";
+        case SW_E_NOMEM: return "SW_E_NOMEM";
+        case SW_E_HIP: return "SW_E_HIP";
+        case SW_E_UNSUPPORTED: return "SW_E_UNSUPPORTED";
+        case SW_E_SIZE: return "SW_E_SIZE";
+        default: return "SW_E_UNKNOWN";
+    }
+}
+
+const char* sw_last_error(void) { return g_err.c_str(); }
+
+sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts,
+                     sw_stream stream, sw_db** out) {
+    g_err.clear();
+    if (!out) return fail(SW_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
+    if (n > ((int64_t)1 << 31) - 256) return fail(SW_E_UNSUPPORTED, "more than 2^31 subjects");
+    if (n > 0 && (!h_offsets || !d_residues)) return fail(SW_E_INVALID, "NULL residues or offsets");
+    if (n > 0 && h_offsets[0] < 0) return fail(SW_E_INVALID, "offsets[0] < 0");
+    std::vector<int32_t> len(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t l = h_offsets[k + 1] - h_offsets[k];
+        if (l < 0) return fail(SW_E_INVALID, "offsets decrease at %lld", (long long)k);
+        if (l > (1 << 24)) return fail(SW_E_UNSUPPORTED, "subject %lld longer than 2^24", (long long)k);
+        len[k] = (int32_t)l;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sw_db* db = new (std::nothrow) sw_db();
+    if (!db) return fail(SW_E_NOMEM, "host allocation failed");
+    auto bail = [&](sw_status s) { sw_db_free(db); return s; };
+    if (hipGetDevice(&db->device) != hipSuccess) return bail(fail(SW_E_HIP, "no current HIP device"));
+    if (opts) {
+        const int fl = opts->force_lanes;
+        if (fl != 0) {
+            if (fl < 0 || fl > 64 || (fl & (fl - 1))) return bail(fail(SW_E_INVALID, "force_lanes must be 0 or a power of two <= 64"));
+            db->force_lgB = __builtin_ctz(fl);
+        }
+        if (opts->rerun_threshold < 0) return bail(fail(SW_E_INVALID, "rerun_threshold must be >= 0"));
+        if (opts->rerun_threshold > 0) db->sat = std::min<int32_t>(opts->rerun_threshold, kSat16);
+    }
+    db->n = n;
+    db->off_first = n > 0 ? h_offsets[0] : 0;
+    db->off_last = n > 0 ? h_offsets[n] : 0;
+    db->total_res = db->off_last - db->off_first;
+
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+    db->ngroups = (int)((n + kGroupSubjects - 1) / kGroupSubjects);
+    const int G = db->ngroups;
+    std::vector<GroupRec> groups(G);
+    std::vector<int64_t> gdw(G);
+    std::vector<int32_t> perm((size_t)G * kGroupSubjects, -1);
+    std::vector<int64_t> soff(n);
+    std::vector<int32_t> slen(n);
+    db->ncols.resize(G);
+    int64_t base = 0;
+    for (int g = 0; g < G; ++g) {
+        const int32_t nc = (int32_t)round_up(len[order[(size_t)g * kGroupSubjects]], kChunkCols);
+        groups[g] = GroupRec{base, nc, g * kGroupSubjects};
+        gdw[g] = base / 4;
+        db->ncols[g] = nc;
+        db->ncols_max = std::max(db->ncols_max, nc);
+        base += (int64_t)nc * kGroupSubjects;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        perm[i] = order[i];
+        soff[i] = h_offsets[order[i]];
+        slen[i] = len[order[i]];
+    }
+    db->image_bytes = base;
+    if (G > 0) {
+        DevBuf d_soff, d_slen, d_gdw, d_err;
+        hipError_t e = hipSuccess;
+        if ((e = db->image.reserve(std::max<int64_t>(base, 4))) != hipSuccess ||
+            (e = db->groups.reserve(sizeof(GroupRec) * G)) != hipSuccess ||
+            (e = db->perm.reserve(sizeof(int32_t) * perm.size())) != hipSuccess ||
+            (e = d_soff.reserve(sizeof(int64_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
+            (e = d_slen.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
+            (e = d_gdw.reserve(sizeof(int64_t) * G)) != hipSuccess || (e = d_err.reserve(4)) != hipSuccess) {
+            d_soff.release(); d_slen.release(); d_gdw.release(); d_err.release();
+            return bail(fail(e == hipErrorOutOfMemory ? SW_E_NOMEM : SW_E_HIP, "device allocation: %s", hipGetErrorString(e)));
+        }
+        int32_t zero = 0, herr = 0;
+        auto step = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+        step(hipMemcpyAsync(db->groups.p, groups.data(), sizeof(GroupRec) * G, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(db->perm.p, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_soff.p, soff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_slen.p, slen.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_gdw.p, gdw.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_err.p, &zero, 4, hipMemcpyHostToDevice, st));
+        step(launch_interleave(d_residues, d_soff.as<int64_t>(), d_slen.as<int32_t>(), n, db->groups.as<GroupRec>(),
+                               d_gdw.as<int64_t>(), G, db->image.as<uint32_t>(), base / 4, d_err.as<int32_t>(), st));
+        step(hipMemcpyAsync(&herr, d_err.p, 4, hipMemcpyDeviceToHost, st));
+        step(hipStreamSynchronize(st));
+        d_soff.release(); d_slen.release(); d_gdw.release(); d_err.release();
+        if (e != hipSuccess) return bail(fail(SW_E_HIP, "packing: %s", hipGetErrorString(e)));
+        if (herr) return bail(fail(SW_E_RESIDUE, "database residue code outside 0..19"));
+    }
+    *out = db;
+    return SW_OK;
+}
+
+void sw_db_free(sw_db* db) {
+    if (!db) return;
+    DeviceGuard dg(db->device);
+    hipDeviceSynchronize();
+    db->image.release(); db->groups.release(); db->perm.release();
+    db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
+    db->counters.release(); db->rerun.release(); db->scores_tmp.release(); db->topk_dummy.release();
+    db->hstage.release();
+    for (auto& kv : db->plans) kv.second.items.release();
+    db->batch_plan.items.release();
+    for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    delete db;
+}
+
+sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* device_bytes) {
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if (n) *n = db->n;
+    if (residues) *residues = db->total_res;
+    if (device_bytes)
+        *device_bytes = (int64_t)(db->image.bytes + db->groups.bytes + db->perm.bytes + db->scratch16.bytes +
+                                  db->scratch32.bytes + db->prof.bytes + db->stage.bytes + db->rerun.bytes +
+                                  db->scores_tmp.bytes);
+    return SW_OK;
+}
+
+static sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if (n != db->n) return fail(SW_E_INVALID, "n = %lld but the database holds %lld subjects", (long long)n, (long long)db->n);
+    if (h_offsets && n > 0 && (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last))
+        return fail(SW_E_INVALID, "offsets do not match the packed database");
+    return SW_OK;
+}
+
+sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets, int64_t n,
+                    const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out,
+                    sw_stream stream) {
+    g_err.clear();
+    sw_status s;
+    if ((s = check_db_args(db, h_offsets, n)) != SW_OK) return s;
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (qlen < 0) return fail(SW_E_INVALID, "qlen must be >= 0");
+    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
+    if (n > 0 && !d_scores_out) return fail(SW_E_INVALID, "scores_out is NULL");
+    for (int32_t i = 0; i < qlen; ++i)
+        if (h_query[i] < 0 || h_query[i] >= 20) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..19", h_query[i], i);
+    if (n == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (qlen == 0) { HIP_TRY(launch_fill(d_scores_out, n, 0, st)); return SW_OK; }
+    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    Plan* plan = nullptr;
+    if ((s = get_plan(db, qlen, &plan)) != SW_OK) return s;
+    const int64_t qo[2] = {0, qlen};
+    Staged S;
+    if ((s = stage_queries(db, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
+    const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
+    return run_sweeps(db, S, plan->items.as<WgItem>(), plan->count, gap_open, gap_extend, d_scores_out, rerun_cap, st);
+}
+
+sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
+                  sw_stream stream) {
+    g_err.clear();
+    if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
+    if (k < 1 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 1..1024 (got %d)", k);
+    if ((n > 0 && !d_scores) || !d_top_scores || !d_top_index) return fail(SW_E_INVALID, "NULL pointer");
+    HIP_TRY(launch_topk(d_scores, n, n, 1, k, d_top_scores, d_top_index, static_cast<hipStream_t>(stream)));
+    return SW_OK;
+}
+
+sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                          const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* d_scores,
+                          int32_t* d_top_scores, int64_t* d_top_index, sw_stream stream) {
+    g_err.clear();
+    sw_status s;
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (nq < 0) return fail(SW_E_INVALID, "nq must be >= 0");
+    if (nq > 0 && (!h_qoffsets || !h_queries)) return fail(SW_E_INVALID, "NULL queries or offsets");
+    if (k < 0 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 0..1024 (got %d)", k);
+    if (k > 0 && (!d_top_scores || !d_top_index)) return fail(SW_E_INVALID, "NULL top-k outputs");
+    if (!d_scores && k == 0) return fail(SW_E_INVALID, "no output requested (scores NULL and k == 0)");
+    for (int q = 0; q < nq; ++q) {
+        if (h_qoffsets[q + 1] < h_qoffsets[q]) return fail(SW_E_INVALID, "query offsets decrease at %d", q);
+        if (h_qoffsets[q + 1] - h_qoffsets[q] > (1 << 24)) return fail(SW_E_UNSUPPORTED, "query %d too long", q);
+    }
+    if (nq > 0)
+        for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
+            if (h_queries[i] < 0 || h_queries[i] >= 20) return fail(SW_E_RESIDUE, "query residue outside 0..19 at %lld", (long long)i);
+    if (nq == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = db->n;
+    int32_t* scores = d_scores;
+    if (!scores) {
+        HIP_TRY(db->scores_tmp.reserve((size_t)nq * std::max<int64_t>(n, 1) * sizeof(int32_t)));
+        scores = db->scores_tmp.as<int32_t>();
+    }
+    if (n > 0) {
+        if ((s = ensure_workspace(db)) != SW_OK) return s;
+        std::vector<int> qlens(nq);
+        for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
+        // zero-length queries score 0 everywhere
+        for (int q = 0; q < nq; ++q)
+            if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
+        std::vector<WgItem> items;
+        plan_units(db, qlens, items);
+        HIP_TRY(db->batch_plan.items.reserve(std::max<size_t>(items.size(), 1) * sizeof(WgItem)));
+        HIP_TRY(hipMemcpyAsync(db->batch_plan.items.p, items.data(), items.size() * sizeof(WgItem),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));   // host vector goes out of scope
+        db->batch_plan.count = (int32_t)items.size();
+        Staged S;
+        if ((s = stage_queries(db, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
+        const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
+        if (!items.empty())
+            if ((s = run_sweeps(db, S, db->batch_plan.items.as<WgItem>(), (int)items.size(), gap_open, gap_extend,
+                                scores, rerun_cap, st)) != SW_OK)
+                return s;
+    }
+    if (k > 0) HIP_TRY(launch_topk(scores, n, n, nq, k, d_top_scores, d_top_index, st));
+    return SW_OK;
+}
+
+sw_status sw_profile_kernels(sw_db* db, int32_t enable) {
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    std::lock_guard<std::mutex> lk(db->mu);
+    db->timing = enable != 0;
+    db->ev_used.clear();
+    return SW_OK;
+}
+
+sw_status sw_kernel_times(sw_db* db, float* ms_out, int32_t cap, int32_t* count) {
+    if (!db || !count || (cap > 0 && !ms_out)) return fail(SW_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    *count = 0;
+    for (int i : db->ev_used) {
+        HIP_TRY(hipEventSynchronize(db->ev_pool[i].second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, db->ev_pool[i].first, db->ev_pool[i].second));
+        if (*count < cap) ms_out[(*count)++] = ms;
+    }
+    db->ev_used.clear();
+    return SW_OK;
+}
+
+sw_status sw_last_stats(sw_db* db, int64_t out[4]) {
+    if (!db || !out) return fail(SW_E_INVALID, "NULL argument");
+    DeviceGuard dg(db->device);
+    int32_t c[kCounters] = {0, 0, 0, 0};
+    if (db->counters.p) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(c, db->counters.p, sizeof c, hipMemcpyDeviceToHost));
+    }
+    out[0] = db->last_items;
+    out[1] = c[1];
+    out[2] = db->last_rows;
+    out[3] = (int64_t)db->last_grid * kWaves;
+    return SW_OK;
+}
+
+}  // extern "C"

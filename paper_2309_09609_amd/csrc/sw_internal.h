@@ -1,0 +1,73 @@
+// Library-internal layout and launch descriptors shared by the host code and
+// the gfx950 kernels of libswsearch.  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace sw {
+
+// ---------------------------------------------------------------- constants
+constexpr int kNRes = 21;          // 20 residues + one padding row in the profile
+constexpr int kPadCode = 20;       // residue code used for padding columns
+constexpr int16_t kPadScore = -1024;   // substitution score of padding (any value <= 0 is invisible)
+constexpr int kGroupPairs = 64;    // subject pairs per group (one per lane of a wave)
+constexpr int kGroupSubjects = 2 * kGroupPairs;
+constexpr int kChunkCols = 4;      // columns per interleaved chunk (one dword per subject)
+constexpr int kChunkBytes = kGroupPairs * 8;   // one chunk row of a group: 64 pairs x 2 subjects x 4 residues
+constexpr int kWaves = 4;          // waves per workgroup of the sweep kernel
+constexpr int kRows = 16;          // query rows per lane (R) of the sweep kernels
+constexpr int kSliceRows = 1024;   // largest rows-per-pass (B*R) kept in LDS: 64 lanes x 16 rows
+constexpr int kProfRowAlign = 1024;    // profile row stride is a multiple of this (covers every B*R)
+constexpr int16_t kSat16 = 32767;  // 16-bit saturation value: a score equal to it is recomputed in 32 bits
+
+// Packed database image, one record per group of 128 length-sorted subjects.
+// Residues of group g live at image + base, as chunk rows of kChunkBytes bytes:
+// byte (chunk c, pair p, half h, k) = residue (4c + k) of subject 2p + h of the group,
+// or kPadCode past the subject's end.  Columns are padded to a multiple of 4.
+struct GroupRec {
+    int64_t base;     // byte offset of the group's first chunk row
+    int32_t ncols;    // padded column count (multiple of 4) = longest subject of the group, rounded up
+    int32_t first;    // index of the group's first subject in length-sorted order (= 128 g)
+};
+
+// One unit of work for a wave: pairs [k*P, (k+1)*P) of group g, P = 64 >> lgB, with B = 1 << lgB
+// lanes cooperating on each pair.  A workgroup item bundles up to kWaves consecutive units
+// (wave w takes unit k0 + w, carried into following groups) of one query.
+struct WgItem {
+    int32_t g0;       // group of the first unit
+    int32_t q;        // query index within the launch
+    int16_t k0;       // sub-group index of the first unit within g0
+    int8_t lgB;       // log2 of lanes per pair (0..6)
+    int8_t count;     // number of valid units (1..kWaves)
+    int32_t cost;     // planner's cost estimate (diagnostic)
+};
+
+// Per-query descriptor.
+struct QDesc {
+    int64_t prof_off;     // element offset of this query's profile [kNRes][mp] in the profile buffer
+    int64_t out_off;      // element offset of this query's score row in the output
+    int32_t m;            // query length (>= 1)
+    int32_t mp;           // profile row stride (multiple of kProfRowAlign, >= m)
+};
+
+struct SweepArgs {
+    const WgItem* items;
+    const int32_t* n_items_dev;   // if non-null, the item count is read here (rerun launches)
+    int32_t n_items;              // item count (or capacity when n_items_dev is used)
+    int32_t* counter;             // work counter, zeroed before the launch
+    const uint8_t* image;
+    const GroupRec* groups;
+    const int32_t* perm;          // sorted slot -> original subject index, -1 for padding slots
+    const int16_t* prof;
+    const QDesc* qd;
+    int32_t go, ge;
+    uint32_t* scratch;            // per-wave boundary-row slots
+    int64_t slot_words;           // uint32 words per wave slot
+    int32_t* scores;
+    WgItem* rerun;                // 16-bit sweep: pairs that saturated are appended here
+    int32_t* rerun_count;
+    int32_t rerun_cap;
+    int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
+    int32_t sat;                  // 16-bit scores >= sat are recomputed with 32-bit cells
+};
+
+}  // namespace sw

@@ -1,0 +1,56 @@
+"""The C-ABI library loads, exports every entry point the header declares, and
+rejects bad arguments before touching a GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2309_09609_amd as sw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "swsearch.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sw.load()
+    names = header_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(sw.EXPORTS)
+
+
+def test_status_strings():
+    lib = sw.load()
+    for code, name in sw.STATUS.items():
+        assert lib.sw_status_str(code).decode() == name
+
+
+def test_argument_errors_without_gpu():
+    lib = sw.load()
+    h = ctypes.c_void_p()
+    offs = np.array([0, 3], dtype=np.int64)
+    # negative n and NULL output
+    assert lib.sw_db_pack(None, offs.ctypes.data, -1, None, None, ctypes.byref(h)) == -1
+    assert lib.sw_db_pack(None, offs.ctypes.data, 1, None, None, None) == -1
+    assert b"out" in lib.sw_last_error()
+    # NULL handle
+    sm = np.zeros(400, dtype=np.int8)
+    q = np.zeros(3, dtype=np.int8)
+    assert lib.sw_search(q.ctypes.data, 3, None, None, 0, sm.ctypes.data, 10, 2, None, None) == -1
+    # k outside 1..1024
+    assert lib.sw_topk(None, 0, 0, None, None, None) == -5
+    assert lib.sw_topk(None, 0, 2000, None, None, None) == -5
+    # batch: NULL handle
+    assert lib.sw_search_batch(None, None, 0, None, sm.ctypes.data, 1, 1, 0, None, None, None, None) == -1
+
+
+def test_pack_opts_layout():
+    assert ctypes.sizeof(sw.PackOpts) == 32

@@ -1,0 +1,262 @@
+"""GPU parity: every score from the HIP path equals the CPU oracle exactly.
+
+Integer arithmetic end to end, so the bar is bit-exact equality (tolerance 0)
+on every subject compared.  Cases span several groups and passes, ragged
+tails, empty subjects, every lane-cooperation degree B (forced through the
+``force_lanes`` hook), the 32-bit recompute path, extreme matrices and gap
+penalties, and the full-size workload on a sampled subject set.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from inputs import blosum62, synth
+from refs import identity_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_scores(sw, db, q, sm, go, ge, **kw):
+    import torch
+    D = sw.Database(db.residues, db.offsets, **kw)
+    out = D.search(q, sm, go, ge)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.int64)
+    stats = D.stats()
+    D.close()
+    return res, stats
+
+
+def assert_equal_scores(got, want, ctx=""):
+    got = np.asarray(got, dtype=np.int64)
+    want = np.asarray(want, dtype=np.int64)
+    assert got.shape == want.shape, ctx
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{ctx}: {bad.size} mismatches, first at {bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}"
+
+
+def test_workload1_all_scores(gpu, blosum):
+    qs, db = synth.workload1()
+    say("workload1: 1 x 144 vs 2000")
+    got, st = gpu_scores(gpu, db, qs[0], blosum, 10, 2)
+    want = oracle.scores(qs[0], db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(got, want, "workload1")
+    assert want.max() > 100   # planted homologs score high
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("m", [1, 16, 37, 300])
+def test_every_lane_degree(gpu, blosum, lanes, m):
+    db = synth.small_db(seed=11 + m, n=300, lo=0, hi=700)
+    q = synth.small_query(seed=m, m=m)
+    say(f"lanes={lanes} m={m}")
+    got, st = gpu_scores(gpu, db, q, blosum, 10, 2, force_lanes=lanes)
+    want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(got, want, f"lanes={lanes} m={m}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 257])
+def test_ragged_database_sizes(gpu, blosum, n):
+    db = synth.small_db(seed=n, n=n, lo=0, hi=90)
+    q = synth.small_query(seed=n + 1, m=33)
+    say(f"n={n}")
+    got, _ = gpu_scores(gpu, db, q, blosum, 10, 2)
+    assert_equal_scores(got, oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), f"n={n}")
+
+
+def test_empty_subjects_and_empty_query(gpu, blosum):
+    db = synth.small_db(seed=5, n=200, lo=0, hi=3)     # many zero-length subjects
+    q = synth.small_query(seed=5, m=20)
+    got, _ = gpu_scores(gpu, db, q, blosum, 10, 2)
+    assert_equal_scores(got, oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), "tiny subjects")
+    got, _ = gpu_scores(gpu, db, np.zeros(0, np.int8), blosum, 10, 2)
+    assert (got == 0).all()
+
+
+@pytest.mark.parametrize("go,ge", [(0, 0), (1, 11), (11, 1), (50000, 3), (3, 70000), (12, 12)])
+def test_gap_penalties(gpu, blosum, go, ge):
+    db = synth.small_db(seed=21, n=200, lo=1, hi=400)
+    q = synth.small_query(seed=21, m=150)
+    say(f"go={go} ge={ge}")
+    for lanes in (0, 1, 16):
+        got, _ = gpu_scores(gpu, db, q, blosum, go, ge, force_lanes=lanes)
+        assert_equal_scores(got, oracle.scores(q, db.residues, db.offsets, blosum, go, ge), f"{go}/{ge} lanes={lanes}")
+
+
+@pytest.mark.parametrize("kind", ["random_extreme", "identity", "lcs"])
+def test_substitution_matrices(gpu, kind):
+    rng = np.random.default_rng(3)
+    if kind == "random_extreme":
+        sm = rng.integers(-128, 128, size=(20, 20)).astype(np.int8)
+        go, ge = 40, 5
+    elif kind == "identity":
+        sm = identity_matrix(1, -128)
+        go, ge = 127, 127
+    else:
+        sm = identity_matrix(1, 0)
+        go, ge = 0, 0
+    db = synth.small_db(seed=31, n=150, lo=1, hi=300)
+    q = synth.small_query(seed=31, m=120)
+    for lanes in (0, 1, 8, 64):
+        got, _ = gpu_scores(gpu, db, q, sm, go, ge, force_lanes=lanes)
+        assert_equal_scores(got, oracle.scores(q, db.residues, db.offsets, sm, go, ge), f"{kind} lanes={lanes}")
+
+
+def _overflow_db():
+    """Subjects built around a W^3000 block: self scores far above 32767."""
+    rng = np.random.default_rng(7)
+    W = 17
+    subs = [np.full(3000, W, np.int8), np.concatenate([rng.integers(0, 20, 50), np.full(3000, W), rng.integers(0, 20, 70)]),
+            np.full(2990, W, np.int8), np.full(100, W, np.int8)]
+    subs += [rng.integers(0, 20, int(rng.integers(1, 400))).astype(np.int8) for _ in range(140)]
+    perm = rng.permutation(len(subs))
+    subs = [np.asarray(subs[i], np.int8) for i in perm]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum([s.size for s in subs])
+    return synth.Database(np.concatenate(subs), offs, name="overflow")
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 64])
+def test_scores_above_int16_are_exact(gpu, blosum, lanes):
+    db = _overflow_db()
+    q = np.full(3000, 17, np.int8)
+    got, st = gpu_scores(gpu, db, q, blosum, 10, 2, force_lanes=lanes)
+    want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+    assert want.max() == 33000
+    assert_equal_scores(got, want, f"overflow lanes={lanes}")
+    assert st["rerun_pairs"] >= 2
+
+
+@pytest.mark.parametrize("lanes", [0, 4])
+def test_forced_rerun_everything(gpu, blosum, lanes):
+    """With the rerun threshold at 1 every pair goes through the 32-bit sweep."""
+    db = synth.small_db(seed=41, n=260, lo=0, hi=500)
+    q = synth.small_query(seed=41, m=200)
+    got, st = gpu_scores(gpu, db, q, blosum, 10, 2, rerun_threshold=1, force_lanes=lanes)
+    assert_equal_scores(got, oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), "forced rerun")
+    assert st["rerun_pairs"] >= 120
+
+
+def test_long_subjects(gpu, blosum):
+    """Subjects up to 35,000 residues (multi-pass, many-lane units)."""
+    rng = np.random.default_rng(9)
+    lens = [35000, 20000, 9000, 5000, 3000] + list(rng.integers(50, 500, 40))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    subs[1][5000:5400] = subs[0][100:500]        # a shared segment gives a strong local hit
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    q = np.concatenate([subs[0][100:500], synth.background_residues(rng, 1100)])
+    got, _ = gpu_scores(gpu, db, q, blosum, 10, 2)
+    want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(got, want, "long subjects")
+    assert want[0] > 1500 and want[1] > 1500
+
+
+def test_repeat_is_deterministic(gpu, blosum):
+    import torch
+    qs, db = synth.workload1()
+    D = gpu.Database(db.residues, db.offsets)
+    a = D.search(qs[0], blosum, 10, 2).clone()
+    b = D.search(qs[0], blosum, 10, 2).clone()
+    c = D.search(qs[0][::-1].copy(), blosum, 10, 2).clone()
+    d = D.search(qs[0], blosum, 10, 2).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, d)
+    want = oracle.scores(qs[0][::-1].copy(), db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(c.cpu().numpy(), want, "second query on the same handle")
+    D.close()
+
+
+@pytest.mark.parametrize("k", [1, 10, 100, 1024])
+def test_topk_matches_oracle(gpu, k):
+    import torch
+    rng = np.random.default_rng(k)
+    s = rng.integers(0, 60, size=5000).astype(np.int32)    # many ties
+    d = torch.from_numpy(s).cuda()
+    ts, ti = gpu.topk(d, k)
+    torch.cuda.synchronize()
+    ws, wi = oracle.topk(s, k)
+    assert (ts.cpu().numpy() == ws).all() and (ti.cpu().numpy() == wi).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 7])
+def test_topk_short_vectors(gpu, n):
+    import torch
+    s = np.arange(n, dtype=np.int32)[::-1].copy()
+    d = torch.from_numpy(s).cuda() if n else torch.zeros(1, dtype=torch.int32, device="cuda")
+    ts = torch.empty(10, dtype=torch.int32, device="cuda")
+    ti = torch.empty(10, dtype=torch.int64, device="cuda")
+    gpu.sw_topk(d, n, 10, ts, ti)
+    torch.cuda.synchronize()
+    ws, wi = oracle.topk(s, 10)
+    assert (ts.cpu().numpy() == ws).all() and (ti.cpu().numpy() == wi).all()
+
+
+def test_batch_matches_oracle(gpu, blosum):
+    import torch
+    qs, db = synth.workload1()
+    rng = np.random.default_rng(2)
+    queries = [qs[0], synth.small_query(1, 1), synth.small_query(2, 530), np.zeros(0, np.int8),
+               db.subject(17).copy(), synth.small_query(3, 64)]
+    D = gpu.Database(db.residues, db.offsets)
+    scores, ts, ti = D.search_batch(queries, blosum, 10, 2, k=10)
+    torch.cuda.synchronize()
+    S = scores.cpu().numpy()
+    for i, q in enumerate(queries):
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+        assert_equal_scores(S[i], want, f"batch query {i}")
+        ws, wi = oracle.topk(want, 10)
+        assert (ts[i].cpu().numpy() == ws).all() and (ti[i].cpu().numpy() == wi).all(), i
+    # top-k only (no score matrix kept)
+    _, ts2, ti2 = D.search_batch(queries, blosum, 10, 2, k=10, keep_scores=False)
+    torch.cuda.synchronize()
+    assert torch.equal(ts, ts2) and torch.equal(ti, ti2)
+    D.close()
+
+
+def test_invalid_residues_are_rejected(gpu, blosum):
+    qs, db = synth.workload1()
+    D = gpu.Database(db.residues, db.offsets)
+    bad = qs[0].copy()
+    bad[5] = 20
+    with pytest.raises(gpu.SwError) as e:
+        D.search(bad, blosum, 10, 2)
+    assert e.value.status == -2
+    with pytest.raises(gpu.SwError):
+        D.search(qs[0], blosum, -1, 2)
+    D.close()
+    res = db.residues.copy()
+    res[100] = 25
+    with pytest.raises(gpu.SwError) as e:
+        gpu.Database(res, db.offsets)
+    assert e.value.status == -2
+
+
+def test_full_size_workload2_sampled(gpu, blosum):
+    """570k-subject database: every score of the sample (every 1000th subject,
+    planted homologs, overflow sentinels, all subjects longer than 3,000) for the
+    shortest query and the sentinel query, in the launch configuration the
+    benchmark times."""
+    import torch
+    db = synth.sp570k()
+    qs = synth.workload2_queries()
+    idx = synth.parity_sample(db)
+    say(f"workload2 full size: n={db.n} sample={idx.size}")
+    D = gpu.Database(db.residues, db.offsets)
+    for k in (0, synth.WL2_QLENS.index(3735)):
+        out = D.search(qs[k], blosum, 10, 2)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()[idx]
+        want = oracle.scores(qs[k], db.residues, db.offsets, blosum, 10, 2, idx=idx)
+        assert_equal_scores(got, want, f"workload2 query {k}")
+        if k:
+            assert (want[np.isin(idx, db.sentinels)] > 32767).all()
+    D.close()
