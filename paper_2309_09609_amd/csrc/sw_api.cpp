@@ -113,8 +113,9 @@ struct sw_db {
     int64_t off_first = 0, off_last = 0;
     int ngroups = 0;
     std::vector<int32_t> ncols;       // per group
+    std::vector<int32_t> pcols;       // per pair: longest subject of the pair, rounded up to 4
     int32_t ncols_max = 0;
-    DevBuf image, groups, perm;
+    DevBuf image, groups, perm, pair_cols;
     int64_t image_bytes = 0;
     // launch geometry
     int cus = 0, wg16 = 0, wg32 = 0;   // persistent workgroups of the 16-bit and 32-bit sweeps
@@ -189,8 +190,8 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, std::vector<WgIt
                 lgB = db->force_lgB;
                 while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
             }
-            const int64_t c = unit_cost(m, nc, lgB);
             for (int k = 0; k < (1 << lgB); ++k) {
+                const int64_t c = unit_cost(m, db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))], lgB);
                 if (cur.count == kWaves || cur.lgB != lgB) {
                     flush();
                     cur.g0 = g;
@@ -293,6 +294,7 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_it
     a.image = db->image.as<uint8_t>();
     a.groups = db->groups.as<GroupRec>();
     a.perm = db->perm.as<int32_t>();
+    a.pair_cols = db->pair_cols.as<int32_t>();
     a.prof = db->prof.as<int16_t>();
     a.qd = S.qd;
     a.go = go;
@@ -434,7 +436,10 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         db->ncols_max = std::max(db->ncols_max, nc);
         base += (int64_t)nc * kGroupSubjects;
     }
+    db->pcols.assign((size_t)G * kGroupPairs, 0);
     for (int64_t i = 0; i < n; ++i) {
+        const size_t pi = (size_t)(i / 2);
+        db->pcols[pi] = std::max<int32_t>(db->pcols[pi], (int32_t)round_up(len[order[i]], kChunkCols));
         perm[i] = order[i];
         soff[i] = h_offsets[order[i]];
         slen[i] = len[order[i]];
@@ -446,6 +451,7 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         if ((e = db->image.reserve(std::max<int64_t>(base, 4))) != hipSuccess ||
             (e = db->groups.reserve(sizeof(GroupRec) * G)) != hipSuccess ||
             (e = db->perm.reserve(sizeof(int32_t) * perm.size())) != hipSuccess ||
+            (e = db->pair_cols.reserve(sizeof(int32_t) * db->pcols.size())) != hipSuccess ||
             (e = d_soff.reserve(sizeof(int64_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
             (e = d_slen.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
             (e = d_gdw.reserve(sizeof(int64_t) * G)) != hipSuccess || (e = d_err.reserve(4)) != hipSuccess) {
@@ -456,6 +462,7 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         auto step = [&](hipError_t x) { if (e == hipSuccess) e = x; };
         step(hipMemcpyAsync(db->groups.p, groups.data(), sizeof(GroupRec) * G, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(db->perm.p, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(db->pair_cols.p, db->pcols.data(), sizeof(int32_t) * db->pcols.size(), hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_soff.p, soff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_slen.p, slen.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_gdw.p, gdw.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
@@ -476,7 +483,7 @@ void sw_db_free(sw_db* db) {
     if (!db) return;
     DeviceGuard dg(db->device);
     hipDeviceSynchronize();
-    db->image.release(); db->groups.release(); db->perm.release();
+    db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
     db->counters.release(); db->rerun.release(); db->scores_tmp.release(); db->topk_dummy.release();
     db->hstage.release();

@@ -57,6 +57,7 @@ struct SweepArgs {
     const uint8_t* image;
     const GroupRec* groups;
     const int32_t* perm;          // sorted slot -> original subject index, -1 for padding slots
+    const int32_t* pair_cols;     // [group*64 + pair]: longest subject of the pair, rounded up to 4
     const int16_t* prof;
     const QDesc* qd;
     int32_t go, ge;

@@ -266,7 +266,12 @@ __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k
     const int rows_pp = R << lgB;
     const int passes = (Q.m + rows_pp - 1) / rows_pp;
     GroupRec G{0, 0, 0};
-    if (valid) G = a.groups[g];
+    int ncols = 0;
+    if (valid) {
+        G = a.groups[g];
+        // pairs are sorted by length within the group: the unit's first pair is its widest
+        ncols = a.pair_cols[g * kGroupPairs + k * P];
+    }
     const int pair = k * P + s;
     const uint8_t* resp = a.image + G.base + pair * 8;
     const int16_t* prof = a.prof + Q.prof_off;
@@ -287,9 +292,9 @@ __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k
         }
         if (valid) {
             if (lgB == 0)
-                sweep_pass<C, false>(resp, G.ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
             else
-                sweep_pass<C, true>(resp, G.ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
