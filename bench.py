@@ -144,6 +144,10 @@ def main():
     t1 = time.perf_counter()
     kt = D.kernel_times()           # ms per 16-bit sweep launch in the timed region
     st = D.stats()
+    if args.form == "plain" and kt.size == args.steps * len(queries):
+        per_q = kt.reshape(args.steps, len(queries)).mean(axis=0)
+        for m, ms in zip(qlens, per_q):
+            print(f"# m={m:5d}  sweep {ms:8.2f} ms  {m * total_res / ms / 1e6:7.0f} GCUPS", file=sys.stderr)
     elapsed = t1 - t0
     gcups = cells_step * args.steps / elapsed / 1e9
     kernel_s = float(kt.sum()) / 1e3

@@ -75,7 +75,10 @@ typedef struct {
                                  subjects is swept by this many cooperating lanes */
     int32_t rerun_threshold;  /* test hook: 0 = 32767; a smaller value sends every pair whose
                                  16-bit score reaches it to the exact 32-bit recompute */
-    int32_t reserved[5];
+    int32_t rows_per_lane;    /* tuning: 0 = planner decides; 4, 8 or 16 query rows per lane */
+    int32_t unit_share;       /* tuning: largest work unit as a fraction of one persistent wave's
+                                 share of a search, in 1/1000; 0 = default (250) */
+    int32_t reserved[3];
 } sw_pack_opts;
 
 /*
@@ -154,12 +157,14 @@ const char* sw_last_error(void);
 /*
  * Execution statistics of the most recent sw_search / sw_search_batch on the
  * handle (read after the stream has completed):
- *   out[0] = number of work items in the 16-bit sweep,
- *   out[1] = number of subject pairs recomputed with 32-bit cells,
- *   out[2] = rows per lane (R) used,  out[3] = persistent waves launched.
+ *   out[0] = work items of the bulk 16-bit launch,  out[1] = subject pairs
+ *   recomputed with 32-bit cells,  out[2] = rows per lane (R) of the bulk launch,
+ *   out[3] = persistent waves launched,  out[4] = work items of the side launch
+ *   (long pairs of a short query),  out[5] = rows per lane of the side launch,
+ *   out[6], out[7] = 0 (reserved).
  * This call synchronises the handle's device.
  */
-sw_status sw_last_stats(sw_db* db, int64_t out[4]);
+sw_status sw_last_stats(sw_db* db, int64_t out[8]);
 
 /*
  * Kernel timing for benchmarks.  When enabled, every search on the handle

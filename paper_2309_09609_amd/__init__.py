@@ -98,17 +98,19 @@ def _ptr(a) -> ctypes.c_void_p:
 # --------------------------------------------------------------------------- C-ABI mirrors
 class PackOpts(ctypes.Structure):
     _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
-                ("rerun_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("rerun_threshold", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
+                ("unit_share", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
-def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0) -> ctypes.c_void_p:
+def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
+               unit_share=0) -> ctypes.c_void_p:
     """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
-    ``force_lanes`` and ``rerun_threshold`` are test hooks (see sw_pack_opts)."""
+    ``force_lanes``, ``rerun_threshold`` and ``rows_per_lane`` are tuning/test hooks (see sw_pack_opts)."""
     lib = load()
     offs = _host_i64(h_offsets)
     n = offs.size - 1
     h = ctypes.c_void_p()
-    opts = PackOpts(0, int(force_lanes), int(rerun_threshold))
+    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share))
     _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
                           _stream(stream), ctypes.byref(h)))
     return h
@@ -146,7 +148,8 @@ def sw_search_batch(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, 
 class Database:
     """A packed, device-resident protein database."""
 
-    def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0):
+    def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
+                 rows_per_lane=0, unit_share=0):
         import torch
         self.offsets = _host_i64(offsets)
         self.n = self.offsets.size - 1
@@ -159,7 +162,8 @@ class Database:
         if d_res.numel() == 0:
             d_res = torch.zeros(1, dtype=torch.int8, device=device)
         self.device = d_res.device
-        self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold)
+        self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
+                                 unit_share)
         del d_res
 
     def close(self):
@@ -179,10 +183,10 @@ class Database:
         return {"n": n.value, "residues": r.value, "device_bytes": b.value}
 
     def stats(self):
-        out = np.zeros(4, dtype=np.int64)
+        out = np.zeros(8, dtype=np.int64)
         _check(load().sw_last_stats(self.handle, _ptr(out)))
         return {"items": int(out[0]), "rerun_pairs": int(out[1]), "rows_per_lane": int(out[2]),
-                "waves": int(out[3])}
+                "waves": int(out[3]), "side_items": int(out[4]), "side_rows_per_lane": int(out[5])}
 
     def profile_kernels(self, enable=True):
         """Record HIP events around every 16-bit sweep launch of this handle."""

@@ -25,8 +25,8 @@
 #include "sw_internal.h"
 
 namespace sw {
-hipError_t launch_sweep(bool i16, const SweepArgs& a, int grid, hipStream_t st);
-hipError_t sweep_occupancy(bool i16, int* blocks_per_cu);
+hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
@@ -97,9 +97,12 @@ struct HostPinned {
     }
 };
 
+// Work items of one search: the bulk at R_main rows per lane and, on a side
+// stream, the long pairs of short queries at a smaller R_side.
 struct Plan {
-    DevBuf items;
-    int32_t count = 0;
+    DevBuf items;                 // [main items..., side items...]
+    int32_t n_main = 0, n_side = 0;
+    int R_main = 16, R_side = 16;
 };
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -118,7 +121,10 @@ struct sw_db {
     DevBuf image, groups, perm, pair_cols;
     int64_t image_bytes = 0;
     // launch geometry
-    int cus = 0, wg16 = 0, wg32 = 0;   // persistent workgroups of the 16-bit and 32-bit sweeps
+    int cus = 0, wg16 = 0, wg32 = 0;   // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
+    int wgR[17] = {0};                // persistent workgroups per 16-bit instance, by R
+    hipStream_t side = nullptr;       // second stream for the long pairs of short queries
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t slot_cap = 0;             // (column x pair) capacity of one wave's boundary slot
     // workspace
     DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp, topk_dummy;
@@ -126,8 +132,10 @@ struct sw_db {
     int32_t rerun_cap = 0;
     std::map<std::pair<int, int>, Plan> plans;   // (qlen, 0) -> plan for a single query
     Plan batch_plan;
-    int last_items = 0, last_rows = kRows, last_grid = 0;
+    int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
     int force_lgB = -1;               // test hook: fixed lanes per pair
+    int force_R = 0;                  // test hook / tuning: fixed rows per lane (4, 8, 16)
+    double unit_share = 0.25;         // tuning: largest unit / one wave's share of a search
     bool timing = false;              // record events around each 16-bit sweep
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_used;         // indices into ev_pool, in launch order
@@ -137,7 +145,10 @@ struct sw_db {
 
 namespace {
 
-constexpr int kCounters = 4;   // [0] sweep counter, [1] rerun count, [2] rerun counter, [3] spare
+constexpr int kCounters = 4;   // [0] bulk sweep counter, [1] rerun count, [2] rerun counter, [3] side sweep counter
+constexpr int kRerunRows = 8;  // rows per lane of the 32-bit recompute
+constexpr int kMaxWgPerCu = 4; // persistent workgroups per CU (bounds the scratch slots)
+const int kRowChoices[3] = {4, 8, 16};
 constexpr int kRerunGrid = 64;
 
 struct DeviceGuard {
@@ -150,65 +161,107 @@ struct DeviceGuard {
 };
 
 // ------------------------------------------------------------------ planning
-struct Unit { int32_t g; int16_t k; int8_t lgB; int64_t cost; };
-
-int64_t unit_cost(int m, int ncols, int lgB) {
+int64_t unit_cost(int m, int ncols, int lgB, int R) {
     const int B = 1 << lgB;
-    const int64_t passes = (m + (kRows << lgB) - 1) / (kRows << lgB);
+    const int64_t passes = (m + (R << lgB) - 1) / (R << lgB);
     const int64_t steps = round_up(ncols + B - 1, 4);
-    const int64_t per_step = 10 * kRows + 16 + (lgB ? 6 : 0);
+    const int64_t per_step = 10 * R + 16 + (lgB ? 6 : 0);
     return passes * steps * per_step;
 }
 
-// Work items for queries qs (lengths) against all groups; appends to out.
-void plan_units(const sw_db* db, const std::vector<int>& qlens, std::vector<WgItem>& out) {
-    const int64_t nwaves = (int64_t)db->wg16 * kWaves;
+// Work items for queries of lengths qlens (query index = position) against all
+// groups.  Every group gets the smallest lanes-per-pair B whose units cost at
+// most a set fraction of a persistent wave's share of the work (0.25 by
+// default: smaller units force wide lane cooperation whose pass height exceeds
+// short queries, larger ones lengthen the longest-first tail) and whose boundary row
+// fits a scratch slot.  Units still above that share at B = 64 are pairs that
+// a single wave sweeps column by column; when a smaller R makes them cheaper
+// (short queries: most of a 64 x 16-row pass would be padding) they go to the
+// side list.  Items are ordered longest first.
+void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
+                std::vector<WgItem>& side_out) {
+    int R_main = 16;
+    {
+        int64_t best = -1;
+        for (int R : {8, 16}) {
+            int64_t t = 0;
+            for (int m : qlens)
+                if (m > 0)
+                    for (int g = 0; g < db->ngroups; ++g) t += unit_cost(m, db->ncols[g], 0, R);
+            if (best < 0 || t < best) { best = t; R_main = R; }
+        }
+    }
+    if (db->force_R) R_main = db->force_R;
+    const int64_t nwaves = (int64_t)db->wgR[R_main] * kWaves;
     int64_t total = 0;
     for (int m : qlens)
-        for (int g = 0; g < db->ngroups; ++g) total += unit_cost(m, db->ncols[g], 0);
-    const double cap = 0.5 * (double)total / (double)std::max<int64_t>(nwaves, 1);
+        if (m > 0)
+            for (int g = 0; g < db->ngroups; ++g) total += unit_cost(m, db->ncols[g], 0, R_main);
+    const double cap = db->unit_share * (double)total / (double)std::max<int64_t>(nwaves, 1);
+    int R_side = R_main;
     struct Tmp { WgItem it; int64_t cost; };
-    std::vector<Tmp> items;
+    std::vector<Tmp> items, sitems;
     for (size_t qi = 0; qi < qlens.size(); ++qi) {
         const int m = qlens[qi];
         if (m <= 0) continue;
-        WgItem cur{0, (int32_t)qi, 0, -1, 0, 0};
-        int64_t cur_cost = 0;
-        auto flush = [&]() {
-            if (cur.count > 0) items.push_back({cur, cur_cost});
-            cur.count = 0;
-            cur_cost = 0;
+        // a short query's long pairs: the R that makes a 64-lane unit cheapest
+        // (single-query plans only: a batch has enough work to hide them)
+        int r_long = R_main;
+        if (qlens.size() == 1)
+            for (int R : kRowChoices)
+            if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
+        WgItem cur{0, (int32_t)qi, 0, -1, 0, 0}, scur{0, (int32_t)qi, 0, -1, 0, 0};
+        int64_t cur_cost = 0, scur_cost = 0;
+        auto flush = [](std::vector<Tmp>& v, WgItem& c, int64_t& cc) {
+            if (c.count > 0) v.push_back({c, cc});
+            c.count = 0;
+            cc = 0;
+        };
+        auto add = [&](std::vector<Tmp>& v, WgItem& c, int64_t& cc, int g, int k, int lgB, int64_t cost) {
+            const bool contiguous = c.count > 0 && c.lgB == lgB &&
+                                    ((int64_t)c.g0 << lgB) + c.k0 + c.count == ((int64_t)g << lgB) + k;
+            if (c.count == kWaves || !contiguous) {
+                flush(v, c, cc);
+                c.g0 = g;
+                c.k0 = (int16_t)k;
+                c.lgB = (int8_t)lgB;
+            }
+            c.count++;
+            cc = std::max(cc, cost);
         };
         for (int g = 0; g < db->ngroups; ++g) {
             const int nc = db->ncols[g];
             int lgB = 0;
             for (; lgB < 6; ++lgB) {
                 const int64_t P = kGroupPairs >> lgB;
-                if ((double)unit_cost(m, nc, lgB) <= cap && (int64_t)nc * P <= db->slot_cap) break;
+                if ((double)unit_cost(m, nc, lgB, R_main) <= cap && (int64_t)nc * P <= db->slot_cap) break;
             }
             if (db->force_lgB >= 0) {
                 lgB = db->force_lgB;
                 while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
             }
             for (int k = 0; k < (1 << lgB); ++k) {
-                const int64_t c = unit_cost(m, db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))], lgB);
-                if (cur.count == kWaves || cur.lgB != lgB) {
-                    flush();
-                    cur.g0 = g;
-                    cur.k0 = (int16_t)k;
-                    cur.lgB = (int8_t)lgB;
+                const int uc = db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))];
+                const int64_t c = unit_cost(m, uc, lgB, R_main);
+                if (lgB == 6 && db->force_lgB < 0 && r_long != R_main && (double)c > cap &&
+                    unit_cost(m, uc, 6, r_long) < c) {
+                    add(sitems, scur, scur_cost, g, k, 6, unit_cost(m, uc, 6, r_long));
+                    R_side = r_long;
+                } else {
+                    add(items, cur, cur_cost, g, k, lgB, c);
                 }
-                cur.count++;
-                cur_cost = std::max(cur_cost, c);
             }
         }
-        flush();
+        flush(items, cur, cur_cost);
+        flush(sitems, scur, scur_cost);
     }
-    std::stable_sort(items.begin(), items.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
-    for (auto& t : items) {
-        t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX);
-        out.push_back(t.it);
-    }
+    auto by_cost = [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; };
+    std::stable_sort(items.begin(), items.end(), by_cost);
+    std::stable_sort(sitems.begin(), sitems.end(), by_cost);
+    for (auto& t : items) { t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX); main_out.push_back(t.it); }
+    for (auto& t : sitems) { t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX); side_out.push_back(t.it); }
+    plan->R_main = R_main;
+    plan->R_side = R_side;
 }
 
 sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
@@ -222,11 +275,17 @@ sw_status ensure_workspace(sw_db* db) {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, db->device));
         db->cus = prop.multiProcessorCount;
-        int b16 = 0, b32 = 0;
-        HIP_TRY(sweep_occupancy(true, &b16));
-        HIP_TRY(sweep_occupancy(false, &b32));
-        if (b16 < 1 || b32 < 1) return fail(SW_E_HIP, "sweep kernel cannot be resident (occupancy %d/%d)", b16, b32);
-        db->wg16 = db->cus * b16;
+        int b32 = 0;
+        db->wg16 = 0;
+        for (int R : kRowChoices) {
+            int b = 0;
+            HIP_TRY(sweep_occupancy(true, R, &b));
+            if (b < 1) return fail(SW_E_HIP, "16-bit sweep (R=%d) cannot be resident", R);
+            db->wgR[R] = db->cus * std::min(b, kMaxWgPerCu);
+            db->wg16 = std::max(db->wg16, db->wgR[R]);
+        }
+        HIP_TRY(sweep_occupancy(false, kRerunRows, &b32));
+        if (b32 < 1) return fail(SW_E_HIP, "32-bit sweep cannot be resident");
         db->wg32 = kRerunGrid;
         db->slot_cap = std::max<int64_t>(65536, db->ncols_max);
         const int64_t nw16 = (int64_t)db->wg16 * kWaves;
@@ -234,6 +293,9 @@ sw_status ensure_workspace(sw_db* db) {
         HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4));
         HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4));
         HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t)));
+        HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
     }
     return SW_OK;
 }
@@ -282,14 +344,15 @@ sw_status stage_queries(sw_db* db, const int8_t* h_queries, const int64_t* h_qof
     return SW_OK;
 }
 
-sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_items, int32_t go, int32_t ge,
-                     int32_t* d_scores, int64_t rerun_cap, hipStream_t st) {
+sw_status run_sweeps(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int32_t ge, int32_t* d_scores,
+                     int64_t rerun_cap, hipStream_t st) {
     HIP_TRY(db->rerun.reserve((size_t)rerun_cap * sizeof(WgItem)));
     int32_t* ctr = db->counters.as<int32_t>();
+    const WgItem* d_items = plan.items.as<WgItem>();
     SweepArgs a{};
     a.items = d_items;
     a.n_items_dev = nullptr;
-    a.n_items = n_items;
+    a.n_items = plan.n_main;
     a.counter = ctr + 0;
     a.image = db->image.as<uint8_t>();
     a.groups = db->groups.as<GroupRec>();
@@ -301,13 +364,28 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_it
     a.ge = ge;
     a.scratch = db->scratch16.as<uint32_t>();
     a.slot_words = db->slot_cap * 2;
+    a.slot_base = 0;
     a.scores = d_scores;
     a.rerun = db->rerun.as<WgItem>();
     a.rerun_count = ctr + 1;
     a.rerun_cap = (int32_t)rerun_cap;
     a.unit_list = 0;
     a.sat = db->sat;
-    const int grid16 = std::max(1, std::min(db->wg16, n_items));
+    // the side launch takes the first slots; the bulk launch fills the rest of the GPU
+    const int wg_main = db->wgR[plan.R_main];
+    const int grid_side = std::min(plan.n_side, std::max(1, wg_main / 8));
+    const int grid_main = std::max(1, std::min(wg_main - grid_side, std::max(plan.n_main, 1)));
+    if (plan.n_side > 0) {
+        SweepArgs b = a;
+        b.items = d_items + plan.n_main;
+        b.n_items = plan.n_side;
+        b.counter = ctr + 3;
+        b.slot_base = grid_main;
+        HIP_TRY(hipEventRecord(db->ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(db->side, db->ev_fork, 0));
+        HIP_TRY(launch_sweep(true, plan.R_side, b, grid_side, db->side));
+        HIP_TRY(hipEventRecord(db->ev_join, db->side));
+    }
     int ev = -1;
     if (db->timing) {
         if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
@@ -320,7 +398,8 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_it
         }
         HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
     }
-    HIP_TRY(launch_sweep(true, a, grid16, st));
+    if (plan.n_main > 0) HIP_TRY(launch_sweep(true, plan.R_main, a, grid_main, st));
+    if (plan.n_side > 0) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
         db->ev_used.push_back(ev);
@@ -333,13 +412,28 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const WgItem* d_items, int n_it
     r.counter = ctr + 2;
     r.scratch = db->scratch32.as<uint32_t>();
     r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
+    r.slot_base = 0;
     r.rerun = nullptr;
     r.rerun_count = nullptr;
     r.rerun_cap = 0;
     r.unit_list = 1;
-    HIP_TRY(launch_sweep(false, r, db->wg32, st));
-    db->last_items = n_items;
-    db->last_grid = grid16;
+    HIP_TRY(launch_sweep(false, kRerunRows, r, db->wg32, st));
+    db->last_items = plan.n_main;
+    db->last_rows = plan.R_main;
+    db->last_side_items = plan.n_side;
+    db->last_side_rows = plan.n_side ? plan.R_side : 0;
+    db->last_grid = grid_main + (plan.n_side > 0 ? grid_side : 0);
+    return SW_OK;
+}
+
+sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p) {
+    std::vector<WgItem> mi, si;
+    plan_units(db, qlens, p, mi, si);
+    p->n_main = (int32_t)mi.size();
+    p->n_side = (int32_t)si.size();
+    mi.insert(mi.end(), si.begin(), si.end());
+    HIP_TRY(p->items.reserve(std::max<size_t>(mi.size(), 1) * sizeof(WgItem)));
+    if (!mi.empty()) HIP_TRY(hipMemcpy(p->items.p, mi.data(), mi.size() * sizeof(WgItem), hipMemcpyHostToDevice));
     return SW_OK;
 }
 
@@ -351,12 +445,9 @@ sw_status get_plan(sw_db* db, int m, Plan** out) {
         for (auto& kv : db->plans) kv.second.items.release();
         db->plans.clear();
     }
-    std::vector<WgItem> items;
-    plan_units(db, std::vector<int>{m}, items);
     Plan& p = db->plans[key];
-    p.count = (int32_t)items.size();
-    HIP_TRY(p.items.reserve(std::max<size_t>(items.size(), 1) * sizeof(WgItem)));
-    HIP_TRY(hipMemcpy(p.items.p, items.data(), items.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+    sw_status s = build_plan(db, std::vector<int>{m}, &p);
+    if (s != SW_OK) { p.items.release(); db->plans.erase(key); return s; }
     *out = &p;
     return SW_OK;
 }
@@ -409,6 +500,11 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
             db->force_lgB = __builtin_ctz(fl);
         }
         if (opts->rerun_threshold < 0) return bail(fail(SW_E_INVALID, "rerun_threshold must be >= 0"));
+        const int rpl = opts->rows_per_lane;
+        if (rpl != 0 && rpl != 4 && rpl != 8 && rpl != 16) return bail(fail(SW_E_INVALID, "rows_per_lane must be 0, 4, 8 or 16"));
+        db->force_R = rpl;
+        if (opts->unit_share < 0 || opts->unit_share > 100000) return bail(fail(SW_E_INVALID, "unit_share must be in 0..100000"));
+        if (opts->unit_share > 0) db->unit_share = opts->unit_share / 1000.0;
         if (opts->rerun_threshold > 0) db->sat = std::min<int32_t>(opts->rerun_threshold, kSat16);
     }
     db->n = n;
@@ -490,6 +586,9 @@ void sw_db_free(sw_db* db) {
     for (auto& kv : db->plans) kv.second.items.release();
     db->batch_plan.items.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    if (db->side) hipStreamDestroy(db->side);
+    if (db->ev_fork) hipEventDestroy(db->ev_fork);
+    if (db->ev_join) hipEventDestroy(db->ev_join);
     delete db;
 }
 
@@ -536,7 +635,7 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
     Staged S;
     if ((s = stage_queries(db, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
     const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
-    return run_sweeps(db, S, plan->items.as<WgItem>(), plan->count, gap_open, gap_extend, d_scores_out, rerun_cap, st);
+    return run_sweeps(db, S, *plan, gap_open, gap_extend, d_scores_out, rerun_cap, st);
 }
 
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
@@ -585,20 +684,15 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
         // zero-length queries score 0 everywhere
         for (int q = 0; q < nq; ++q)
             if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
-        std::vector<WgItem> items;
-        plan_units(db, qlens, items);
-        HIP_TRY(db->batch_plan.items.reserve(std::max<size_t>(items.size(), 1) * sizeof(WgItem)));
-        HIP_TRY(hipMemcpyAsync(db->batch_plan.items.p, items.data(), items.size() * sizeof(WgItem),
-                               hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));   // host vector goes out of scope
-        db->batch_plan.count = (int32_t)items.size();
+        // a synchronous copy of the plan: the batch plan buffer is reused by the next call
+        HIP_TRY(hipStreamSynchronize(st));
+        sw_status ps = build_plan(db, qlens, &db->batch_plan);
+        if (ps != SW_OK) return ps;
         Staged S;
         if ((s = stage_queries(db, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
         const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
-        if (!items.empty())
-            if ((s = run_sweeps(db, S, db->batch_plan.items.as<WgItem>(), (int)items.size(), gap_open, gap_extend,
-                                scores, rerun_cap, st)) != SW_OK)
-                return s;
+        if (db->batch_plan.n_main + db->batch_plan.n_side > 0)
+            if ((s = run_sweeps(db, S, db->batch_plan, gap_open, gap_extend, scores, rerun_cap, st)) != SW_OK) return s;
     }
     if (k > 0) HIP_TRY(launch_topk(scores, n, n, nq, k, d_top_scores, d_top_index, st));
     return SW_OK;
@@ -627,7 +721,7 @@ sw_status sw_kernel_times(sw_db* db, float* ms_out, int32_t cap, int32_t* count)
     return SW_OK;
 }
 
-sw_status sw_last_stats(sw_db* db, int64_t out[4]) {
+sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
     if (!db || !out) return fail(SW_E_INVALID, "NULL argument");
     DeviceGuard dg(db->device);
     int32_t c[kCounters] = {0, 0, 0, 0};
@@ -639,6 +733,10 @@ sw_status sw_last_stats(sw_db* db, int64_t out[4]) {
     out[1] = c[1];
     out[2] = db->last_rows;
     out[3] = (int64_t)db->last_grid * kWaves;
+    out[4] = db->last_side_items;
+    out[5] = db->last_side_rows;
+    out[6] = 0;
+    out[7] = 0;
     return SW_OK;
 }
 

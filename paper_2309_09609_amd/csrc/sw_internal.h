@@ -14,7 +14,7 @@ constexpr int kGroupSubjects = 2 * kGroupPairs;
 constexpr int kChunkCols = 4;      // columns per interleaved chunk (one dword per subject)
 constexpr int kChunkBytes = kGroupPairs * 8;   // one chunk row of a group: 64 pairs x 2 subjects x 4 residues
 constexpr int kWaves = 4;          // waves per workgroup of the sweep kernel
-constexpr int kRows = 16;          // query rows per lane (R) of the sweep kernels
+constexpr int kRowsMax = 16;       // most query rows per lane (R) of any sweep instance
 constexpr int kSliceRows = 1024;   // largest rows-per-pass (B*R) kept in LDS: 64 lanes x 16 rows
 constexpr int kProfRowAlign = 1024;    // profile row stride is a multiple of this (covers every B*R)
 constexpr int16_t kSat16 = 32767;  // 16-bit saturation value: a score equal to it is recomputed in 32 bits
@@ -63,6 +63,7 @@ struct SweepArgs {
     int32_t go, ge;
     uint32_t* scratch;            // per-wave boundary-row slots
     int64_t slot_words;           // uint32 words per wave slot
+    int32_t slot_base;            // first workgroup slot of this launch (launches share the scratch)
     int32_t* scores;
     WgItem* rerun;                // 16-bit sweep: pairs that saturated are appended here
     int32_t* rerun_count;

@@ -29,6 +29,8 @@
 // the pair to the 32-bit sweep.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sw_internal.h"
 
 namespace sw {
@@ -121,12 +123,11 @@ __device__ __forceinline__ uint2 load_chunk(const uint8_t* resp, int c, int nchu
 // wave's pairs.  `lrow` points at this lane's profile rows in LDS, laid out
 // [residue][R] (int16).  State lives in registers; only the boundary row
 // between passes touches memory.
-template <class C, bool COOP>
+template <class C, int R, bool COOP>
 __device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int lgB, int b, int s, int p,
                                            int passes, const int16_t* lrow, uint32_t* slot,
                                            typename C::G go, typename C::G ge, typename C::T& S) {
     using T = typename C::T;
-    constexpr int R = kRows;
     const int B = 1 << lgB;
     const int P = kGroupPairs >> lgB;
     const int nchunks = ncols >> 2;
@@ -183,14 +184,22 @@ __device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int l
             const int t = 4 * c + u;
             const int da = (ra >> (8 * u)) & 0xff;
             const int db = (rb >> (8 * u)) & 0xff;
-            const uint4* qa = reinterpret_cast<const uint4*>(lrow + da * R);
-            const uint4* qb = reinterpret_cast<const uint4*>(lrow + db * R);
             uint32_t pa[R / 2], pb[R / 2];
+            if constexpr (R % 8 == 0) {
+                const uint4* qa = reinterpret_cast<const uint4*>(lrow + da * R);
+                const uint4* qb = reinterpret_cast<const uint4*>(lrow + db * R);
 #pragma unroll
-            for (int v = 0; v < R / 8; ++v) {
-                uint4 x = qa[v], y = qb[v];
-                pa[4 * v] = x.x; pa[4 * v + 1] = x.y; pa[4 * v + 2] = x.z; pa[4 * v + 3] = x.w;
-                pb[4 * v] = y.x; pb[4 * v + 1] = y.y; pb[4 * v + 2] = y.z; pb[4 * v + 3] = y.w;
+                for (int v = 0; v < R / 8; ++v) {
+                    uint4 x = qa[v], y = qb[v];
+                    pa[4 * v] = x.x; pa[4 * v + 1] = x.y; pa[4 * v + 2] = x.z; pa[4 * v + 3] = x.w;
+                    pb[4 * v] = y.x; pb[4 * v + 1] = y.y; pb[4 * v + 2] = y.z; pb[4 * v + 3] = y.w;
+                }
+            } else {
+                static_assert(R == 4, "rows per lane must be 4 or a multiple of 8");
+                const uint2 x = *reinterpret_cast<const uint2*>(lrow + da * R);
+                const uint2 y = *reinterpret_cast<const uint2*>(lrow + db * R);
+                pa[0] = x.x; pa[1] = x.y;
+                pb[0] = y.x; pb[1] = y.y;
             }
             T htop, ftop;
             if (COOP) {
@@ -235,29 +244,31 @@ __device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int l
     }
 }
 
-// Load rows [row0, row0 + B*R) of a query profile into LDS as [b][residue][R].
+// Load rows [row0, row0 + B*R) of a query profile into LDS as [b][residue][R],
+// in 16-byte units (8-byte units when R = 4).
+template <int R>
 __device__ __forceinline__ void load_slice(int16_t* dst, const int16_t* prof, int mp, int row0, int lgB,
                                            int tid, int nthreads) {
-    constexpr int R = kRows;
+    constexpr int U = (R % 8 == 0) ? 8 : 4;            // int16 elements per copy unit
+    using V = typename std::conditional<U == 8, uint4, uint2>::type;
     const int rows = R << lgB;
-    const int per_res = rows >> 3;                     // uint4 units per residue row
+    const int per_res = rows / U;                      // units per residue row
     const int total = kNRes * per_res;
     for (int e = tid; e < total; e += nthreads) {
         const int d = e / per_res;
-        const int rem = e - d * per_res;               // = b * (R/8) + r8
-        const int bb = rem / (R / 8);
-        const int r8 = rem - bb * (R / 8);
-        const uint4 v = *reinterpret_cast<const uint4*>(prof + (int64_t)d * mp + row0 + rem * 8);
-        *reinterpret_cast<uint4*>(dst + (bb * kNRes + d) * R + r8 * 8) = v;
+        const int rem = e - d * per_res;               // = b * (R/U) + ru
+        const int bb = rem / (R / U);
+        const int ru = rem - bb * (R / U);
+        const V v = *reinterpret_cast<const V*>(prof + (int64_t)d * mp + row0 + rem * U);
+        *reinterpret_cast<V*>(dst + (bb * kNRes + d) * R + ru * U) = v;
     }
 }
 
-template <class C>
+template <class C, int R>
 __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k, int lgB, int q, bool valid,
                                                 bool shared_slice, int16_t* lds, int wave, int lane,
                                                 uint32_t* slot) {
     using T = typename C::T;
-    constexpr int R = kRows;
     const int B = 1 << lgB;
     const int P = kGroupPairs >> lgB;
     const int s = lane >> lgB;
@@ -275,26 +286,26 @@ __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k
     const int pair = k * P + s;
     const uint8_t* resp = a.image + G.base + pair * 8;
     const int16_t* prof = a.prof + Q.prof_off;
-    int16_t* region = shared_slice ? lds : lds + wave * (kNRes * (kSliceRows / kWaves));
+    int16_t* region = shared_slice ? lds : lds + wave * (kNRes * 16 * R);
     const int16_t* lrow = region + b * kNRes * R;
     const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
     T S = C::zero();
     for (int p = 0; p < passes; ++p) {
         if (shared_slice) {
             __syncthreads();
-            load_slice(region, prof, Q.mp, p * rows_pp, lgB, threadIdx.x, blockDim.x);
+            load_slice<R>(region, prof, Q.mp, p * rows_pp, lgB, threadIdx.x, blockDim.x);
             __syncthreads();
         } else {
             __builtin_amdgcn_wave_barrier();
-            load_slice(region, prof, Q.mp, p * rows_pp, lgB, lane, 64);
+            load_slice<R>(region, prof, Q.mp, p * rows_pp, lgB, lane, 64);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
         if (valid) {
             if (lgB == 0)
-                sweep_pass<C, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, R, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
             else
-                sweep_pass<C, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, R, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
@@ -313,13 +324,14 @@ __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k
     }
 }
 
-template <class C>
+template <class C, int R>
 __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
-    __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * kSliceRows];
+    // one shared slice of up to 64*R rows, or four per-wave slices of up to 16*R rows
+    __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
     __shared__ int s_item;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    uint32_t* slot = a.scratch + ((int64_t)blockIdx.x * kWaves + wave) * a.slot_words;
+    uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
     int n_items = a.n_items;
     if (a.n_items_dev) {
         const int c = min(*a.n_items_dev, a.n_items);
@@ -334,15 +346,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
         if (a.unit_list) {
             // one unit per workgroup, computed by wave 0 with the whole LDS slice
             const WgItem I = a.items[it];
-            run_unit_passes<C>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
+            run_unit_passes<C, R>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
         } else {
             const WgItem I = a.items[it];
             const int B = 1 << I.lgB;
             int k = I.k0 + wave;
             const int g = I.g0 + (k >> I.lgB);
             k &= B - 1;
-            const bool shared_slice = (kRows << I.lgB) > kSliceRows / kWaves;
-            run_unit_passes<C>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
+            const bool shared_slice = I.lgB > 4;        // more than 16 lanes per pair
+            run_unit_passes<C, R>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
         }
     }
 }
@@ -524,17 +536,30 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 }
 
 // ------------------------------------------------------------ host-side launchers
-hipError_t launch_sweep(bool i16, const SweepArgs& a, int grid, hipStream_t st) {
-    if (i16)
-        hipLaunchKernelGGL(k_sweep<CellI16>, dim3(grid), dim3(64 * kWaves), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_sweep<CellI32>, dim3(grid), dim3(64 * kWaves), 0, st, a);
-    return hipGetLastError();
+// Kernel instances: 16-bit cells with R = 4, 8, 16 rows per lane; 32-bit cells with R = 8.
+static const void* sweep_kernel(bool i16, int R) {
+    if (i16) {
+        if (R == 4) return (const void*)k_sweep<CellI16, 4>;
+        if (R == 8) return (const void*)k_sweep<CellI16, 8>;
+        if (R == 16) return (const void*)k_sweep<CellI16, 16>;
+        return nullptr;
+    }
+    if (R == 8) return (const void*)k_sweep<CellI32, 8>;
+    return nullptr;
 }
 
-hipError_t sweep_occupancy(bool i16, int* blocks_per_cu) {
-    return i16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep<CellI16>, 64 * kWaves, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep<CellI32>, 64 * kWaves, 0);
+hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = sweep_kernel(i16, R);
+    if (!k) return hipErrorInvalidValue;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {
+    const void* k = sweep_kernel(i16, R);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
 }
 
 hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,

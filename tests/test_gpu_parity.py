@@ -62,6 +62,38 @@ def test_every_lane_degree(gpu, blosum, lanes, m):
     assert_equal_scores(got, want, f"lanes={lanes} m={m}")
 
 
+@pytest.mark.parametrize("rows", [4, 8, 16])
+@pytest.mark.parametrize("lanes", [0, 1, 4, 16, 64])
+@pytest.mark.parametrize("m", [1, 37, 300])
+def test_every_rows_per_lane(gpu, blosum, rows, lanes, m):
+    db = synth.small_db(seed=71 + m, n=260, lo=0, hi=600)
+    q = synth.small_query(seed=7 * m, m=m)
+    say(f"rows={rows} lanes={lanes} m={m}")
+    got, st = gpu_scores(gpu, db, q, blosum, 10, 2, force_lanes=lanes, rows_per_lane=rows)
+    assert st["rows_per_lane"] == rows
+    want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(got, want, f"rows={rows} lanes={lanes} m={m}")
+
+
+@pytest.mark.parametrize("m", [20, 144, 700])
+def test_short_query_long_subjects_side_stream(gpu, blosum, m):
+    """A large database whose few longest subjects go to the small-R launch on
+    the side stream when the query is short."""
+    rng = np.random.default_rng(m)
+    base = synth.small_db(seed=m, n=6000, lo=20, hi=900, median=300)
+    lens = list(base.lengths) + [35000, 30000, 12000, 9000, 6000]
+    subs = [base.subject(k) for k in range(base.n)] + [synth.background_residues(rng, L) for L in lens[base.n:]]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    q = synth.small_query(seed=m + 5, m=m)
+    got, st = gpu_scores(gpu, db, q, blosum, 10, 2)
+    want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(got, want, f"side stream m={m}")
+    if m <= 144:
+        assert st["side_items"] > 0 and st["side_rows_per_lane"] < 16, st
+
+
 @pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 257])
 def test_ragged_database_sizes(gpu, blosum, n):
     db = synth.small_db(seed=n, n=n, lo=0, hi=90)
