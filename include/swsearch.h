@@ -97,6 +97,14 @@ typedef struct {
 sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t n,
                      const sw_pack_opts* opts, sw_stream stream, sw_db** out);
 
+/*
+ * sw_db_tune - change the tuning knobs of a packed database (the force_lanes,
+ * rerun_threshold, rows_per_lane and unit_share fields of opts; max_qlen is
+ * ignored).  Synchronises the handle's device and drops cached plans and graphs.
+ * Results are bit-identical for every setting; only speed changes.
+ */
+sw_status sw_db_tune(sw_db* db, const sw_pack_opts* opts);
+
 /* Releases the handle and its device memory (after synchronising its device). */
 void sw_db_free(sw_db* db);
 

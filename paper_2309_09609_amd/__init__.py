@@ -25,7 +25,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
           -5: "SW_E_UNSUPPORTED", -6: "SW_E_SIZE"}
 
 # Every entry point declared in include/swsearch.h.
-EXPORTS = ("sw_db_pack", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
+EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -48,6 +48,8 @@ def load():
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.sw_db_pack.restype = I32
     lib.sw_db_pack.argtypes = [P, P, I64, P, P, ctypes.POINTER(P)]
+    lib.sw_db_tune.restype = I32
+    lib.sw_db_tune.argtypes = [P, P]
     lib.sw_db_free.restype = None
     lib.sw_db_free.argtypes = [P]
     lib.sw_db_info.restype = I32
@@ -187,6 +189,11 @@ class Database:
         _check(load().sw_last_stats(self.handle, _ptr(out)))
         return {"items": int(out[0]), "rerun_pairs": int(out[1]), "rows_per_lane": int(out[2]),
                 "waves": int(out[3]), "side_items": int(out[4]), "side_rows_per_lane": int(out[5])}
+
+    def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0):
+        """Change the handle's tuning knobs (results are identical for every setting)."""
+        opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share))
+        _check(load().sw_db_tune(self.handle, ctypes.byref(opts)))
 
     def profile_kernels(self, enable=True):
         """Record HIP events around every 16-bit sweep launch of this handle."""

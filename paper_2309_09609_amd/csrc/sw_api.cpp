@@ -3,12 +3,16 @@
 // sw_db_pack sorts subjects by length (descending, ties by index), cuts the
 // sorted list into groups of 128 and interleaves each group so that one wave
 // reads 4 columns of 128 subjects as 512 contiguous bytes (one dwordx2 per lane).
-// sw_search plans the work per query: every group gets a lane-cooperation
-// degree B (1 = one pair of subjects per lane, 64 = a whole wave on one pair)
-// so that no work unit is large against a persistent wave's share of the query,
-// units are bundled four to a workgroup and ordered longest first, and one
-// persistent launch pulls them from an atomic counter.  Pairs whose 16-bit
-// score saturates are appended to a list that a second, 32-bit launch consumes.
+//
+// A search is planned on the host: every group gets a lane-cooperation degree
+// B (1 = one pair of subjects per lane, 64 = a whole wave on one pair) so that
+// no work unit is large against a persistent wave's share of the search, units
+// are bundled four to a workgroup and ordered longest first, and one persistent
+// launch pulls them from an atomic counter.  The long pairs of a short query
+// run on a second stream with fewer rows per lane.  Pairs whose 16-bit score
+// saturates are appended to a list that a 32-bit launch consumes.  The launch
+// sequence itself allocates nothing, so the batched form captures it once per
+// batch shape as a HIP graph and replays it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,26 +63,29 @@ sw_status fail(sw_status s, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(SW_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
 
-// Device buffer that grows on demand (contents are not preserved).
+// Device buffer that grows on demand (contents are not preserved).  Every
+// reallocation bumps *gen, which invalidates captured graphs.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
-    hipError_t reserve(size_t want) {
+    hipError_t reserve(size_t want, uint64_t* gen = nullptr) {
         if (want <= bytes && p) return hipSuccess;
         if (p) { hipFree(p); p = nullptr; bytes = 0; }
         const size_t sz = std::max<size_t>(want, 256);
         hipError_t e = hipMalloc(&p, sz);
         if (e == hipSuccess) bytes = sz;
+        if (gen) ++*gen;
         return e;
     }
     void release() { if (p) hipFree(p); p = nullptr; bytes = 0; }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned staging buffer; the event marks completion of the last copy out of it.
 struct HostPinned {
     void* p = nullptr;
     size_t bytes = 0;
-    hipEvent_t done = nullptr;   // completion of the last copy that read this buffer
+    hipEvent_t done = nullptr;
     bool pending = false;
     hipError_t reserve(size_t want) {
         if (pending) { hipEventSynchronize(done); pending = false; }
@@ -98,11 +105,39 @@ struct HostPinned {
 };
 
 // Work items of one search: the bulk at R_main rows per lane and, on a side
-// stream, the long pairs of short queries at a smaller R_side.
+// stream, the long pairs of a short query at a smaller R_side.
 struct Plan {
     DevBuf items;                 // [main items..., side items...]
     int32_t n_main = 0, n_side = 0;
     int R_main = 16, R_side = 16;
+};
+
+// Device pointers of the staged queries (descriptors, offsets, matrix + residues).
+struct Staged {
+    const QDesc* qd = nullptr;
+    const int64_t* qoff = nullptr;
+    const int8_t* sm_q = nullptr;
+    int nq = 0;
+    int max_mp = 0;
+};
+
+struct GraphEntry {
+    std::vector<int> qlens;
+    int32_t go = 0, ge = 0, k = 0;
+    const void* scores = nullptr;
+    const void* top_s = nullptr;
+    const void* top_i = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void clear() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        qlens.clear();
+    }
 };
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -121,35 +156,40 @@ struct sw_db {
     DevBuf image, groups, perm, pair_cols;
     int64_t image_bytes = 0;
     // launch geometry
-    int cus = 0, wg16 = 0, wg32 = 0;   // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
+    int cus = 0, wg16 = 0, wg32 = 0;  // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
     int wgR[17] = {0};                // persistent workgroups per 16-bit instance, by R
-    hipStream_t side = nullptr;       // second stream for the long pairs of short queries
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t slot_cap = 0;             // (column x pair) capacity of one wave's boundary slot
+    hipStream_t side = nullptr;       // second stream for the long pairs of short queries
+    hipStream_t cap = nullptr;        // stream the batched sequence is captured on
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // workspace
-    DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp, topk_dummy;
+    uint64_t gen = 1;                 // bumped on every workspace reallocation
+    DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp;
     HostPinned hstage;
-    int32_t rerun_cap = 0;
-    std::map<std::pair<int, int>, Plan> plans;   // (qlen, 0) -> plan for a single query
+    std::map<int, Plan> plans;        // plain searches: query length -> plan
     Plan batch_plan;
+    std::vector<int> batch_qlens;
+    GraphEntry graph;                 // batched form: last captured shape
+    // tuning knobs and test hooks
+    int force_lgB = -1;               // fixed lanes per pair
+    int force_R = 0;                  // fixed rows per lane (4, 8, 16)
+    double unit_share = 0.25;         // largest unit / one wave's share of a search
+    int32_t sat = kSat16;             // rerun threshold
+    // statistics and timing
     int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
-    int force_lgB = -1;               // test hook: fixed lanes per pair
-    int force_R = 0;                  // test hook / tuning: fixed rows per lane (4, 8, 16)
-    double unit_share = 0.25;         // tuning: largest unit / one wave's share of a search
-    bool timing = false;              // record events around each 16-bit sweep
+    bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_used;         // indices into ev_pool, in launch order
-    int32_t sat = kSat16;             // test hook: rerun threshold
     std::mutex mu;
 };
 
 namespace {
 
 constexpr int kCounters = 4;   // [0] bulk sweep counter, [1] rerun count, [2] rerun counter, [3] side sweep counter
+constexpr int kRerunGrid = 64;
 constexpr int kRerunRows = 8;  // rows per lane of the 32-bit recompute
 constexpr int kMaxWgPerCu = 4; // persistent workgroups per CU (bounds the scratch slots)
 const int kRowChoices[3] = {4, 8, 16};
-constexpr int kRerunGrid = 64;
 
 struct DeviceGuard {
     int prev = -1;
@@ -159,6 +199,21 @@ struct DeviceGuard {
     }
     ~DeviceGuard() { if (prev >= 0) hipSetDevice(prev); }
 };
+
+sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
+    if (!opts) return SW_OK;
+    const int fl = opts->force_lanes;
+    if (fl < 0 || fl > 64 || (fl & (fl - 1))) return fail(SW_E_INVALID, "force_lanes must be 0 or a power of two <= 64");
+    if (opts->rerun_threshold < 0) return fail(SW_E_INVALID, "rerun_threshold must be >= 0");
+    const int rpl = opts->rows_per_lane;
+    if (rpl != 0 && rpl != 4 && rpl != 8 && rpl != 16) return fail(SW_E_INVALID, "rows_per_lane must be 0, 4, 8 or 16");
+    if (opts->unit_share < 0 || opts->unit_share > 100000) return fail(SW_E_INVALID, "unit_share must be in 0..100000");
+    db->force_lgB = fl ? __builtin_ctz(fl) : -1;
+    db->force_R = rpl;
+    db->unit_share = opts->unit_share > 0 ? opts->unit_share / 1000.0 : 0.25;
+    db->sat = opts->rerun_threshold > 0 ? std::min<int32_t>(opts->rerun_threshold, kSat16) : kSat16;
+    return SW_OK;
+}
 
 // ------------------------------------------------------------------ planning
 int64_t unit_cost(int m, int ncols, int lgB, int R) {
@@ -173,11 +228,11 @@ int64_t unit_cost(int m, int ncols, int lgB, int R) {
 // groups.  Every group gets the smallest lanes-per-pair B whose units cost at
 // most a set fraction of a persistent wave's share of the work (0.25 by
 // default: smaller units force wide lane cooperation whose pass height exceeds
-// short queries, larger ones lengthen the longest-first tail) and whose boundary row
-// fits a scratch slot.  Units still above that share at B = 64 are pairs that
-// a single wave sweeps column by column; when a smaller R makes them cheaper
-// (short queries: most of a 64 x 16-row pass would be padding) they go to the
-// side list.  Items are ordered longest first.
+// short queries, larger ones lengthen the longest-first tail) and whose
+// boundary row fits a scratch slot.  Units still above that share at B = 64
+// are pairs that a single wave sweeps column by column; for a single short
+// query a smaller R makes them cheaper (most of a 64 x 16-row pass would be
+// padding) and they go to the side list.  Items are ordered longest first.
 void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
                 std::vector<WgItem>& side_out) {
     int R_main = 16;
@@ -204,12 +259,10 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
     for (size_t qi = 0; qi < qlens.size(); ++qi) {
         const int m = qlens[qi];
         if (m <= 0) continue;
-        // a short query's long pairs: the R that makes a 64-lane unit cheapest
-        // (single-query plans only: a batch has enough work to hide them)
         int r_long = R_main;
-        if (qlens.size() == 1)
+        if (qlens.size() == 1 && !db->force_R)
             for (int R : kRowChoices)
-            if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
+                if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
         WgItem cur{0, (int32_t)qi, 0, -1, 0, 0}, scur{0, (int32_t)qi, 0, -1, 0, 0};
         int64_t cur_cost = 0, scur_cost = 0;
         auto flush = [](std::vector<Tmp>& v, WgItem& c, int64_t& cc) {
@@ -264,6 +317,40 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
     plan->R_side = R_side;
 }
 
+sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p) {
+    std::vector<WgItem> mi, si;
+    plan_units(db, qlens, p, mi, si);
+    p->n_main = (int32_t)mi.size();
+    p->n_side = (int32_t)si.size();
+    mi.insert(mi.end(), si.begin(), si.end());
+    HIP_TRY(p->items.reserve(std::max<size_t>(mi.size(), 1) * sizeof(WgItem), &db->gen));
+    if (!mi.empty()) HIP_TRY(hipMemcpy(p->items.p, mi.data(), mi.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+    return SW_OK;
+}
+
+sw_status get_plan(sw_db* db, int m, Plan** out) {
+    auto it = db->plans.find(m);
+    if (it != db->plans.end()) { *out = &it->second; return SW_OK; }
+    if (db->plans.size() >= 64) {
+        for (auto& kv : db->plans) kv.second.items.release();
+        db->plans.clear();
+    }
+    Plan& p = db->plans[m];
+    sw_status s = build_plan(db, std::vector<int>{m}, &p);
+    if (s != SW_OK) { p.items.release(); db->plans.erase(m); return s; }
+    *out = &p;
+    return SW_OK;
+}
+
+void clear_caches(sw_db* db) {
+    for (auto& kv : db->plans) kv.second.items.release();
+    db->plans.clear();
+    db->batch_plan.items.release();
+    db->batch_plan.n_main = db->batch_plan.n_side = 0;
+    db->batch_qlens.clear();
+    db->graph.clear();
+}
+
 sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
     if (!subst) return fail(SW_E_INVALID, "substitution matrix pointer is NULL");
     if (go < 0 || ge < 0) return fail(SW_E_INVALID, "gap penalties must be >= 0 (got %d, %d)", go, ge);
@@ -290,64 +377,82 @@ sw_status ensure_workspace(sw_db* db) {
         db->slot_cap = std::max<int64_t>(65536, db->ncols_max);
         const int64_t nw16 = (int64_t)db->wg16 * kWaves;
         const int64_t nw32 = (int64_t)db->wg32 * kWaves;
-        HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4));
-        HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4));
-        HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t)));
+        HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4, &db->gen));
+        HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4, &db->gen));
+        HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t), &db->gen));
         HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&db->cap, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
     }
     return SW_OK;
 }
 
-// Stages [QDesc x nq][qoff x nq][subst 400][queries] in pinned memory, copies
-// it to the device and launches the profile kernel.  Returns device pointers.
-struct Staged { const QDesc* qd; const int64_t* qoff; const int8_t* sm_q; int max_mp; };
+// Layout of the staging buffer: [QDesc x nq][qoff x nq][subst 400][queries].
+struct StageLayout { size_t off_qoff, off_sm, total; int64_t prof_elems; int max_mp; };
 
-sw_status stage_queries(sw_db* db, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
-                        const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out) {
-    std::vector<QDesc> qd(nq);
-    int64_t prof_elems = 0;
-    int max_mp = kProfRowAlign;
+StageLayout stage_layout(const int64_t* h_qoffsets, int nq) {
+    StageLayout L{};
+    L.off_qoff = round_up(sizeof(QDesc) * nq, 64);
+    L.off_sm = L.off_qoff + round_up(sizeof(int64_t) * nq, 64);
+    L.total = L.off_sm + 400 + (h_qoffsets[nq] - h_qoffsets[0]);
+    L.max_mp = kProfRowAlign;
     for (int q = 0; q < nq; ++q) {
         const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
         const int mp = (int)round_up(std::max(m, 1), kProfRowAlign);
-        qd[q] = QDesc{prof_elems, (int64_t)q * score_row_stride, m, mp};
-        prof_elems += (int64_t)kNRes * mp;
-        max_mp = std::max(max_mp, mp);
+        L.prof_elems += (int64_t)kNRes * mp;
+        L.max_mp = std::max(L.max_mp, mp);
     }
-    const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
-    const size_t off_qd = 0;
-    const size_t off_qoff = round_up(sizeof(QDesc) * nq, 64);
-    const size_t off_sm = off_qoff + round_up(sizeof(int64_t) * nq, 64);
-    const size_t total = off_sm + 400 + qbytes;
-    HIP_TRY(db->hstage.reserve(total));
-    if (!db->hstage.done) HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
-    HIP_TRY(db->stage.reserve(total));
-    HIP_TRY(db->prof.reserve(prof_elems * sizeof(int16_t)));
-    char* h = static_cast<char*>(db->hstage.p);
-    memcpy(h + off_qd, qd.data(), sizeof(QDesc) * nq);
-    int64_t* qo = reinterpret_cast<int64_t*>(h + off_qoff);
-    for (int q = 0; q < nq; ++q) qo[q] = h_qoffsets[q] - h_qoffsets[0];
-    memcpy(h + off_sm, subst, 400);
-    if (qbytes) memcpy(h + off_sm + 400, h_queries + h_qoffsets[0], qbytes);
-    HIP_TRY(hipMemcpyAsync(db->stage.p, h, total, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(db->hstage.done, st));
-    db->hstage.pending = true;
-    char* d = db->stage.as<char>();
-    out->qd = reinterpret_cast<const QDesc*>(d + off_qd);
-    out->qoff = reinterpret_cast<const int64_t*>(d + off_qoff);
-    out->sm_q = reinterpret_cast<const int8_t*>(d + off_sm);
-    out->max_mp = max_mp;
-    HIP_TRY(launch_profile(out->sm_q, out->qd, nq, out->qoff, db->prof.as<int16_t>(), db->counters.as<int32_t>(),
-                           kCounters, max_mp, st));
+    return L;
+}
+
+// Every device buffer a launch sequence for this input needs (may reallocate).
+sw_status reserve_for(sw_db* db, const StageLayout& L, int64_t rerun_cap) {
+    HIP_TRY(db->hstage.reserve(L.total));
+    HIP_TRY(db->stage.reserve(L.total, &db->gen));
+    HIP_TRY(db->prof.reserve(L.prof_elems * sizeof(int16_t), &db->gen));
+    HIP_TRY(db->rerun.reserve((size_t)rerun_cap * sizeof(WgItem), &db->gen));
     return SW_OK;
 }
 
-sw_status run_sweeps(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int32_t ge, int32_t* d_scores,
-                     int64_t rerun_cap, hipStream_t st) {
-    HIP_TRY(db->rerun.reserve((size_t)rerun_cap * sizeof(WgItem)));
+// Copies the queries (host) into the staging buffer on the device.  No launch.
+sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
+                        const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out) {
+    char* h = static_cast<char*>(db->hstage.p);
+    int64_t prof_off = 0;
+    QDesc* qd = reinterpret_cast<QDesc*>(h);
+    int64_t* qo = reinterpret_cast<int64_t*>(h + L.off_qoff);
+    for (int q = 0; q < nq; ++q) {
+        const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
+        const int mp = (int)round_up(std::max(m, 1), kProfRowAlign);
+        qd[q] = QDesc{prof_off, (int64_t)q * score_row_stride, m, mp};
+        prof_off += (int64_t)kNRes * mp;
+        qo[q] = h_qoffsets[q] - h_qoffsets[0];
+    }
+    memcpy(h + L.off_sm, subst, 400);
+    const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
+    if (qbytes) memcpy(h + L.off_sm + 400, h_queries + h_qoffsets[0], qbytes);
+    HIP_TRY(hipMemcpyAsync(db->stage.p, h, L.total, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(db->hstage.done, st));
+    db->hstage.pending = true;
+    char* d = db->stage.as<char>();
+    out->qd = reinterpret_cast<const QDesc*>(d);
+    out->qoff = reinterpret_cast<const int64_t*>(d + L.off_qoff);
+    out->sm_q = reinterpret_cast<const int8_t*>(d + L.off_sm);
+    out->nq = nq;
+    out->max_mp = L.max_mp;
+    return SW_OK;
+}
+
+// The launch sequence of a search: profile (zeroes the counters), the side and
+// bulk 16-bit sweeps, the 32-bit recompute, top-k.  Allocates nothing and never
+// waits on the host, so it can be captured into a graph.
+sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int32_t ge, int32_t* d_scores,
+                  int64_t n, int64_t rerun_cap, int k, int32_t* top_s, int64_t* top_i, hipStream_t st,
+                  bool time_sweep) {
     int32_t* ctr = db->counters.as<int32_t>();
+    HIP_TRY(launch_profile(S.sm_q, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
     const WgItem* d_items = plan.items.as<WgItem>();
     SweepArgs a{};
     a.items = d_items;
@@ -387,7 +492,7 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const Plan& plan, int32_t go, i
         HIP_TRY(hipEventRecord(db->ev_join, db->side));
     }
     int ev = -1;
-    if (db->timing) {
+    if (time_sweep && db->timing) {
         if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
         ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
         while ((int)db->ev_pool.size() <= ev) {
@@ -418,6 +523,7 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const Plan& plan, int32_t go, i
     r.rerun_cap = 0;
     r.unit_list = 1;
     HIP_TRY(launch_sweep(false, kRerunRows, r, db->wg32, st));
+    if (k > 0) HIP_TRY(launch_topk(d_scores, n, n, S.nq, k, top_s, top_i, st));
     db->last_items = plan.n_main;
     db->last_rows = plan.R_main;
     db->last_side_items = plan.n_side;
@@ -426,30 +532,25 @@ sw_status run_sweeps(sw_db* db, const Staged& S, const Plan& plan, int32_t go, i
     return SW_OK;
 }
 
-sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p) {
-    std::vector<WgItem> mi, si;
-    plan_units(db, qlens, p, mi, si);
-    p->n_main = (int32_t)mi.size();
-    p->n_side = (int32_t)si.size();
-    mi.insert(mi.end(), si.begin(), si.end());
-    HIP_TRY(p->items.reserve(std::max<size_t>(mi.size(), 1) * sizeof(WgItem)));
-    if (!mi.empty()) HIP_TRY(hipMemcpy(p->items.p, mi.data(), mi.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if (n != db->n) return fail(SW_E_INVALID, "n = %lld but the database holds %lld subjects", (long long)n, (long long)db->n);
+    if (h_offsets && n > 0 && (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last))
+        return fail(SW_E_INVALID, "offsets do not match the packed database");
     return SW_OK;
 }
 
-sw_status get_plan(sw_db* db, int m, Plan** out) {
-    auto key = std::make_pair(m, 0);
-    auto it = db->plans.find(key);
-    if (it != db->plans.end()) { *out = &it->second; return SW_OK; }
-    if (db->plans.size() >= 64) {
-        for (auto& kv : db->plans) kv.second.items.release();
-        db->plans.clear();
+int record_timer_start(sw_db* db, hipStream_t st) {
+    if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
+    const int ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
+    while ((int)db->ev_pool.size() <= ev) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess) return -1;
+        if (hipEventCreate(&y) != hipSuccess) { hipEventDestroy(x); return -1; }
+        db->ev_pool.push_back({x, y});
     }
-    Plan& p = db->plans[key];
-    sw_status s = build_plan(db, std::vector<int>{m}, &p);
-    if (s != SW_OK) { p.items.release(); db->plans.erase(key); return s; }
-    *out = &p;
-    return SW_OK;
+    if (hipEventRecord(db->ev_pool[ev].first, st) != hipSuccess) return -1;
+    return ev;
 }
 
 }  // namespace
@@ -493,20 +594,8 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
     if (!db) return fail(SW_E_NOMEM, "host allocation failed");
     auto bail = [&](sw_status s) { sw_db_free(db); return s; };
     if (hipGetDevice(&db->device) != hipSuccess) return bail(fail(SW_E_HIP, "no current HIP device"));
-    if (opts) {
-        const int fl = opts->force_lanes;
-        if (fl != 0) {
-            if (fl < 0 || fl > 64 || (fl & (fl - 1))) return bail(fail(SW_E_INVALID, "force_lanes must be 0 or a power of two <= 64"));
-            db->force_lgB = __builtin_ctz(fl);
-        }
-        if (opts->rerun_threshold < 0) return bail(fail(SW_E_INVALID, "rerun_threshold must be >= 0"));
-        const int rpl = opts->rows_per_lane;
-        if (rpl != 0 && rpl != 4 && rpl != 8 && rpl != 16) return bail(fail(SW_E_INVALID, "rows_per_lane must be 0, 4, 8 or 16"));
-        db->force_R = rpl;
-        if (opts->unit_share < 0 || opts->unit_share > 100000) return bail(fail(SW_E_INVALID, "unit_share must be in 0..100000"));
-        if (opts->unit_share > 0) db->unit_share = opts->unit_share / 1000.0;
-        if (opts->rerun_threshold > 0) db->sat = std::min<int32_t>(opts->rerun_threshold, kSat16);
-    }
+    sw_status so = apply_opts(db, opts);
+    if (so != SW_OK) return bail(so);
     db->n = n;
     db->off_first = n > 0 ? h_offsets[0] : 0;
     db->off_last = n > 0 ? h_offsets[n] : 0;
@@ -575,18 +664,32 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
     return SW_OK;
 }
 
+sw_status sw_db_tune(sw_db* db, const sw_pack_opts* opts) {
+    g_err.clear();
+    if (!db || !opts) return fail(SW_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    sw_db probe;
+    sw_status s = apply_opts(&probe, opts);        // validate before touching the handle
+    if (s != SW_OK) return s;
+    HIP_TRY(hipDeviceSynchronize());               // no search of this handle may be in flight
+    apply_opts(db, opts);
+    clear_caches(db);
+    return SW_OK;
+}
+
 void sw_db_free(sw_db* db) {
     if (!db) return;
     DeviceGuard dg(db->device);
     hipDeviceSynchronize();
+    clear_caches(db);
     db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
-    db->counters.release(); db->rerun.release(); db->scores_tmp.release(); db->topk_dummy.release();
+    db->counters.release(); db->rerun.release(); db->scores_tmp.release();
     db->hstage.release();
-    for (auto& kv : db->plans) kv.second.items.release();
-    db->batch_plan.items.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (db->side) hipStreamDestroy(db->side);
+    if (db->cap) hipStreamDestroy(db->cap);
     if (db->ev_fork) hipEventDestroy(db->ev_fork);
     if (db->ev_join) hipEventDestroy(db->ev_join);
     delete db;
@@ -597,17 +700,9 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
     if (n) *n = db->n;
     if (residues) *residues = db->total_res;
     if (device_bytes)
-        *device_bytes = (int64_t)(db->image.bytes + db->groups.bytes + db->perm.bytes + db->scratch16.bytes +
-                                  db->scratch32.bytes + db->prof.bytes + db->stage.bytes + db->rerun.bytes +
-                                  db->scores_tmp.bytes);
-    return SW_OK;
-}
-
-static sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
-    if (!db) return fail(SW_E_INVALID, "db is NULL");
-    if (n != db->n) return fail(SW_E_INVALID, "n = %lld but the database holds %lld subjects", (long long)n, (long long)db->n);
-    if (h_offsets && n > 0 && (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last))
-        return fail(SW_E_INVALID, "offsets do not match the packed database");
+        *device_bytes = (int64_t)(db->image.bytes + db->groups.bytes + db->perm.bytes + db->pair_cols.bytes +
+                                  db->scratch16.bytes + db->scratch32.bytes + db->prof.bytes + db->stage.bytes +
+                                  db->rerun.bytes + db->scores_tmp.bytes);
     return SW_OK;
 }
 
@@ -632,10 +727,12 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
     Plan* plan = nullptr;
     if ((s = get_plan(db, qlen, &plan)) != SW_OK) return s;
     const int64_t qo[2] = {0, qlen};
-    Staged S;
-    if ((s = stage_queries(db, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
+    const StageLayout L = stage_layout(qo, 1);
     const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
-    return run_sweeps(db, S, *plan, gap_open, gap_extend, d_scores_out, rerun_cap, st);
+    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
+    return enqueue(db, S, *plan, gap_open, gap_extend, d_scores_out, n, rerun_cap, 0, nullptr, nullptr, st, true);
 }
 
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
@@ -672,29 +769,68 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
     DeviceGuard dg(db->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = db->n;
+    std::vector<int> qlens(nq);
+    for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
     int32_t* scores = d_scores;
     if (!scores) {
-        HIP_TRY(db->scores_tmp.reserve((size_t)nq * std::max<int64_t>(n, 1) * sizeof(int32_t)));
+        HIP_TRY(db->scores_tmp.reserve((size_t)nq * std::max<int64_t>(n, 1) * sizeof(int32_t), &db->gen));
         scores = db->scores_tmp.as<int32_t>();
     }
-    if (n > 0) {
-        if ((s = ensure_workspace(db)) != SW_OK) return s;
-        std::vector<int> qlens(nq);
-        for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
-        // zero-length queries score 0 everywhere
-        for (int q = 0; q < nq; ++q)
-            if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
-        // a synchronous copy of the plan: the batch plan buffer is reused by the next call
-        HIP_TRY(hipStreamSynchronize(st));
-        sw_status ps = build_plan(db, qlens, &db->batch_plan);
-        if (ps != SW_OK) return ps;
-        Staged S;
-        if ((s = stage_queries(db, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
-        const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
-        if (db->batch_plan.n_main + db->batch_plan.n_side > 0)
-            if ((s = run_sweeps(db, S, db->batch_plan, gap_open, gap_extend, scores, rerun_cap, st)) != SW_OK) return s;
+    if (n == 0) {
+        if (k > 0) HIP_TRY(launch_topk(scores, 0, 0, nq, k, d_top_scores, d_top_index, st));
+        return SW_OK;
     }
-    if (k > 0) HIP_TRY(launch_topk(scores, n, n, nq, k, d_top_scores, d_top_index, st));
+    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    // zero-length queries score 0 everywhere (outside the captured sequence)
+    for (int q = 0; q < nq; ++q)
+        if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
+    if (qlens != db->batch_qlens) {
+        HIP_TRY(hipStreamSynchronize(st));          // the previous batch may still read the plan buffer
+        db->batch_qlens.clear();
+        if ((s = build_plan(db, qlens, &db->batch_plan)) != SW_OK) return s;
+        db->batch_qlens = qlens;
+    }
+    const StageLayout L = stage_layout(h_qoffsets, nq);
+    const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
+    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
+    GraphEntry& G = db->graph;
+    const bool hit = G.exec && G.gen == db->gen && G.qlens == qlens && G.go == gap_open && G.ge == gap_extend &&
+                     G.k == k && G.scores == scores && G.top_s == d_top_scores && G.top_i == d_top_index &&
+                     G.stream == st;
+    if (!hit) {
+        // captured on the library's own stream (the caller's may be the legacy
+        // default stream, which cannot be captured); launched on the caller's
+        G.clear();
+        HIP_TRY(hipStreamBeginCapture(db->cap, hipStreamCaptureModeThreadLocal));
+        s = enqueue(db, S, db->batch_plan, gap_open, gap_extend, scores, n, rerun_cap, k, d_top_scores, d_top_index,
+                    db->cap, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(db->cap, &graph);
+        if (s != SW_OK) { if (graph) hipGraphDestroy(graph); return s; }
+        if (e != hipSuccess) return fail(SW_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { hipGraphDestroy(graph); return fail(SW_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
+        G.graph = graph;
+        G.exec = exec;
+        G.qlens = qlens;
+        G.go = gap_open;
+        G.ge = gap_extend;
+        G.k = k;
+        G.scores = scores;
+        G.top_s = d_top_scores;
+        G.top_i = d_top_index;
+        G.stream = st;
+        G.gen = db->gen;
+    }
+    const int ev = db->timing ? record_timer_start(db, st) : -1;
+    HIP_TRY(hipGraphLaunch(G.exec, st));
+    if (ev >= 0) {
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
+        db->ev_used.push_back(ev);
+    }
     return SW_OK;
 }
 

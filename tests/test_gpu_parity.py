@@ -254,6 +254,47 @@ def test_batch_matches_oracle(gpu, blosum):
     D.close()
 
 
+def test_batch_graph_replay(gpu, blosum):
+    """The batched launch sequence is captured once per shape and replayed: replay
+    it several times with new query contents of the same lengths, eager work and
+    synchronisations in between, and check every replay against the oracle."""
+    import torch
+    db = synth.small_db(seed=91, n=700, lo=1, hi=600)
+    lens = [5, 130, 47, 800, 1]
+    D = gpu.Database(db.residues, db.offsets)
+    scores = torch.empty((len(lens), db.n), dtype=torch.int32, device="cuda")
+    ts = torch.empty((len(lens), 10), dtype=torch.int32, device="cuda")
+    ti = torch.empty((len(lens), 10), dtype=torch.int64, device="cuda")
+    for rep in range(4):
+        queries = [synth.small_query(seed=1000 * rep + i, m=L) for i, L in enumerate(lens)]
+        qo = np.concatenate([[0], np.cumsum(lens)])
+        gpu.sw_search_batch(np.concatenate(queries), qo, D.handle, blosum, 10, 2, 10, scores, ts, ti)
+        torch.cuda.synchronize()
+        eager = torch.arange(1000, device="cuda").sum()      # unrelated eager work between replays
+        S = scores.cpu().numpy()
+        for i, q in enumerate(queries):
+            want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+            assert_equal_scores(S[i], want, f"replay {rep} query {i}")
+            ws, wi = oracle.topk(want, 10)
+            assert (ts[i].cpu().numpy() == ws).all() and (ti[i].cpu().numpy() == wi).all()
+        assert int(eager) == 499500
+    D.close()
+
+
+@pytest.mark.parametrize("knobs", [dict(rows_per_lane=8), dict(rows_per_lane=16, unit_share=50),
+                                   dict(force_lanes=4), dict(unit_share=2000)])
+def test_tuning_knobs_do_not_change_results(gpu, blosum, knobs):
+    import torch
+    qs, db = synth.workload1()
+    D = gpu.Database(db.residues, db.offsets)
+    base = D.search(qs[0], blosum, 10, 2).clone()
+    D.tune(**knobs)
+    other = D.search(qs[0], blosum, 10, 2).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(base, other), knobs
+    D.close()
+
+
 def test_invalid_residues_are_rejected(gpu, blosum):
     qs, db = synth.workload1()
     D = gpu.Database(db.residues, db.offsets)
