@@ -50,6 +50,9 @@ def workload(name: str):
     if name == "long10k":
         qs, db = synth.workload4()
         return qs, db, "64 queries 500..5,000 vs 10,000 subjects 3,000..35,000, BLOSUM62 10/2"
+    if name == "serve10M":
+        db = synth.workload5_db()
+        return [], db, "10,000,000 subjects (log-normal median 250, max 35,000), Poisson query arrivals"
     if name == "batch256":
         db = synth.sp570k()
         return synth.workload3_queries(db), db, "256 queries 50..5,000 vs 570,000 subjects, BLOSUM62 10/2, top-10"
@@ -75,13 +78,68 @@ def cpu_baseline(queries, db, sm, seconds: float):
             "sample": f"query 0 (m={q.size}) vs the first {done} subjects ({cells:.3e} cells) in {dt:.1f} s"}
 
 
+def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
+    """Served form: continuous batching vs plain FIFO on one Poisson trace."""
+    import torch
+    from inputs import synth
+    from paper_2309_09609_amd.serve import GpuEngine, Server, fifo_run
+    warm = 10
+    qs = synth.workload5_queries(warm + args.requests + 5)
+    cells = lambda q: int(q.size) * total_res  # noqa: E731
+    # plain service rate from a few searches
+    out = torch.empty(db.n, dtype=torch.int32, device="cuda")
+    D.search(qs[0], sm, 10, 2, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    probe = qs[-5:]
+    for q in probe:
+        D.search(q, sm, 10, 2, out=out)
+        sw.topk(out, 10)
+    torch.cuda.synchronize()
+    service = (time.perf_counter() - t) / len(probe) * float(np.mean([q.size for q in qs[: warm + args.requests]])) \
+        / float(np.mean([q.size for q in probe]))
+    rate = args.load / service
+    print(f"# plain service time {service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
+    trace = qs[: warm + args.requests]
+    arrivals = synth.poisson_arrivals(rate, len(trace))
+    eng = GpuEngine(D, sm, 10, 2, k=10)
+    srv = Server(eng, nchunks=args.chunks, mem_budget=2 << 30)
+    srv.run(trace[:warm], arrivals[:warm] - arrivals[0])
+    print("# served: warm-up done", file=sys.stderr, flush=True)
+    rep = srv.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells)
+    served = rep.summary()
+    print(f"# served: {served}", file=sys.stderr, flush=True)
+    fifo = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells).summary()
+    print(f"# plain FIFO: {fifo}", file=sys.stderr, flush=True)
+    res = {
+        "metric": METRIC, "value": round(served["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.requests,
+        "warmup": warm, "ms_per_step": round(served["makespan_s"] / args.requests * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16x2 saturating + int32 recompute", "data": "synthetic",
+        "config": {"workload": "serve10M", "form": "served (continuous batching)", "subjects": db.n,
+                   "residues": total_res, "requests": args.requests, "arrival_rate_per_s": round(rate, 3),
+                   "load_vs_plain": args.load, "chunks": args.chunks, "mem_budget_bytes": 2 << 30,
+                   "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
+        "latency": {"served_p50_s": round(served["p50_s"], 4), "served_p99_s": round(served["p99_s"], 4),
+                    "plain_p50_s": round(fifo["p50_s"], 4), "plain_p99_s": round(fifo["p99_s"], 4),
+                    "p99_gain": round(fifo["p99_s"] / served["p99_s"], 3) if served["p99_s"] > 0 else None},
+        "extra": {"served": served, "plain_fifo": fifo,
+                  "pct_int32_cell_peak": round(100 * served["gcups"] / perfmodel.mi355x_peak_gcups(), 2)},
+    }
+    D.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256"])
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256", "serve10M"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served"])
+    ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
+    ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
+    ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -118,6 +176,8 @@ def main():
     torch.cuda.synchronize()
     print(f"# packed in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     total_res = int(db.offsets[-1] - db.offsets[0])
+    if args.form == "served":
+        return serve_bench(args, sw, D, db, sm, total_res, perfmodel)
     qlens = [int(q.size) for q in queries]
     cells_step = sum(qlens) * total_res
     out = torch.empty(db.n, dtype=torch.int32, device="cuda")

@@ -157,6 +157,25 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
                           int32_t k, int32_t* d_scores, int32_t* d_top_scores, int64_t* d_top_index,
                           sw_stream stream);
 
+/*
+ * sw_search_multi - one launch sequence in which each query scores one chunk of
+ * the database (the building block of continuous batching in a serving loop).
+ * The length-sorted groups of 128 subjects are dealt round-robin into nchunks
+ * chunks: chunk c holds groups c, c + nchunks, c + 2*nchunks, ..., so every
+ * chunk has the same length mix.  Query q scores the subjects of chunk
+ * h_chunk[q] and writes those entries of its own score vector h_d_scores[q]
+ * (device int32[n], original subject order); entries of other chunks are left
+ * untouched.  After one call per chunk (in any order, in any mix of queries)
+ * the vector holds every score.  A zero-length query fills its whole vector
+ * with 0.
+ *   h_chunk    : host int32[nq], each in 0..nchunks-1.
+ *   h_d_scores : host array of nq device pointers.
+ * Synchronises the stream before planning (the plan buffer is reused).
+ */
+sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, const int32_t* h_chunk,
+                          int32_t nchunks, sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
+                          int32_t* const* h_d_scores, sw_stream stream);
+
 /* Human-readable name of a status code (static string). */
 const char* sw_status_str(sw_status s);
 /* Description of the most recent error on the calling thread ("" if none). */

@@ -26,6 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
+           "sw_search_multi",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -60,6 +61,8 @@ def load():
     lib.sw_topk.argtypes = [P, I64, I32, P, P, P]
     lib.sw_search_batch.restype = I32
     lib.sw_search_batch.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P]
+    lib.sw_search_multi.restype = I32
+    lib.sw_search_multi.argtypes = [P, P, I32, P, I32, P, P, I32, I32, P, P]
     lib.sw_status_str.restype = ctypes.c_char_p
     lib.sw_status_str.argtypes = [I32]
     lib.sw_last_error.restype = ctypes.c_char_p
@@ -144,6 +147,19 @@ def sw_search_batch(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, 
     P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
     _check(lib.sw_search_batch(_ptr(q), _ptr(qo), qo.size - 1, handle, _ptr(sm), int(gap_open), int(gap_extend),
                                int(k), P(d_scores), P(d_top_scores), P(d_top_index), _stream(stream)))
+
+
+def sw_search_multi(h_queries, h_qoffsets, chunks, nchunks, handle, subst, gap_open, gap_extend, d_scores_list,
+                    stream=None):
+    """Each query scores one database chunk into its own score tensor (see the C header)."""
+    lib = load()
+    q = _host_i8(h_queries)
+    qo = _host_i64(h_qoffsets)
+    ch = np.ascontiguousarray(np.asarray(chunks, dtype=np.int32))
+    sm = _host_i8(subst).reshape(-1)
+    ptrs = (ctypes.c_void_p * max(len(d_scores_list), 1))(*[t.data_ptr() for t in d_scores_list])
+    _check(lib.sw_search_multi(_ptr(q), _ptr(qo), qo.size - 1, _ptr(ch), int(nchunks), handle, _ptr(sm),
+                               int(gap_open), int(gap_extend), ptrs, _stream(stream)))
 
 
 # --------------------------------------------------------------------------- convenience layer

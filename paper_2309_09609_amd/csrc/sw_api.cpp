@@ -167,7 +167,7 @@ struct sw_db {
     DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp;
     HostPinned hstage;
     std::map<int, Plan> plans;        // plain searches: query length -> plan
-    Plan batch_plan;
+    Plan batch_plan, multi_plan;
     std::vector<int> batch_qlens;
     GraphEntry graph;                 // batched form: last captured shape
     // tuning knobs and test hooks
@@ -234,24 +234,26 @@ int64_t unit_cost(int m, int ncols, int lgB, int R) {
 // query a smaller R makes them cheaper (most of a 64 x 16-row pass would be
 // padding) and they go to the side list.  Items are ordered longest first.
 void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
-                std::vector<WgItem>& side_out) {
+                std::vector<WgItem>& side_out, const std::vector<int>* chunk = nullptr, int nchunks = 1) {
+    // query qi covers groups chunk[qi], chunk[qi] + nchunks, ... (all groups when nchunks == 1)
+    auto first_group = [&](size_t qi) { return chunk ? (*chunk)[qi] : 0; };
     int R_main = 16;
     {
         int64_t best = -1;
         for (int R : {8, 16}) {
             int64_t t = 0;
-            for (int m : qlens)
-                if (m > 0)
-                    for (int g = 0; g < db->ngroups; ++g) t += unit_cost(m, db->ncols[g], 0, R);
+            for (size_t qi = 0; qi < qlens.size(); ++qi)
+                if (qlens[qi] > 0)
+                    for (int g = first_group(qi); g < db->ngroups; g += nchunks) t += unit_cost(qlens[qi], db->ncols[g], 0, R);
             if (best < 0 || t < best) { best = t; R_main = R; }
         }
     }
     if (db->force_R) R_main = db->force_R;
     const int64_t nwaves = (int64_t)db->wgR[R_main] * kWaves;
     int64_t total = 0;
-    for (int m : qlens)
-        if (m > 0)
-            for (int g = 0; g < db->ngroups; ++g) total += unit_cost(m, db->ncols[g], 0, R_main);
+    for (size_t qi = 0; qi < qlens.size(); ++qi)
+        if (qlens[qi] > 0)
+            for (int g = first_group(qi); g < db->ngroups; g += nchunks) total += unit_cost(qlens[qi], db->ncols[g], 0, R_main);
     const double cap = db->unit_share * (double)total / (double)std::max<int64_t>(nwaves, 1);
     int R_side = R_main;
     struct Tmp { WgItem it; int64_t cost; };
@@ -263,7 +265,8 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
         if (qlens.size() == 1 && !db->force_R)
             for (int R : kRowChoices)
                 if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
-        WgItem cur{0, (int32_t)qi, 0, -1, 0, 0}, scur{0, (int32_t)qi, 0, -1, 0, 0};
+        const int g_first = first_group(qi);
+        WgItem cur{0, (int32_t)qi, 0, -1, 0, nchunks}, scur{0, (int32_t)qi, 0, -1, 0, nchunks};
         int64_t cur_cost = 0, scur_cost = 0;
         auto flush = [](std::vector<Tmp>& v, WgItem& c, int64_t& cc) {
             if (c.count > 0) v.push_back({c, cc});
@@ -271,8 +274,9 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
             cc = 0;
         };
         auto add = [&](std::vector<Tmp>& v, WgItem& c, int64_t& cc, int g, int k, int lgB, int64_t cost) {
-            const bool contiguous = c.count > 0 && c.lgB == lgB &&
-                                    ((int64_t)c.g0 << lgB) + c.k0 + c.count == ((int64_t)g << lgB) + k;
+            // position of (group, sub-unit) in this query's unit sequence
+            const int64_t seq_g = (g - g_first) / nchunks, seq_c = (c.g0 - g_first) / nchunks;
+            const bool contiguous = c.count > 0 && c.lgB == lgB && (seq_c << lgB) + c.k0 + c.count == (seq_g << lgB) + k;
             if (c.count == kWaves || !contiguous) {
                 flush(v, c, cc);
                 c.g0 = g;
@@ -282,7 +286,7 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
             c.count++;
             cc = std::max(cc, cost);
         };
-        for (int g = 0; g < db->ngroups; ++g) {
+        for (int g = g_first; g < db->ngroups; g += nchunks) {
             const int nc = db->ncols[g];
             int lgB = 0;
             for (; lgB < 6; ++lgB) {
@@ -311,15 +315,16 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
     auto by_cost = [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; };
     std::stable_sort(items.begin(), items.end(), by_cost);
     std::stable_sort(sitems.begin(), sitems.end(), by_cost);
-    for (auto& t : items) { t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX); main_out.push_back(t.it); }
-    for (auto& t : sitems) { t.it.cost = (int32_t)std::min<int64_t>(t.cost >> 8, INT32_MAX); side_out.push_back(t.it); }
+    for (auto& t : items) main_out.push_back(t.it);
+    for (auto& t : sitems) side_out.push_back(t.it);
     plan->R_main = R_main;
     plan->R_side = R_side;
 }
 
-sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p) {
+sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p, const std::vector<int>* chunk = nullptr,
+                     int nchunks = 1) {
     std::vector<WgItem> mi, si;
-    plan_units(db, qlens, p, mi, si);
+    plan_units(db, qlens, p, mi, si, chunk, nchunks);
     p->n_main = (int32_t)mi.size();
     p->n_side = (int32_t)si.size();
     mi.insert(mi.end(), si.begin(), si.end());
@@ -347,6 +352,8 @@ void clear_caches(sw_db* db) {
     db->plans.clear();
     db->batch_plan.items.release();
     db->batch_plan.n_main = db->batch_plan.n_side = 0;
+    db->multi_plan.items.release();
+    db->multi_plan.n_main = db->multi_plan.n_side = 0;
     db->batch_qlens.clear();
     db->graph.clear();
 }
@@ -418,7 +425,8 @@ sw_status reserve_for(sw_db* db, const StageLayout& L, int64_t rerun_cap) {
 
 // Copies the queries (host) into the staging buffer on the device.  No launch.
 sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
-                        const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out) {
+                        const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out,
+                        int32_t* const* per_query_out = nullptr) {
     char* h = static_cast<char*>(db->hstage.p);
     int64_t prof_off = 0;
     QDesc* qd = reinterpret_cast<QDesc*>(h);
@@ -426,7 +434,7 @@ sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries
     for (int q = 0; q < nq; ++q) {
         const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
         const int mp = (int)round_up(std::max(m, 1), kProfRowAlign);
-        qd[q] = QDesc{prof_off, (int64_t)q * score_row_stride, m, mp};
+        qd[q] = QDesc{prof_off, (int64_t)q * score_row_stride, per_query_out ? per_query_out[q] : nullptr, m, mp};
         prof_off += (int64_t)kNRes * mp;
         qo[q] = h_qoffsets[q] - h_qoffsets[0];
     }
@@ -832,6 +840,45 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
         db->ev_used.push_back(ev);
     }
     return SW_OK;
+}
+
+sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, const int32_t* h_chunk,
+                          int32_t nchunks, sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
+                          int32_t* const* h_d_scores, sw_stream stream) {
+    g_err.clear();
+    sw_status s;
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (nq < 0 || nchunks < 1) return fail(SW_E_INVALID, "nq must be >= 0 and nchunks >= 1");
+    if (nq > 0 && (!h_qoffsets || !h_queries || !h_chunk || !h_d_scores)) return fail(SW_E_INVALID, "NULL argument");
+    for (int q = 0; q < nq; ++q) {
+        if (h_qoffsets[q + 1] < h_qoffsets[q]) return fail(SW_E_INVALID, "query offsets decrease at %d", q);
+        if (h_qoffsets[q + 1] - h_qoffsets[q] > (1 << 24)) return fail(SW_E_UNSUPPORTED, "query %d too long", q);
+        if (h_chunk[q] < 0 || h_chunk[q] >= nchunks) return fail(SW_E_INVALID, "chunk %d of query %d outside 0..%d", h_chunk[q], q, nchunks - 1);
+        if (db->n > 0 && !h_d_scores[q]) return fail(SW_E_INVALID, "score vector of query %d is NULL", q);
+    }
+    if (nq > 0)
+        for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
+            if (h_queries[i] < 0 || h_queries[i] >= 20) return fail(SW_E_RESIDUE, "query residue outside 0..19 at %lld", (long long)i);
+    if (nq == 0 || db->n == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    std::vector<int> qlens(nq), chunk(h_chunk, h_chunk + nq);
+    for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
+    // a zero-length query scores 0 on its chunk: fill its whole vector (other chunks are 0 as well)
+    for (int q = 0; q < nq; ++q)
+        if (qlens[q] == 0) HIP_TRY(launch_fill(h_d_scores[q], db->n, 0, st));
+    HIP_TRY(hipStreamSynchronize(st));              // the previous call may still read the plan buffer
+    if ((s = build_plan(db, qlens, &db->multi_plan, &chunk, nchunks)) != SW_OK) return s;
+    const StageLayout L = stage_layout(h_qoffsets, nq);
+    const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
+    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, 0, st, &S, h_d_scores)) != SW_OK) return s;
+    if (db->multi_plan.n_main + db->multi_plan.n_side == 0) return SW_OK;
+    return enqueue(db, S, db->multi_plan, gap_open, gap_extend, nullptr, db->n, rerun_cap, 0, nullptr, nullptr, st, true);
 }
 
 sw_status sw_profile_kernels(sw_db* db, int32_t enable) {

@@ -30,21 +30,23 @@ struct GroupRec {
 };
 
 // One unit of work for a wave: pairs [k*P, (k+1)*P) of group g, P = 64 >> lgB, with B = 1 << lgB
-// lanes cooperating on each pair.  A workgroup item bundles up to kWaves consecutive units
-// (wave w takes unit k0 + w, carried into following groups) of one query.
+// lanes cooperating on each pair.  A workgroup item bundles up to kWaves units of one query:
+// wave w takes unit k0 + w, carried into the following groups of the item's group sequence
+// g0, g0 + gstep, g0 + 2 gstep, ... (gstep > 1 when a search covers every gstep-th group).
 struct WgItem {
     int32_t g0;       // group of the first unit
     int32_t q;        // query index within the launch
     int16_t k0;       // sub-group index of the first unit within g0
     int8_t lgB;       // log2 of lanes per pair (0..6)
     int8_t count;     // number of valid units (1..kWaves)
-    int32_t cost;     // planner's cost estimate (diagnostic)
+    int32_t gstep;    // distance between consecutive groups of the item
 };
 
 // Per-query descriptor.
 struct QDesc {
     int64_t prof_off;     // element offset of this query's profile [kNRes][mp] in the profile buffer
-    int64_t out_off;      // element offset of this query's score row in the output
+    int64_t out_off;      // element offset of this query's score row in the common output
+    int32_t* out;         // if non-null: this query's own score vector (out_off is then ignored)
     int32_t m;            // query length (>= 1)
     int32_t mp;           // profile row stride (multiple of kProfRowAlign, >= m)
 };

@@ -314,12 +314,12 @@ __device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k
     if (b == 0) {
         const int slot0 = g * kGroupSubjects + 2 * pair;
         const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
-        int32_t* out = a.scores + Q.out_off;
+        int32_t* out = Q.out ? Q.out : a.scores + Q.out_off;
         if (o0 >= 0) out[o0] = C::lo(S);
         if (o1 >= 0) out[o1] = C::hi(S);
         if (a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) {
             const int idx = atomicAdd(a.rerun_count, 1);
-            if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, q, (int16_t)pair, 6, 1, 0};
+            if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, q, (int16_t)pair, 6, 1, 1};
         }
     }
 }
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
             const WgItem I = a.items[it];
             const int B = 1 << I.lgB;
             int k = I.k0 + wave;
-            const int g = I.g0 + (k >> I.lgB);
+            const int g = I.g0 + (k >> I.lgB) * I.gstep;
             k &= B - 1;
             const bool shared_slice = I.lgB > 4;        // more than 16 lanes per pair
             run_unit_passes<C, R>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);

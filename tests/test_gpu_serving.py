@@ -1,0 +1,66 @@
+"""GPU: chunked multi-query launches and the continuous-batching server give
+exactly the oracle's scores and top-k, and each request's result is the same
+alone and in the mix (tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nchunks", [1, 3, 7])
+def test_search_multi_covers_all_chunks(gpu, blosum, nchunks):
+    import torch
+    db = synth.small_db(seed=5 + nchunks, n=2500, lo=1, hi=700, median=250)
+    D = gpu.Database(db.residues, db.offsets)
+    qs = [synth.small_query(seed=s, m=m) for s, m in [(1, 33), (2, 260), (3, 1), (4, 900)]]
+    outs = [torch.full((db.n,), -7, dtype=torch.int32, device="cuda") for _ in qs]
+    qo = np.concatenate([[0], np.cumsum([q.size for q in qs])])
+    for step in range(nchunks):
+        # each query starts at a different chunk
+        chunks = [(i + step) % nchunks for i in range(len(qs))]
+        gpu.sw_search_multi(np.concatenate(qs), qo, chunks, nchunks, D.handle, blosum, 10, 2, outs)
+        torch.cuda.synchronize()
+        if step == 0 and nchunks > 1:
+            assert (outs[0].cpu().numpy() == -7).any()      # other chunks not written yet
+    for q, o in zip(qs, outs):
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+        assert (o.cpu().numpy() == want).all()
+    D.close()
+
+
+def test_server_results_alone_and_in_mix(gpu, blosum):
+    from paper_2309_09609_amd.serve import GpuEngine, Server
+    db = synth.small_db(seed=77, n=3000, lo=20, hi=1500, median=300)
+    D = gpu.Database(db.residues, db.offsets)
+    rng = np.random.default_rng(1)
+    qs = [synth.small_query(seed=100 + i, m=int(m)) for i, m in enumerate(rng.integers(30, 700, 12))]
+    arrivals = np.sort(rng.uniform(0, 0.05, len(qs)))
+    eng = GpuEngine(D, blosum, 10, 2, k=10)
+    mix = Server(eng, nchunks=4).run(qs, arrivals)
+    assert mix.max_active > 1
+    for i, q in enumerate(qs):
+        alone = Server(GpuEngine(D, blosum, 10, 2, k=10), nchunks=4).run([q], [0.0])
+        a_s, a_i = alone.results[0]
+        m_s, m_i = mix.results[i]
+        assert (a_s == m_s).all() and (a_i == m_i).all(), i
+        ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 10)
+        assert (m_s == ws).all() and (m_i == wi).all(), i
+    D.close()
+
+
+def test_server_under_tiny_memory_budget(gpu, blosum):
+    from paper_2309_09609_amd.serve import GpuEngine, Server
+    db = synth.small_db(seed=78, n=1000, lo=20, hi=800, median=300)
+    D = gpu.Database(db.residues, db.offsets)
+    qs = [synth.small_query(seed=200 + i, m=50 + 40 * i) for i in range(6)]
+    eng = GpuEngine(D, blosum, 10, 2, k=5)
+    srv = Server(eng, nchunks=3, mem_budget=2 * eng.slot_bytes)
+    rep = srv.run(qs, np.zeros(len(qs)))
+    assert srv.max_slots == 2 and rep.max_active == 2 and srv.allocated == 2
+    for i, q in enumerate(qs):
+        ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 5)
+        assert (rep.results[i][0] == ws).all() and (rep.results[i][1] == wi).all()
+    D.close()

@@ -1,0 +1,104 @@
+"""Host logic of the continuous-batching scheduler, on the CPU with a fake
+engine and a simulated clock (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_2309_09609_amd.serve import Server
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class FakeEngine:
+    """Records which chunk each request scores at each step; a step costs time
+    proportional to the number of requests in it."""
+
+    def __init__(self, clock, slot_bytes=100, step_cost=0.01):
+        self.clock, self.slot_bytes, self.step_cost = clock, slot_bytes, step_cost
+        self.log = []          # (step, rid, chunk)
+        self.steps = 0
+        self.sizes = []
+
+    def new_slot(self):
+        return object()
+
+    def step(self, reqs, chunks, nchunks):
+        assert len(set(id(r.slot) for r in reqs)) == len(reqs), "two active requests share a slot"
+        for r, c in zip(reqs, chunks):
+            self.log.append((self.steps, r.rid, c))
+        self.sizes.append(len(reqs))
+        self.steps += 1
+        self.clock.t += self.step_cost * len(reqs)
+
+    def topk(self, r):
+        return r.rid
+
+    def sync(self):
+        pass
+
+    def fetch(self, h):
+        return ("top", h)
+
+
+def run(nreq, nchunks, budget, arrivals):
+    clock = FakeClock()
+    eng = FakeEngine(clock)
+    srv = Server(eng, nchunks=nchunks, mem_budget=budget)
+    qs = [np.zeros(10 + i, np.int8) for i in range(nreq)]
+    rep = srv.run(qs, arrivals, clock=clock, sleep=clock.sleep, cells_per_query=lambda q: q.size)
+    return eng, srv, rep
+
+
+@pytest.mark.parametrize("nchunks", [1, 3, 8])
+def test_every_request_scores_every_chunk_once(nchunks):
+    arr = np.linspace(0, 0.3, 25)
+    eng, srv, rep = run(25, nchunks, 10 ** 6, arr)
+    seen = {}
+    for _, rid, c in eng.log:
+        seen.setdefault(rid, []).append(c)
+    assert sorted(seen) == list(range(25))
+    for rid, cs in seen.items():
+        assert sorted(cs) == list(range(nchunks)), rid
+    assert set(rep.results) == set(range(25))
+    assert all(rep.results[r] == ("top", r) for r in range(25))
+    assert (rep.latencies > 0).all()
+
+
+def test_admission_is_bounded_by_memory():
+    arr = np.zeros(20)                        # everything arrives at once
+    eng, srv, rep = run(20, 4, budget=350, arrivals=arr)   # 350 // 100 = 3 slots
+    assert srv.max_slots == 3
+    assert max(eng.sizes) <= 3 and rep.max_active == 3
+    assert srv.allocated == 3                 # slots are recycled, never more than the budget
+    assert set(rep.results) == set(range(20))
+    assert rep.admitted_order == list(range(20))
+
+
+def test_late_arrivals_join_requests_in_flight():
+    """Continuous batching: a request arriving while others are mid-way joins the
+    next iteration instead of waiting for them to finish."""
+    arr = np.array([0.0, 0.0, 0.015, 0.035])
+    eng, srv, rep = run(4, 8, 10 ** 6, arr)
+    first_step = {}
+    last_step = {}
+    for s, rid, _ in eng.log:
+        first_step.setdefault(rid, s)
+        last_step[rid] = s
+    assert first_step[2] > first_step[0] and first_step[2] < last_step[0]
+    assert first_step[3] < last_step[0]
+    assert max(eng.sizes) >= 3
+
+
+def test_idle_server_waits_for_arrivals():
+    arr = np.array([1.0, 5.0])
+    eng, srv, rep = run(2, 2, 10 ** 6, arr)
+    assert eng.steps == 4 and max(eng.sizes) == 1
+    assert rep.latencies.max() < 0.1
