@@ -78,7 +78,10 @@ typedef struct {
     int32_t rows_per_lane;    /* tuning: 0 = planner decides; 4, 8 or 16 query rows per lane */
     int32_t unit_share;       /* tuning: largest work unit as a fraction of one persistent wave's
                                  share of a search, in 1/1000; 0 = default (250) */
-    int32_t reserved[3];
+    int32_t lane_pack;        /* tuning, batched and multi-query forms: 0 or 1 = the two 16-bit halves
+                                 of a lane hold two subjects; 2 = they hold two queries (queries are
+                                 paired by length; a single query always uses subject pairs) */
+    int32_t reserved[2];
 } sw_pack_opts;
 
 /*

@@ -104,18 +104,18 @@ def _ptr(a) -> ctypes.c_void_p:
 class PackOpts(ctypes.Structure):
     _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
                 ("rerun_threshold", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
-                ("unit_share", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("unit_share", ctypes.c_int32), ("lane_pack", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
-               unit_share=0) -> ctypes.c_void_p:
+               unit_share=0, lane_pack=0) -> ctypes.c_void_p:
     """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
     ``force_lanes``, ``rerun_threshold`` and ``rows_per_lane`` are tuning/test hooks (see sw_pack_opts)."""
     lib = load()
     offs = _host_i64(h_offsets)
     n = offs.size - 1
     h = ctypes.c_void_p()
-    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share))
+    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack))
     _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
                           _stream(stream), ctypes.byref(h)))
     return h
@@ -167,7 +167,7 @@ class Database:
     """A packed, device-resident protein database."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
-                 rows_per_lane=0, unit_share=0):
+                 rows_per_lane=0, unit_share=0, lane_pack=0):
         import torch
         self.offsets = _host_i64(offsets)
         self.n = self.offsets.size - 1
@@ -181,7 +181,7 @@ class Database:
             d_res = torch.zeros(1, dtype=torch.int8, device=device)
         self.device = d_res.device
         self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
-                                 unit_share)
+                                 unit_share, lane_pack)
         del d_res
 
     def close(self):
@@ -206,9 +206,10 @@ class Database:
         return {"items": int(out[0]), "rerun_pairs": int(out[1]), "rows_per_lane": int(out[2]),
                 "waves": int(out[3]), "side_items": int(out[4]), "side_rows_per_lane": int(out[5])}
 
-    def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0):
+    def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0, lane_pack=0):
         """Change the handle's tuning knobs (results are identical for every setting)."""
-        opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share))
+        opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share),
+                        int(lane_pack))
         _check(load().sw_db_tune(self.handle, ctypes.byref(opts)))
 
     def profile_kernels(self, enable=True):

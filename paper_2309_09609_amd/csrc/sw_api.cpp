@@ -31,6 +31,8 @@
 namespace sw {
 hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
+hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
 hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
@@ -110,6 +112,8 @@ struct Plan {
     DevBuf items;                 // [main items..., side items...]
     int32_t n_main = 0, n_side = 0;
     int R_main = 16, R_side = 16;
+    bool qpack = false;           // items index query pairs (two queries per lane)
+    DevBuf qpairs;                // int2 per pair: (query a, query b or -1)
 };
 
 // Device pointers of the staged queries (descriptors, offsets, matrix + residues).
@@ -158,6 +162,7 @@ struct sw_db {
     // launch geometry
     int cus = 0, wg16 = 0, wg32 = 0;  // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
     int wgR[17] = {0};                // persistent workgroups per 16-bit instance, by R
+    int wgQ[17] = {0};                // persistent workgroups per query-pair instance, by R
     int64_t slot_cap = 0;             // (column x pair) capacity of one wave's boundary slot
     hipStream_t side = nullptr;       // second stream for the long pairs of short queries
     hipStream_t cap = nullptr;        // stream the batched sequence is captured on
@@ -175,6 +180,7 @@ struct sw_db {
     int force_R = 0;                  // fixed rows per lane (4, 8, 16)
     double unit_share = 0.25;         // largest unit / one wave's share of a search
     int32_t sat = kSat16;             // rerun threshold
+    int lane_pack = 1;                // 1: subject pairs per lane; 2: query pairs per lane (several queries)
     // statistics and timing
     int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
     bool timing = false;
@@ -207,11 +213,13 @@ sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
     if (opts->rerun_threshold < 0) return fail(SW_E_INVALID, "rerun_threshold must be >= 0");
     const int rpl = opts->rows_per_lane;
     if (rpl != 0 && rpl != 4 && rpl != 8 && rpl != 16) return fail(SW_E_INVALID, "rows_per_lane must be 0, 4, 8 or 16");
+    if (opts->lane_pack < 0 || opts->lane_pack > 2) return fail(SW_E_INVALID, "lane_pack must be 0, 1 or 2");
     if (opts->unit_share < 0 || opts->unit_share > 100000) return fail(SW_E_INVALID, "unit_share must be in 0..100000");
     db->force_lgB = fl ? __builtin_ctz(fl) : -1;
     db->force_R = rpl;
     db->unit_share = opts->unit_share > 0 ? opts->unit_share / 1000.0 : 0.25;
     db->sat = opts->rerun_threshold > 0 ? std::min<int32_t>(opts->rerun_threshold, kSat16) : kSat16;
+    db->lane_pack = opts->lane_pack == 2 ? 2 : 1;
     return SW_OK;
 }
 
@@ -321,15 +329,104 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
     plan->R_side = R_side;
 }
 
+// Query-pair plan: queries on the same chunk are sorted by length and paired
+// neighbour with neighbour (a leftover query runs alone in its half-empty lanes);
+// each pair sweeps max(m_a, m_b) rows.  A unit holds P = 64/B subjects and a
+// group 2B units; B is capped at 32 (the interleaved slice is twice as large).
+void plan_units_q2(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& out,
+                   std::vector<int2>& pairs, const std::vector<int>* chunk, int nchunks) {
+    const int R = db->force_R == 8 ? 8 : 16;
+    std::vector<int> order;
+    for (int q = 0; q < (int)qlens.size(); ++q)
+        if (qlens[q] > 0) order.push_back(q);
+    auto ch = [&](int q) { return chunk ? (*chunk)[q] : 0; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return ch(a) != ch(b) ? ch(a) < ch(b) : qlens[a] > qlens[b];
+    });
+    for (size_t i = 0; i < order.size();) {
+        if (i + 1 < order.size() && ch(order[i]) == ch(order[i + 1])) {
+            pairs.push_back(make_int2(order[i], order[i + 1]));
+            i += 2;
+        } else {
+            pairs.push_back(make_int2(order[i], -1));
+            i += 1;
+        }
+    }
+    auto cost = [&](int m, int nc, int lgB) {
+        const int B = 1 << lgB;
+        const int64_t passes = (m + (R << lgB) - 1) / (R << lgB);
+        return passes * round_up(nc + B - 1, 4) * (int64_t)(9 * R + 16 + (lgB ? 6 : 0));
+    };
+    const int64_t nwaves = (int64_t)db->wgQ[R] * kWaves;
+    int64_t total = 0;
+    for (const int2& pr : pairs) {
+        const int m = std::max(qlens[pr.x], pr.y >= 0 ? qlens[pr.y] : 0);
+        for (int g = ch(pr.x); g < db->ngroups; g += nchunks) total += 2 * cost(m, db->ncols[g], 0);
+    }
+    const double cap = db->unit_share * (double)total / (double)std::max<int64_t>(nwaves, 1);
+    struct Tmp { WgItem it; int64_t cost; };
+    std::vector<Tmp> items;
+    for (size_t pi = 0; pi < pairs.size(); ++pi) {
+        const int2 pr = pairs[pi];
+        const int m = std::max(qlens[pr.x], pr.y >= 0 ? qlens[pr.y] : 0);
+        const int g_first = ch(pr.x);
+        WgItem cur{0, (int32_t)pi, 0, -1, 0, nchunks};
+        int64_t cc = 0;
+        for (int g = g_first; g < db->ngroups; g += nchunks) {
+            const int nc = db->ncols[g];
+            int lgB = 0;
+            for (; lgB < 5; ++lgB)
+                if ((double)cost(m, nc, lgB) <= cap && (int64_t)nc * (kGroupPairs >> lgB) <= db->slot_cap) break;
+            if (db->force_lgB >= 0) lgB = std::min(db->force_lgB, 5);
+            while (lgB < 5 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
+            const int units = 2 << lgB;
+            const int P = kGroupPairs >> lgB;
+            const int64_t seq_g = (g - g_first) / nchunks;
+            for (int k = 0; k < units; ++k) {
+                const int64_t c = cost(m, db->pcols[(size_t)g * kGroupPairs + ((k * P) >> 1)], lgB);
+                const int64_t seq_c = (cur.g0 - g_first) / nchunks;
+                const bool contiguous = cur.count > 0 && cur.lgB == lgB &&
+                                        seq_c * units + cur.k0 + cur.count == seq_g * units + k;
+                if (cur.count == kWaves || !contiguous) {
+                    if (cur.count > 0) items.push_back({cur, cc});
+                    cur.g0 = g;
+                    cur.k0 = (int16_t)k;
+                    cur.lgB = (int8_t)lgB;
+                    cur.count = 0;
+                    cc = 0;
+                }
+                cur.count++;
+                cc = std::max(cc, c);
+            }
+        }
+        if (cur.count > 0) items.push_back({cur, cc});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; });
+    for (auto& t : items) out.push_back(t.it);
+    plan->R_main = R;
+    plan->R_side = R;
+}
+
 sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p, const std::vector<int>* chunk = nullptr,
                      int nchunks = 1) {
     std::vector<WgItem> mi, si;
-    plan_units(db, qlens, p, mi, si, chunk, nchunks);
+    std::vector<int2> pairs;
+    int nonempty = 0;
+    for (int m : qlens) nonempty += m > 0;
+    p->qpack = db->lane_pack == 2 && nonempty >= 2;
+    if (p->qpack)
+        plan_units_q2(db, qlens, p, mi, pairs, chunk, nchunks);
+    else
+        plan_units(db, qlens, p, mi, si, chunk, nchunks);
     p->n_main = (int32_t)mi.size();
     p->n_side = (int32_t)si.size();
     mi.insert(mi.end(), si.begin(), si.end());
     HIP_TRY(p->items.reserve(std::max<size_t>(mi.size(), 1) * sizeof(WgItem), &db->gen));
     if (!mi.empty()) HIP_TRY(hipMemcpy(p->items.p, mi.data(), mi.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+    if (p->qpack) {
+        HIP_TRY(p->qpairs.reserve(std::max<size_t>(pairs.size(), 1) * sizeof(int2), &db->gen));
+        if (!pairs.empty()) HIP_TRY(hipMemcpy(p->qpairs.p, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
     return SW_OK;
 }
 
@@ -351,8 +448,10 @@ void clear_caches(sw_db* db) {
     for (auto& kv : db->plans) kv.second.items.release();
     db->plans.clear();
     db->batch_plan.items.release();
+    db->batch_plan.qpairs.release();
     db->batch_plan.n_main = db->batch_plan.n_side = 0;
     db->multi_plan.items.release();
+    db->multi_plan.qpairs.release();
     db->multi_plan.n_main = db->multi_plan.n_side = 0;
     db->batch_qlens.clear();
     db->graph.clear();
@@ -378,10 +477,19 @@ sw_status ensure_workspace(sw_db* db) {
             db->wgR[R] = db->cus * std::min(b, kMaxWgPerCu);
             db->wg16 = std::max(db->wg16, db->wgR[R]);
         }
+        for (int R : {8, 16}) {
+            int b = 0;
+            HIP_TRY(sweep_occupancy_q2(R, &b));
+            if (b < 1) return fail(SW_E_HIP, "query-pair sweep (R=%d) cannot be resident", R);
+            db->wgQ[R] = db->cus * std::min(b, kMaxWgPerCu);
+            db->wg16 = std::max(db->wg16, db->wgQ[R]);
+        }
         HIP_TRY(sweep_occupancy(false, kRerunRows, &b32));
         if (b32 < 1) return fail(SW_E_HIP, "32-bit sweep cannot be resident");
         db->wg32 = kRerunGrid;
-        db->slot_cap = std::max<int64_t>(65536, db->ncols_max);
+        // a unit's boundary row is (columns x subjects-or-pairs per wave); the widest
+        // query-pair unit is 2 subjects of the longest subject's width
+        db->slot_cap = std::max<int64_t>(65536, 2 * (int64_t)db->ncols_max);
         const int64_t nw16 = (int64_t)db->wg16 * kWaves;
         const int64_t nw32 = (int64_t)db->wg32 * kWaves;
         HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4, &db->gen));
@@ -484,8 +592,9 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
     a.rerun_cap = (int32_t)rerun_cap;
     a.unit_list = 0;
     a.sat = db->sat;
+    a.qpairs = plan.qpack ? plan.qpairs.as<int2>() : nullptr;
     // the side launch takes the first slots; the bulk launch fills the rest of the GPU
-    const int wg_main = db->wgR[plan.R_main];
+    const int wg_main = plan.qpack ? db->wgQ[plan.R_main] : db->wgR[plan.R_main];
     const int grid_side = std::min(plan.n_side, std::max(1, wg_main / 8));
     const int grid_main = std::max(1, std::min(wg_main - grid_side, std::max(plan.n_main, 1)));
     if (plan.n_side > 0) {
@@ -511,7 +620,12 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
         }
         HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
     }
-    if (plan.n_main > 0) HIP_TRY(launch_sweep(true, plan.R_main, a, grid_main, st));
+    if (plan.n_main > 0) {
+        if (plan.qpack)
+            HIP_TRY(launch_sweep_q2(plan.R_main, a, grid_main, st));
+        else
+            HIP_TRY(launch_sweep(true, plan.R_main, a, grid_main, st));
+    }
     if (plan.n_side > 0) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));

@@ -72,6 +72,7 @@ struct SweepArgs {
     int32_t rerun_cap;
     int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
     int32_t sat;                  // 16-bit scores >= sat are recomputed with 32-bit cells
+    const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
 };
 
 }  // namespace sw

@@ -359,6 +359,242 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
     }
 }
 
+// ------------------------------------------------------------ query-pair sweep
+// Two queries per lane: the two halves of every packed cell are the same
+// subject against query a and query b, so a row's substitution pair is one
+// dword of a pre-interleaved profile slice and needs no permute.  A wave owns
+// P = 64/B subjects of a group (B lanes each, anti-diagonal as above); a group
+// has 2B such units.
+
+__device__ __forceinline__ uint32_t load_chunk1(const uint8_t* resp, int c, int nchunks) {
+    if (c < 0 || c >= nchunks) return 0x14141414u;
+    return *reinterpret_cast<const uint32_t*>(resp + (int64_t)c * kChunkBytes);
+}
+
+template <int R, bool COOP>
+__device__ __forceinline__ void sweep_pass_q2(const uint8_t* resp, int ncols, int lgB, int b, int s, int p, int passes,
+                                              const uint32_t* lrow, uint32_t* slot, u2 go, u2 ge, s2& S) {
+    using C = CellI16;
+    using T = s2;
+    const int B = 1 << lgB;
+    const int P = kGroupPairs >> lgB;
+    const int nchunks = ncols >> 2;
+    const int nsteps = ncols + B - 1;
+    const int nloop = (nsteps + 3) >> 2;
+    const bool first_lane = (b == 0);
+    const bool read_bnd = first_lane && p > 0;
+    const bool write_bnd = (b == B - 1) && p + 1 < passes;
+    const int cstride = P * 4 * C::kWords;
+    uint32_t* sbase = slot + s * 4 * C::kWords;
+
+    T H0[R], H1[R], E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { H0[r] = C::zero(); H1[r] = C::zero(); E[r] = C::zero(); }
+    T diag_top = C::zero();
+    T up_h = C::zero(), up_f = C::zero();
+    const int coff = COOP ? ((-b) >> 2) : 0;
+    const int csh = COOP ? ((-b) & 3) : 0;
+    uint32_t lo = load_chunk1(resp, coff, nchunks);
+    uint32_t hi = COOP ? load_chunk1(resp, coff + 1, nchunks) : 0u;
+    T bh[4], bf[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { bh[u] = C::zero(); bf[u] = C::zero(); }
+    if (read_bnd && nchunks > 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ld_words<C>(sbase + u * C::kWords, bh[u], bf[u]);
+    }
+    for (int c = 0; c < nloop; ++c) {
+        const uint32_t nhi = load_chunk1(resp, coff + c + (COOP ? 2 : 1), nchunks);
+        T nbh[4], nbf[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { nbh[u] = C::zero(); nbf[u] = C::zero(); }
+        if (read_bnd && c + 1 < nchunks) {
+            const uint32_t* w = sbase + (int64_t)(c + 1) * cstride;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ld_words<C>(w + u * C::kWords, nbh[u], nbf[u]);
+        }
+        const uint32_t rr = COOP ? __builtin_amdgcn_alignbyte(hi, lo, csh) : lo;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = 4 * c + u;
+            const int d = (rr >> (8 * u)) & 0xff;
+            uint32_t w[R];
+            if constexpr (R % 4 == 0) {
+                const uint4* q = reinterpret_cast<const uint4*>(lrow + d * R);
+#pragma unroll
+                for (int v = 0; v < R / 4; ++v) {
+                    const uint4 x = q[v];
+                    w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
+                }
+            }
+            T htop, ftop;
+            if (COOP) {
+                htop = C::sel(first_lane, bh[u], up_h);
+                ftop = C::sel(first_lane, bf[u], up_f);
+            } else {
+                htop = bh[u];
+                ftop = bf[u];
+            }
+            T* Hin = (u & 1) ? H1 : H0;
+            T* Hout = (u & 1) ? H0 : H1;
+            T diag = diag_top;
+            T F = ftop;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                T hd = C::add(diag, bits<T>(w[r]));
+                T h = C::mx(C::mx(hd, E[r]), F);
+                S = C::mx(S, hd);
+                diag = Hin[r];
+                Hout[r] = h;
+                T hgo = C::gap(h, go);
+                E[r] = C::mx(C::gap(E[r], ge), hgo);
+                F = C::mx(C::gap(F, ge), hgo);
+            }
+            diag_top = htop;
+            const T hbot = Hout[R - 1];
+            if (write_bnd) {
+                const int j = t - (B - 1);
+                if (j >= 0 && j < ncols)
+                    C::put(sbase + (int64_t)(j >> 2) * cstride + (j & 3) * C::kWords, hbot, F);
+            }
+            if (COOP) {
+                up_h = C::shift(hbot);
+                up_f = C::shift(F);
+            }
+        }
+        lo = COOP ? hi : nhi;
+        hi = nhi;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { bh[u] = nbh[u]; bf[u] = nbf[u]; }
+    }
+}
+
+// Rows [row0, row0 + B*R) of two query profiles interleaved into LDS as
+// [b][residue][R] dwords (low half query a, high half query b).  Rows past a
+// profile's stride read as padding.
+template <int R>
+__device__ __forceinline__ void load_slice_q2(uint32_t* dst, const int16_t* pa, int mpa, const int16_t* pb, int mpb,
+                                              int row0, int lgB, int tid, int nthreads) {
+    const int rows = R << lgB;
+    const int per_res = rows / 8;                       // 8-row units per residue
+    const int total = kNRes * per_res;
+    for (int e = tid; e < total; e += nthreads) {
+        const int d = e / per_res;
+        const int rem = e - d * per_res;
+        const int row = row0 + rem * 8;
+        const int bb = (rem * 8) / R;
+        const int r0 = rem * 8 - bb * R;
+        constexpr uint32_t kPad2 = (uint32_t)(uint16_t)kPadScore * 0x10001u;
+        uint4 va = make_uint4(kPad2, kPad2, kPad2, kPad2), vb = va;
+        if (row < mpa) va = *reinterpret_cast<const uint4*>(pa + (int64_t)d * mpa + row);
+        if (row < mpb) vb = *reinterpret_cast<const uint4*>(pb + (int64_t)d * mpb + row);
+        uint4 o0, o1;
+        o0.x = __builtin_amdgcn_perm(vb.x, va.x, 0x05040100u); o0.y = __builtin_amdgcn_perm(vb.x, va.x, 0x07060302u);
+        o0.z = __builtin_amdgcn_perm(vb.y, va.y, 0x05040100u); o0.w = __builtin_amdgcn_perm(vb.y, va.y, 0x07060302u);
+        o1.x = __builtin_amdgcn_perm(vb.z, va.z, 0x05040100u); o1.y = __builtin_amdgcn_perm(vb.z, va.z, 0x07060302u);
+        o1.z = __builtin_amdgcn_perm(vb.w, va.w, 0x05040100u); o1.w = __builtin_amdgcn_perm(vb.w, va.w, 0x07060302u);
+        uint4* o = reinterpret_cast<uint4*>(dst + (bb * kNRes + d) * R + r0);
+        o[0] = o0;
+        o[1] = o1;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void run_unit_q2(const SweepArgs& a, int g, int k, int lgB, int qp, bool valid,
+                                            bool shared_slice, int16_t* lds, int wave, int lane, uint32_t* slot) {
+    using T = s2;
+    const int B = 1 << lgB;
+    const int P = kGroupPairs >> lgB;                   // subjects per unit
+    const int s = lane >> lgB;
+    const int b = lane & (B - 1);
+    const int2 pr = a.qpairs[qp];
+    const QDesc Qa = a.qd[pr.x];
+    const QDesc Qb = a.qd[pr.y >= 0 ? pr.y : pr.x];
+    const int m = max(Qa.m, Qb.m);
+    const int rows_pp = R << lgB;
+    const int passes = (m + rows_pp - 1) / rows_pp;
+    GroupRec G{0, 0, 0};
+    int ncols = 0;
+    const int su = k * P + s;                           // subject within the group
+    if (valid) {
+        G = a.groups[g];
+        ncols = a.pair_cols[g * kGroupPairs + ((k * P) >> 1)];
+    }
+    const uint8_t* resp = a.image + G.base + (su >> 1) * 8 + (su & 1) * 4;
+    uint32_t* region = reinterpret_cast<uint32_t*>(shared_slice ? lds : lds + wave * (kNRes * 16 * R));
+    const uint32_t* lrow = region + b * kNRes * R;
+    const u2 go = CellI16::gapv(a.go), ge = CellI16::gapv(a.ge);
+    T S = CellI16::zero();
+    for (int p = 0; p < passes; ++p) {
+        if (shared_slice) {
+            __syncthreads();
+            load_slice_q2<R>(region, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
+                             threadIdx.x, blockDim.x);
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_wave_barrier();
+            load_slice_q2<R>(region, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
+                             lane, 64);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (valid) {
+            if (lgB == 0)
+                sweep_pass_q2<R, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+            else
+                sweep_pass_q2<R, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+    if (!valid) return;
+    for (int o = 1; o < B; o <<= 1) S = CellI16::xmax(S, o);
+    if (b == 0) {
+        const int slot0 = g * kGroupSubjects + su;
+        const int o = a.perm[slot0];
+        if (o >= 0) {
+            int32_t* outa = Qa.out ? Qa.out : a.scores + Qa.out_off;
+            outa[o] = S.x;
+            if (pr.y >= 0) {
+                int32_t* outb = Qb.out ? Qb.out : a.scores + Qb.out_off;
+                outb[o] = S.y;
+            }
+        }
+        if (a.rerun != nullptr) {
+            if (S.x >= a.sat) {
+                const int idx = atomicAdd(a.rerun_count, 1);
+                if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, pr.x, (int16_t)(su >> 1), 6, 1, 1};
+            }
+            if (pr.y >= 0 && S.y >= a.sat) {
+                const int idx = atomicAdd(a.rerun_count, 1);
+                if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, pr.y, (int16_t)(su >> 1), 6, 1, 1};
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
+    __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
+    __shared__ int s_item;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const WgItem I = a.items[it];
+        const int units = 2 << I.lgB;                   // units per group
+        int k = I.k0 + wave;
+        const int g = I.g0 + (k / units) * I.gstep;
+        k %= units;
+        const bool shared_slice = I.lgB > 3;            // more than 8 lanes per subject
+        run_unit_q2<R>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
+    }
+}
+
 // ------------------------------------------------------------ query profile
 // prof[d][i] = SM(Q[i], d) for d < 20 and i < m; kPadScore elsewhere.  One
 // staging buffer holds the 20x20 matrix followed by the query codes.
@@ -537,6 +773,26 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 // ------------------------------------------------------------ host-side launchers
 // Kernel instances: 16-bit cells with R = 4, 8, 16 rows per lane; 32-bit cells with R = 8.
+static const void* sweep_kernel_q2(int R) {
+    if (R == 8) return (const void*)k_sweep_q2<8>;
+    if (R == 16) return (const void*)k_sweep_q2<16>;
+    return nullptr;
+}
+
+hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = sweep_kernel_q2(R);
+    if (!k) return hipErrorInvalidValue;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu) {
+    const void* k = sweep_kernel_q2(R);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
+}
+
 static const void* sweep_kernel(bool i16, int R) {
     if (i16) {
         if (R == 4) return (const void*)k_sweep<CellI16, 4>;

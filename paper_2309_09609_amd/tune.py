@@ -1,8 +1,9 @@
 """Autotuner for the batched search.
 
-Tries tiling and work-splitting choices of the sweep (rows per lane, the size
-of a work unit relative to a persistent wave's share, a minimum number of
-cooperating lanes per subject pair) on a sample of the caller's batch, keeps
+Tries lane packing (two subjects or two queries in the 16-bit halves of a
+lane) and tiling and work-splitting choices of the sweep (rows per lane, the
+size of a work unit relative to a persistent wave's share, a minimum number of
+cooperating lanes per subject) on a sample of the caller's batch, keeps
 only candidates whose scores are bit-identical to the first candidate's, and
 picks the fastest.  Results are cached in a JSON file keyed by the GPU
 architecture and a bucket of the workload shape, so later runs skip the search.
@@ -15,13 +16,16 @@ import time
 
 import numpy as np
 
+# lane_pack 1: the two 16-bit halves of a lane hold two subjects; 2: two queries
 DEFAULT_CANDIDATES = [
-    dict(rows_per_lane=16, unit_share=250, force_lanes=0),
-    dict(rows_per_lane=8, unit_share=250, force_lanes=0),
-    dict(rows_per_lane=16, unit_share=1000, force_lanes=0),
-    dict(rows_per_lane=16, unit_share=100, force_lanes=0),
-    dict(rows_per_lane=16, unit_share=250, force_lanes=2),
-    dict(rows_per_lane=8, unit_share=1000, force_lanes=0),
+    dict(rows_per_lane=16, unit_share=250, force_lanes=0, lane_pack=1),
+    dict(rows_per_lane=16, unit_share=250, force_lanes=2, lane_pack=1),
+    dict(rows_per_lane=16, unit_share=100, force_lanes=2, lane_pack=1),
+    dict(rows_per_lane=8, unit_share=250, force_lanes=0, lane_pack=1),
+    dict(rows_per_lane=16, unit_share=250, force_lanes=0, lane_pack=2),
+    dict(rows_per_lane=16, unit_share=250, force_lanes=2, lane_pack=2),
+    dict(rows_per_lane=16, unit_share=100, force_lanes=2, lane_pack=2),
+    dict(rows_per_lane=8, unit_share=250, force_lanes=2, lane_pack=2),
 ]
 
 

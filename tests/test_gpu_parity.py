@@ -295,6 +295,60 @@ def test_tuning_knobs_do_not_change_results(gpu, blosum, knobs):
     D.close()
 
 
+@pytest.mark.parametrize("knobs", [dict(lane_pack=2), dict(lane_pack=2, rows_per_lane=8),
+                                   dict(lane_pack=2, force_lanes=4), dict(lane_pack=2, force_lanes=32),
+                                   dict(lane_pack=2, rerun_threshold=1)])
+def test_query_pair_packing(gpu, blosum, knobs):
+    """Two queries per lane: pairs of very different lengths, an odd leftover
+    query, an empty query, every score and top-k against the oracle."""
+    import torch
+    db = synth.small_db(seed=93, n=900, lo=0, hi=700)
+    lens = [5, 800, 130, 129, 0, 47, 1]
+    queries = [synth.small_query(seed=500 + i, m=L) for i, L in enumerate(lens)]
+    D = gpu.Database(db.residues, db.offsets, **knobs)
+    scores, ts, ti = D.search_batch(queries, blosum, 10, 2, k=10)
+    torch.cuda.synchronize()
+    S = scores.cpu().numpy()
+    for i, q in enumerate(queries):
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+        assert_equal_scores(S[i], want, f"{knobs} query {i}")
+        ws, wi = oracle.topk(want, 10)
+        assert (ts[i].cpu().numpy() == ws).all() and (ti[i].cpu().numpy() == wi).all()
+    D.close()
+
+
+def test_query_pair_packing_overflow(gpu, blosum):
+    """Saturating pairs recomputed for each query of a query pair."""
+    import torch
+    db = _overflow_db()
+    queries = [np.full(3000, 17, np.int8), np.full(2995, 17, np.int8), synth.small_query(3, 300)]
+    D = gpu.Database(db.residues, db.offsets, lane_pack=2)
+    scores, _, _ = D.search_batch(queries, blosum, 10, 2, k=0)
+    torch.cuda.synchronize()
+    for i, q in enumerate(queries):
+        assert_equal_scores(scores[i].cpu().numpy(), oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), f"q{i}")
+    assert D.stats()["rerun_pairs"] >= 4
+    D.close()
+
+
+def test_query_pair_long_subjects(gpu, blosum):
+    """Query pairs over subjects up to 35,000 residues (widest scratch slots)."""
+    import torch
+    rng = np.random.default_rng(19)
+    lens = [35000, 34000, 15000, 3000] + list(rng.integers(10, 600, 300))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    queries = [synth.small_query(seed=40 + i, m=m) for i, m in enumerate([700, 650, 90])]
+    D = gpu.Database(db.residues, db.offsets, lane_pack=2)
+    scores, _, _ = D.search_batch(queries, blosum, 10, 2, k=0)
+    torch.cuda.synchronize()
+    for i, q in enumerate(queries):
+        assert_equal_scores(scores[i].cpu().numpy(), oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), f"q{i}")
+    D.close()
+
+
 def test_invalid_residues_are_rejected(gpu, blosum):
     qs, db = synth.workload1()
     D = gpu.Database(db.residues, db.offsets)

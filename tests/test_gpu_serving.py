@@ -10,11 +10,12 @@ from inputs import synth
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("lane_pack", [1, 2])
 @pytest.mark.parametrize("nchunks", [1, 3, 7])
-def test_search_multi_covers_all_chunks(gpu, blosum, nchunks):
+def test_search_multi_covers_all_chunks(gpu, blosum, nchunks, lane_pack):
     import torch
     db = synth.small_db(seed=5 + nchunks, n=2500, lo=1, hi=700, median=250)
-    D = gpu.Database(db.residues, db.offsets)
+    D = gpu.Database(db.residues, db.offsets, lane_pack=lane_pack)
     qs = [synth.small_query(seed=s, m=m) for s, m in [(1, 33), (2, 260), (3, 1), (4, 900)]]
     outs = [torch.full((db.n,), -7, dtype=torch.int32, device="cuda") for _ in qs]
     qo = np.concatenate([[0], np.cumsum([q.size for q in qs])])
