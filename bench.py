@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
+    ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -185,9 +186,13 @@ def main():
     tuned = None
     if args.form == "batched":
         from paper_2309_09609_amd import tune as tuner
-        print("# autotuning on a sample of the batch", file=sys.stderr, flush=True)
-        tuned = tuner.tune(D, queries, sm, 10, 2, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
-                           use_cache=False, verbose=True)
+        if args.knobs:
+            D.tune(**json.loads(args.knobs))
+            tuned = {"knobs": json.loads(args.knobs)}
+        else:
+            print("# autotuning on a sample of the batch", file=sys.stderr, flush=True)
+            tuned = tuner.tune(D, queries, sm, 10, 2, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
+                               use_cache=False, verbose=True)
         print(f"# tuned: {tuned['knobs']}", file=sys.stderr, flush=True)
         top_s = torch.empty((len(queries), 10), dtype=torch.int32, device="cuda")
         top_i = torch.empty((len(queries), 10), dtype=torch.int64, device="cuda")

@@ -47,12 +47,15 @@ def _arch() -> str:
 
 
 def _sample(queries, k: int, seed: int = 0):
-    """Up to k queries spread over the length range of the batch."""
+    """Up to k queries spread over the length range of the batch, taken as k/2
+    neighbours in length order, so that pairing queries by length in the sample
+    looks like pairing them in the whole batch."""
     if len(queries) <= k:
         return list(queries)
     order = np.argsort([q.size for q in queries], kind="stable")
-    pick = order[np.linspace(0, len(order) - 1, k).round().astype(int)]
-    return [queries[i] for i in pick]
+    anchors = np.linspace(0, len(order) - 2, max(k // 2, 1)).round().astype(int)
+    pick = sorted(set(int(i) for a in anchors for i in (a, a + 1)))
+    return [queries[order[i]] for i in pick]
 
 
 def tune(db, queries, subst, gap_open=10, gap_extend=2, candidates=None, sample=8, repeats=2,
