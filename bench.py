@@ -59,6 +59,23 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(args):
+    """HBM bytes per launch of the plain 16-bit sweep from the committed PMC
+    summary, if it was taken on the kernel source as it is now (else None)."""
+    import hashlib
+    if args.form != "plain" or args.workload != "sp570k":
+        return None
+    path = os.path.join(ROOT, "profiles", "traffic_k_sweep_i16_sp570k_plain.json")
+    try:
+        d = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2309_09609_amd", "csrc", "sw_kernels.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return d.get("hbm_bytes_per_launch_avg")
+
+
 def cpu_baseline(queries, db, sm, seconds: float):
     """The oracle, as it stands, on the host cores: first query against
     consecutive blocks of subjects until about ``seconds`` of work."""
@@ -143,6 +160,8 @@ def main():
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched-compare", action="store_true",
+                    help="plain form: skip timing the batched form on the same queries")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -234,7 +253,8 @@ def main():
     achieved = CELL_OPS * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
     roof = {"bound": "alu", "achieved": round(achieved, 3) if achieved else None,
             "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s (int16 lane-ops)",
-            "frac": round(achieved * 1e12 / peak_ops, 4) if achieved else None, "traffic": None,
+            "frac": round(achieved * 1e12 / peak_ops, 4) if achieved else None,
+            "traffic": measured_traffic(args),
             "kernel": "k_sweep<CellI16>" if args.form == "plain" else "batched graph (sweeps + recompute + top-k)",
             "launches": launches,
             "avg_launch_ms": round(kernel_s * 1e3 / max(launches, 1), 3),
@@ -253,6 +273,27 @@ def main():
                   "rerun_pairs_last_call": st["rerun_pairs"], "waves": st["waves"],
                   "tuned_knobs": tuned["knobs"] if tuned else None},
     }
+    if args.form == "plain" and not args.no_batched_compare:
+        # the same queries in the batched form: one graph launch for all of them
+        from paper_2309_09609_amd import tune as tuner
+        print("# batched form on the same queries (autotuned)", file=sys.stderr, flush=True)
+        tb = tuner.tune(D, queries, sm, 10, 2, use_cache=False)
+        qcat = np.concatenate(queries)
+        qoff = np.concatenate([[0], np.cumsum(qlens)]).astype(np.int64)
+        bs = torch.empty((len(queries), db.n), dtype=torch.int32, device="cuda")
+        sw.sw_search_batch(qcat, qoff, D.handle, sm, 10, 2, 0, bs, None, None)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for _ in range(args.steps):
+            sw.sw_search_batch(qcat, qoff, D.handle, sm, 10, 2, 0, bs, None, None)
+        torch.cuda.synchronize()
+        tb1 = time.perf_counter()
+        bg = cells_step * args.steps / (tb1 - tb0) / 1e9
+        # same scores as the plain form (the last plain step left query 19's scores in `out`)
+        same = bool(torch.equal(bs[-1], out))
+        res["extra"]["batched_same_queries"] = {"gcups": round(bg, 2), "gain_vs_plain": round(bg / gcups, 3),
+                                                "ms_per_step": round((tb1 - tb0) / args.steps * 1e3, 3),
+                                                "knobs": tb["knobs"], "scores_equal_plain": same}
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(queries, db, sm, args.cpu_seconds)
