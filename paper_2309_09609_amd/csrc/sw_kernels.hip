@@ -118,6 +118,107 @@ __device__ __forceinline__ uint2 load_chunk(const uint8_t* resp, int c, int nchu
     return *reinterpret_cast<const uint2*>(resp + (int64_t)c * kChunkBytes);
 }
 
+// ------------------------------------------------------------ scheduled 16-bit rows
+// One column step of R rows of packed 16-bit cells, written as one asm block
+// whose order never lets an instruction read the result of the packed (VOP3P)
+// instruction just before it: gfx950 needs a wait state there, and the
+// compiler, whose scheduler does not model that hazard, otherwise pays it with
+// an s_nop on nearly every row.  Per row r the block interleaves the chain
+// H -> H-Go -> F' -> next H with independent work of the neighbouring rows:
+//   hd   = H[r] + SM(r+1)        next row's diagonal term, read before H[r] changes
+//   H[r] = max(t, F)             t = max(hd_r, E[r]) from the row before
+//   es   = E[r] -sat Ge
+//   hgo  = H[r] -sat Go
+//   fs   = F -sat Ge
+//   (permute of row r+2's substitution pair, subject-pair form only)
+//   t    = max(hd, E[r+1])
+//   E[r] = max(es, hgo)
+//   F    = max(fs, hgo)
+//   S    = max(S, hd)
+// This is the arithmetic of the generic row loop in sweep_pass, reordered.
+#define SWA(r) "v_pk_add_i16 %[hd], %[h" #r "], %[sm] clamp\n"
+#define SWAW(r, n) "v_pk_add_i16 %[hd], %[h" #r "], %[w" #n "] clamp\n"
+#define SWD(r) "v_pk_max_i16 %[h" #r "], %[t], %[f]\n"
+#define SWF(r) "v_pk_sub_u16 %[es], %[e" #r "], %[ge] clamp\n"
+#define SWE(r) "v_pk_sub_u16 %[hgo], %[h" #r "], %[go] clamp\n"
+#define SWH "v_pk_sub_u16 %[fs], %[f], %[ge] clamp\n"
+#define SWP(k, sel) "v_perm_b32 %[sm], %[b" #k "], %[a" #k "], %[" #sel "]\n"
+#define SWB(n) "v_pk_max_i16 %[t], %[hd], %[e" #n "]\n"
+#define SWG(r) "v_pk_max_i16 %[e" #r "], %[es], %[hgo]\n"
+#define SWI "v_pk_max_i16 %[f], %[fs], %[hgo]\n"
+#define SWC "v_pk_max_i16 %[s], %[s], %[hd]\n"
+// subject-pair form: row r's pair is perm(b[r/2], a[r/2]) with selector s0 (even r) or s1 (odd r)
+#define SW_PRO "v_perm_b32 %[sm], %[b0], %[a0], %[s0]\n" "v_pk_add_i16 %[hd], %[dt], %[sm] clamp\n" SWP(0, s1) SWB(0) SWC
+#define SW_BLK(r, n, k2, sel2) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWP(k2, sel2) SWB(n) SWG(r) SWI SWC
+#define SW_BLKN(r, n) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI SWC
+#define SW_LAST(r) SWD(r) SWF(r) SWE(r) SWH SWG(r) SWI
+// pre-packed form: row r's pair is w[r]; the prologue takes row 0's F - Ge
+#define SW_PROW "v_pk_add_i16 %[hd], %[dt], %[w0] clamp\n" SWH SWB(0) SWC
+#define SW_BLK0W SWAW(0, 1) SWD(0) SWF(0) SWE(0) SWB(1) SWG(0) SWI SWC
+#define SW_BLKW(r, n) SWAW(r, n) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI SWC
+
+#define SW_HE(i) [h##i] "+v"(H[i]), [e##i] "+v"(E[i])
+#define SW_AB(i) [a##i] "v"(pa[i]), [b##i] "v"(pb[i])
+#define SW_W(i) [w##i] "v"(w[i])
+#define SW_OUTS [s] "+v"(S), [f] "+v"(F), [hd] "=&v"(hd), [t] "=&v"(t), [hgo] "=&v"(hgo), [es] "=&v"(es), \
+                [fs] "=&v"(fs)
+#define SW_INS [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge)
+
+// Subject-pair form: pa/pb hold rows 2k, 2k+1 of subject a and of subject b.
+template <int R>
+__device__ __forceinline__ void rows16_pair(s2* H, s2* E, s2& S, s2& F, s2 diag, const uint32_t* pa,
+                                            const uint32_t* pb, u2 go, u2 ge) {
+    s2 hd, t, hgo, es, fs, sm;
+    const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
+    if constexpr (R == 16) {
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLK(2, 3, 2, s0) SW_BLK(3, 4, 2, s1)
+                SW_BLK(4, 5, 3, s0) SW_BLK(5, 6, 3, s1) SW_BLK(6, 7, 4, s0) SW_BLK(7, 8, 4, s1)
+                    SW_BLK(8, 9, 5, s0) SW_BLK(9, 10, 5, s1) SW_BLK(10, 11, 6, s0) SW_BLK(11, 12, 6, s1)
+                        SW_BLK(12, 13, 7, s0) SW_BLK(13, 14, 7, s1) SW_BLKN(14, 15) SW_LAST(15)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
+              SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS, [sm] "=&v"(sm)
+            : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5), SW_AB(6), SW_AB(7),
+              [s0] "s"(s0), [s1] "s"(s1));
+    } else if constexpr (R == 8) {
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLK(2, 3, 2, s0) SW_BLK(3, 4, 2, s1)
+                SW_BLK(4, 5, 3, s0) SW_BLK(5, 6, 3, s1) SW_BLKN(6, 7) SW_LAST(7)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS,
+              [sm] "=&v"(sm)
+            : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), [s0] "s"(s0), [s1] "s"(s1));
+    } else {
+        static_assert(R == 4, "rows per lane must be 4, 8 or 16");
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLKN(2, 3) SW_LAST(3)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS, [sm] "=&v"(sm)
+            : SW_INS, SW_AB(0), SW_AB(1), [s0] "s"(s0), [s1] "s"(s1));
+    }
+}
+
+// Pre-packed form: w[r] is row r's substitution pair.
+template <int R>
+__device__ __forceinline__ void rows16_packed(s2* H, s2* E, s2& S, s2& F, s2 diag, const uint32_t* w, u2 go,
+                                              u2 ge) {
+    s2 hd, t, hgo, es, fs;
+    if constexpr (R == 16) {
+        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_BLKW(3, 4) SW_BLKW(4, 5) SW_BLKW(5, 6) SW_BLKW(6, 7)
+                SW_BLKW(7, 8) SW_BLKW(8, 9) SW_BLKW(9, 10) SW_BLKW(10, 11) SW_BLKW(11, 12) SW_BLKW(12, 13)
+                    SW_BLKW(13, 14) SW_BLKW(14, 15) SW_LAST(15)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
+              SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS
+            : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7), SW_W(8), SW_W(9),
+              SW_W(10), SW_W(11), SW_W(12), SW_W(13), SW_W(14), SW_W(15));
+    } else if constexpr (R == 8) {
+        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_BLKW(3, 4) SW_BLKW(4, 5) SW_BLKW(5, 6) SW_BLKW(6, 7)
+                SW_LAST(7)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS
+            : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7));
+    } else {
+        static_assert(R == 4, "rows per lane must be 4, 8 or 16");
+        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_LAST(3)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS
+            : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3));
+    }
+}
+
 // ------------------------------------------------------------ one pass of one wave
 // Rows [p*B*R, (p+1)*B*R) of the query against columns [0, ncols) of the
 // wave's pairs.  `lrow` points at this lane's profile rows in LDS, laid out
@@ -140,9 +241,9 @@ __device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int l
     const int cstride = P * 4 * C::kWords;        // words per chunk row of the slot
     uint32_t* sbase = slot + s * 4 * C::kWords;
 
-    T H0[R], H1[R], E[R];
+    T H[R], E[R];      // H and E of this lane's rows at the last column done
 #pragma unroll
-    for (int r = 0; r < R; ++r) { H0[r] = C::zero(); H1[r] = C::zero(); E[r] = C::zero(); }
+    for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
     T diag_top = C::zero();          // H of the row above this lane's block, previous column
     T up_h = C::zero(), up_f = C::zero();   // values shifted in from lane b-1
 
@@ -209,23 +310,25 @@ __device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int l
                 htop = bh[u];
                 ftop = bf[u];
             }
-            T* Hin = (u & 1) ? H1 : H0;
-            T* Hout = (u & 1) ? H0 : H1;
-            T diag = diag_top;
             T F = ftop;
+            if constexpr (std::is_same<C, CellI16>::value) {
+                rows16_pair<R>(H, E, S, F, diag_top, pa, pb, go, ge);
+            } else {
+                T diag = diag_top;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                T hd = C::add(diag, C::sm(pa[r >> 1], pb[r >> 1], r));
-                T h = C::mx(C::mx(hd, E[r]), F);
-                S = C::mx(S, hd);
-                diag = Hin[r];
-                Hout[r] = h;
-                T hgo = C::gap(h, go);
-                E[r] = C::mx(C::gap(E[r], ge), hgo);
-                F = C::mx(C::gap(F, ge), hgo);
+                for (int r = 0; r < R; ++r) {
+                    T hd = C::add(diag, C::sm(pa[r >> 1], pb[r >> 1], r));
+                    T h = C::mx(C::mx(hd, E[r]), F);
+                    S = C::mx(S, hd);
+                    diag = H[r];
+                    H[r] = h;
+                    T hgo = C::gap(h, go);
+                    E[r] = C::mx(C::gap(E[r], ge), hgo);
+                    F = C::mx(C::gap(F, ge), hgo);
+                }
             }
             diag_top = htop;
-            const T hbot = Hout[R - 1];
+            const T hbot = H[R - 1];
             if (write_bnd) {
                 const int j = t - (B - 1);
                 if (j >= 0 && j < ncols)
@@ -387,9 +490,9 @@ __device__ __forceinline__ void sweep_pass_q2(const uint8_t* resp, int ncols, in
     const int cstride = P * 4 * C::kWords;
     uint32_t* sbase = slot + s * 4 * C::kWords;
 
-    T H0[R], H1[R], E[R];
+    T H[R], E[R];      // H and E of this lane's rows at the last column done
 #pragma unroll
-    for (int r = 0; r < R; ++r) { H0[r] = C::zero(); H1[r] = C::zero(); E[r] = C::zero(); }
+    for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
     T diag_top = C::zero();
     T up_h = C::zero(), up_f = C::zero();
     const int coff = COOP ? ((-b) >> 2) : 0;
@@ -435,23 +538,10 @@ __device__ __forceinline__ void sweep_pass_q2(const uint8_t* resp, int ncols, in
                 htop = bh[u];
                 ftop = bf[u];
             }
-            T* Hin = (u & 1) ? H1 : H0;
-            T* Hout = (u & 1) ? H0 : H1;
-            T diag = diag_top;
             T F = ftop;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                T hd = C::add(diag, bits<T>(w[r]));
-                T h = C::mx(C::mx(hd, E[r]), F);
-                S = C::mx(S, hd);
-                diag = Hin[r];
-                Hout[r] = h;
-                T hgo = C::gap(h, go);
-                E[r] = C::mx(C::gap(E[r], ge), hgo);
-                F = C::mx(C::gap(F, ge), hgo);
-            }
+            rows16_packed<R>(H, E, S, F, diag_top, w, go, ge);
             diag_top = htop;
-            const T hbot = Hout[R - 1];
+            const T hbot = H[R - 1];
             if (write_bnd) {
                 const int j = t - (B - 1);
                 if (j >= 0 && j < ncols)
