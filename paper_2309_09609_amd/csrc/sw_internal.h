@@ -6,8 +6,8 @@
 namespace sw {
 
 // ---------------------------------------------------------------- constants
-constexpr int kNRes = 21;          // 20 residues + one padding row in the profile
-constexpr int kPadCode = 20;       // residue code used for padding columns
+constexpr int kNRes = 21;          // profile rows: padding (image code 0) and the 20 residues (codes 1..20)
+constexpr int kPadCode = 0;        // image byte of padding columns (residue codes are stored + 1)
 constexpr int16_t kPadScore = -1024;   // substitution score of padding (any value <= 0 is invisible)
 constexpr int kGroupPairs = 64;    // subject pairs per group (one per lane of a wave)
 constexpr int kGroupSubjects = 2 * kGroupPairs;
@@ -17,12 +17,12 @@ constexpr int kWaves = 4;          // waves per workgroup of the sweep kernel
 constexpr int kRowsMax = 16;       // most query rows per lane (R) of any sweep instance
 constexpr int kSliceRows = 1024;   // largest rows-per-pass (B*R) kept in LDS: 64 lanes x 16 rows
 constexpr int kProfRowAlign = 1024;    // profile row stride is a multiple of this (covers every B*R)
-constexpr int16_t kSat16 = 32767;  // 16-bit saturation value: a score equal to it is recomputed in 32 bits
+constexpr int16_t kSat16 = 0x7C00; // 16-bit scores at or above this are recomputed in 32 bits
 
 // Packed database image, one record per group of 128 length-sorted subjects.
 // Residues of group g live at image + base, as chunk rows of kChunkBytes bytes:
-// byte (chunk c, pair p, half h, k) = residue (4c + k) of subject 2p + h of the group,
-// or kPadCode past the subject's end.  Columns are padded to a multiple of 4.
+// byte (chunk c, pair p, half h, k) = 1 + residue (4c + k) of subject 2p + h of the group,
+// or kPadCode (0) past the subject's end.  Columns are padded to a multiple of 4.
 struct GroupRec {
     int64_t base;     // byte offset of the group's first chunk row
     int32_t ncols;    // padded column count (multiple of 4) = longest subject of the group, rounded up

@@ -6,27 +6,32 @@
 //   E[i][j] = max(H[i][j-1] - Go, E[i][j-1] - Ge)
 //   F[i][j] = max(H[i-1][j] - Go, F[i-1][j] - Ge)
 //
-// Sweep decomposition.  A wave owns P = 64/B subject pairs of one length-sorted
-// group; B lanes cooperate on each pair.  Lane b of a pair owns R query rows
-// of every pass (a pass covers B*R consecutive rows) and, at step t, updates
-// column j = t - b of both subjects of its pair: the B lanes form an
-// anti-diagonal wavefront across the matrix (intra-task parallelism, Sec. II-B)
-// while the P pairs of the wave are independent matrices (inter-task
-// parallelism).  B = 1 is the pure inter-task sweep; B = 64 puts a whole wave
-// on one pair.  The bottom row of lane b (H and F at each column) reaches
-// lane b+1 one step later through a DPP wave shift; between passes it goes
-// through a per-wave scratch slot in global memory.
+// Sweep decomposition.  A wave owns P = 64/B lanes' worth of subjects of one
+// length-sorted group; B lanes cooperate on each.  Lane b owns R query rows of
+// every pass (a pass covers B*R consecutive rows) and, at step t, updates
+// column j = t - b: the B lanes form an anti-diagonal wavefront across the
+// matrix (intra-task parallelism, Sec. II-B) while the P lane groups of the
+// wave are independent matrices (inter-task parallelism).  B = 1 is the pure
+// inter-task sweep; B = 64 puts a whole wave on one matrix.  The bottom row of
+// lane b (H and F at each column) reaches lane b+1 one step later through a
+// DPP wave shift; between passes it goes through a per-wave scratch slot.
+//
+// The two 16-bit halves of a lane hold either two subjects of the group
+// against one query (subject pairs) or one subject against two queries (query
+// pairs).  Image bytes are residue code + 1, 0 for padding, so that buffer
+// loads outside a group (which return zeros) read padding.
 //
 // Cell arithmetic.  Per cell the kernel keeps E already advanced to the next
 // column and F to the next row, so H - Go is computed once and shared:
-//   hd = Hdiag + SM;  H = max(hd, E, F);  S = max(S, hd)
+//   hd = Hdiag + SM;  H = max(hd, E, F);  S = max(S, H)
 //   hgo = max(H - Go, 0);  E' = max(E - Ge, hgo);  F' = max(F - Ge, hgo)
-// Flooring E and F at zero leaves every H unchanged (H >= 0 already), and
-// S = max(S, hd) equals max(S, H) because E and F never exceed an earlier H.
-// The 16-bit form packs the two subjects of a pair into one VGPR and uses
-// saturating v_pk_add_i16 / v_pk_sub_u16 / v_pk_max_i16: a clamped sum forces
-// the cell, hence S, to 32767, so any S < 32767 is exact and S = 32767 sends
-// the pair to the 32-bit sweep.
+// Flooring E and F at zero leaves every H unchanged (H >= 0 already).  The
+// 16-bit form uses saturating v_pk_add_i16 / v_pk_sub_u16 / v_pk_max_i16, and
+// folds two rows' H into S with one v_pk_maximum3_f16: H >= 0, and non-negative
+// 16-bit integers below 0x7C00 order like the half floats with the same bits,
+// while 0x7C00 and above are infinity or NaN, which the maximum propagates.
+// So S < kSat16 (0x7C00) is exact (no H reached it, so no sum was clamped), and
+// S >= kSat16 sends the pair to the 32-bit sweep.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -37,19 +42,49 @@ namespace sw {
 
 typedef short s2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <class To, class From>
 __device__ __forceinline__ To bits(From v) { return __builtin_bit_cast(To, v); }
 
 __device__ __forceinline__ uint32_t shr1(uint32_t v) {
-    // lane l receives lane l-1's value, lane 0 receives 0 (DPP wave_shr:1)
-    return __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xf, 0xf, false);
+    // lane l receives lane l-1's value (DPP wave_shr:1); lane 0 receives 0
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
+}
+
+// ------------------------------------------------------------ buffer access
+// Raw buffer resource over [base, base + bytes).  A load at an offset outside
+// the range returns zeros and a store there is dropped; the sweep relies on it
+// for padding columns, the zero border of a first pass and lanes with nothing
+// to read or write.  Offsets are formed in the 32-bit per-lane operand, where
+// a negative value wraps to a large one and is out of range too.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kNoAccess = 0x80000000u;   // beyond every buffer range used here (all < 2 GiB)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    // every argument is wave-uniform; say so, or the compiler loops over lanes around each access
+    const uint64_t p = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p), hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    void* q = (void*)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+__device__ __forceinline__ uint32_t ld32(rsrc_t r, uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+__device__ __forceinline__ uint2 ld64(rsrc_t r, uint32_t off) { return bits<uint2>(__builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0)); }
+__device__ __forceinline__ uint4 ld128(rsrc_t r, uint32_t off) { return bits<uint4>(__builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0)); }
+__device__ __forceinline__ void st64(rsrc_t r, uint32_t off, uint32_t x, uint32_t y) {
+    __builtin_amdgcn_raw_buffer_store_b64(v2u{x, y}, r, off, 0, 0);
+}
+__device__ __forceinline__ void st128(rsrc_t r, uint32_t off, uint4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(bits<v4u>(v), r, off, 0, 0);
 }
 
 // ------------------------------------------------------------ cell policies
+// Boundary words of one column: H then F (two packed dwords in 16 bits, four
+// dwords Ha, Hb, Fa, Fb in 32 bits).
 struct CellI16 {
     using T = s2;
-    static constexpr int kWords = 2;           // boundary words per (column, pair): H, F
+    static constexpr int kWords = 2;
     __device__ static T zero() { return T{0, 0}; }
     __device__ static T sm(uint32_t pa, uint32_t pb, int r) {
         // row r of subject a (low half) and of subject b (high half)
@@ -58,14 +93,22 @@ struct CellI16 {
     __device__ static T add(T d, T s) { return __builtin_elementwise_add_sat(d, s); }
     __device__ static T gap(T x, u2 g) { return bits<T>(__builtin_elementwise_sub_sat(bits<u2>(x), g)); }
     __device__ static T mx(T a, T b) { return __builtin_elementwise_max(a, b); }
-    __device__ static void put(uint32_t* w, T h, T f) { *reinterpret_cast<uint2*>(w) = make_uint2(bits<uint32_t>(h), bits<uint32_t>(f)); }
+    // column u (0..3) of a 4-column boundary record
+    __device__ static void col(const uint4* w, int u, T& h, T& f) {
+        const uint4 v = w[u >> 1];
+        h = bits<T>((u & 1) ? v.z : v.x);
+        f = bits<T>((u & 1) ? v.w : v.y);
+    }
+    __device__ static void put(rsrc_t r, uint32_t off, T h, T f) { st64(r, off, bits<uint32_t>(h), bits<uint32_t>(f)); }
     __device__ static T shift(T v) { return bits<T>(shr1(bits<uint32_t>(v))); }
     __device__ static T sel(bool c, T a, T b) { return c ? a : b; }
+    // S halves are compared as unsigned 16-bit patterns (see the header comment)
     __device__ static T xmax(T v, int mask) {
-        return mx(v, bits<T>(__shfl_xor(bits<int>(v), mask, 64)));
+        const u2 o = bits<u2>(__shfl_xor(bits<int>(v), mask, 64));
+        return bits<T>(__builtin_elementwise_max(bits<u2>(v), o));
     }
-    __device__ static int lo(T v) { return v.x; }
-    __device__ static int hi(T v) { return v.y; }
+    __device__ static int lo(T v) { return (int)(unsigned short)v.x; }
+    __device__ static int hi(T v) { return (int)(unsigned short)v.y; }
     using G = u2;
     __device__ static G gapv(int g) { unsigned short c = (unsigned short)(g > 65535 ? 65535 : g); return G{c, c}; }
 };
@@ -74,7 +117,7 @@ struct I2 { int x, y; };
 
 struct CellI32 {
     using T = I2;
-    static constexpr int kWords = 4;           // Ha, Hb, Fa, Fb
+    static constexpr int kWords = 4;
     __device__ static T zero() { return T{0, 0}; }
     __device__ static T sm(uint32_t pa, uint32_t pb, int r) {
         if (r & 1) return T{(int)pa >> 16, (int)pb >> 16};
@@ -84,8 +127,13 @@ struct CellI32 {
     __device__ static int g1(int x, unsigned g) { return (int)__builtin_elementwise_sub_sat((unsigned)x, g); }
     __device__ static T gap(T x, unsigned g) { return T{g1(x.x, g), g1(x.y, g)}; }
     __device__ static T mx(T a, T b) { return T{max(a.x, b.x), max(a.y, b.y)}; }
-    __device__ static void put(uint32_t* w, T h, T f) {
-        *reinterpret_cast<uint4*>(w) = make_uint4((uint32_t)h.x, (uint32_t)h.y, (uint32_t)f.x, (uint32_t)f.y);
+    __device__ static void col(const uint4* w, int u, T& h, T& f) {
+        const uint4 v = w[u];
+        h = T{(int)v.x, (int)v.y};
+        f = T{(int)v.z, (int)v.w};
+    }
+    __device__ static void put(rsrc_t r, uint32_t off, T h, T f) {
+        st128(r, off, make_uint4((uint32_t)h.x, (uint32_t)h.y, (uint32_t)f.x, (uint32_t)f.y));
     }
     __device__ static T shift(T v) { return T{(int)shr1((uint32_t)v.x), (int)shr1((uint32_t)v.y)}; }
     __device__ static T sel(bool c, T a, T b) { return c ? a : b; }
@@ -97,26 +145,6 @@ struct CellI32 {
     using G = unsigned;
     __device__ static G gapv(int g) { return (unsigned)g; }
 };
-
-template <class C>
-__device__ __forceinline__ void ld_words(const uint32_t* p, typename C::T& h, typename C::T& f);
-template <>
-__device__ __forceinline__ void ld_words<CellI16>(const uint32_t* p, s2& h, s2& f) {
-    uint2 v = *reinterpret_cast<const uint2*>(p);
-    h = bits<s2>(v.x);
-    f = bits<s2>(v.y);
-}
-template <>
-__device__ __forceinline__ void ld_words<CellI32>(const uint32_t* p, I2& h, I2& f) {
-    uint4 v = *reinterpret_cast<const uint4*>(p);
-    h = I2{(int)v.x, (int)v.y};
-    f = I2{(int)v.z, (int)v.w};
-}
-
-__device__ __forceinline__ uint2 load_chunk(const uint8_t* resp, int c, int nchunks) {
-    if (c < 0 || c >= nchunks) return make_uint2(0x14141414u, 0x14141414u);
-    return *reinterpret_cast<const uint2*>(resp + (int64_t)c * kChunkBytes);
-}
 
 // ------------------------------------------------------------ scheduled 16-bit rows
 // One column step of R rows of packed 16-bit cells, written as one asm block
@@ -134,7 +162,7 @@ __device__ __forceinline__ uint2 load_chunk(const uint8_t* resp, int c, int nchu
 //   t    = max(hd, E[r+1])
 //   E[r] = max(es, hgo)
 //   F    = max(fs, hgo)
-//   S    = max(S, hd)
+//   S    = maximum3(S, H[r-1], H[r])   after every odd row
 // This is the arithmetic of the generic row loop in sweep_pass, reordered.
 #define SWA(r) "v_pk_add_i16 %[hd], %[h" #r "], %[sm] clamp\n"
 #define SWAW(r, n) "v_pk_add_i16 %[hd], %[h" #r "], %[w" #n "] clamp\n"
@@ -146,16 +174,19 @@ __device__ __forceinline__ uint2 load_chunk(const uint8_t* resp, int c, int nchu
 #define SWB(n) "v_pk_max_i16 %[t], %[hd], %[e" #n "]\n"
 #define SWG(r) "v_pk_max_i16 %[e" #r "], %[es], %[hgo]\n"
 #define SWI "v_pk_max_i16 %[f], %[fs], %[hgo]\n"
-#define SWC "v_pk_max_i16 %[s], %[s], %[hd]\n"
+#define SWM(a, b) "v_pk_maximum3_f16 %[s], %[s], %[h" #a "], %[h" #b "]\n"
 // subject-pair form: row r's pair is perm(b[r/2], a[r/2]) with selector s0 (even r) or s1 (odd r)
-#define SW_PRO "v_perm_b32 %[sm], %[b0], %[a0], %[s0]\n" "v_pk_add_i16 %[hd], %[dt], %[sm] clamp\n" SWP(0, s1) SWB(0) SWC
-#define SW_BLK(r, n, k2, sel2) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWP(k2, sel2) SWB(n) SWG(r) SWI SWC
-#define SW_BLKN(r, n) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI SWC
-#define SW_LAST(r) SWD(r) SWF(r) SWE(r) SWH SWG(r) SWI
+#define SW_PRO "v_perm_b32 %[sm], %[b0], %[a0], %[s0]\n" "v_pk_add_i16 %[hd], %[dt], %[sm] clamp\n" SWP(0, s1) SWB(0)
+#define SW_BLK(r, n, k2, sel2) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWP(k2, sel2) SWB(n) SWG(r) SWI
+#define SW_BLKS(r, n, k2, sel2, rp) SW_BLK(r, n, k2, sel2) SWM(rp, r)
+#define SW_BLKN(r, n) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI
+// the last row starts with E[r] - Ge, as the block before it ends with the write of F
+#define SW_LAST(r, rp) SWF(r) SWD(r) SWH SWE(r) SWM(rp, r) SWG(r) SWI
 // pre-packed form: row r's pair is w[r]; the prologue takes row 0's F - Ge
-#define SW_PROW "v_pk_add_i16 %[hd], %[dt], %[w0] clamp\n" SWH SWB(0) SWC
-#define SW_BLK0W SWAW(0, 1) SWD(0) SWF(0) SWE(0) SWB(1) SWG(0) SWI SWC
-#define SW_BLKW(r, n) SWAW(r, n) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI SWC
+#define SW_PROW "v_pk_add_i16 %[hd], %[dt], %[w0] clamp\n" SWH SWB(0)
+#define SW_BLK0W SWAW(0, 1) SWD(0) SWF(0) SWE(0) SWB(1) SWG(0) SWI
+#define SW_BLKW(r, n) SWAW(r, n) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI
+#define SW_BLKWS(r, n, rp) SW_BLKW(r, n) SWM(rp, r)
 
 #define SW_HE(i) [h##i] "+v"(H[i]), [e##i] "+v"(E[i])
 #define SW_AB(i) [a##i] "v"(pa[i]), [b##i] "v"(pb[i])
@@ -171,23 +202,23 @@ __device__ __forceinline__ void rows16_pair(s2* H, s2* E, s2& S, s2& F, s2 diag,
     s2 hd, t, hgo, es, fs, sm;
     const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
     if constexpr (R == 16) {
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLK(2, 3, 2, s0) SW_BLK(3, 4, 2, s1)
-                SW_BLK(4, 5, 3, s0) SW_BLK(5, 6, 3, s1) SW_BLK(6, 7, 4, s0) SW_BLK(7, 8, 4, s1)
-                    SW_BLK(8, 9, 5, s0) SW_BLK(9, 10, 5, s1) SW_BLK(10, 11, 6, s0) SW_BLK(11, 12, 6, s1)
-                        SW_BLK(12, 13, 7, s0) SW_BLK(13, 14, 7, s1) SW_BLKN(14, 15) SW_LAST(15)
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLK(2, 3, 2, s0) SW_BLKS(3, 4, 2, s1, 2)
+                SW_BLK(4, 5, 3, s0) SW_BLKS(5, 6, 3, s1, 4) SW_BLK(6, 7, 4, s0) SW_BLKS(7, 8, 4, s1, 6)
+                    SW_BLK(8, 9, 5, s0) SW_BLKS(9, 10, 5, s1, 8) SW_BLK(10, 11, 6, s0) SW_BLKS(11, 12, 6, s1, 10)
+                        SW_BLK(12, 13, 7, s0) SW_BLKS(13, 14, 7, s1, 12) SW_BLKN(14, 15) SW_LAST(15, 14)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
               SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS, [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5), SW_AB(6), SW_AB(7),
               [s0] "s"(s0), [s1] "s"(s1));
     } else if constexpr (R == 8) {
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLK(2, 3, 2, s0) SW_BLK(3, 4, 2, s1)
-                SW_BLK(4, 5, 3, s0) SW_BLK(5, 6, 3, s1) SW_BLKN(6, 7) SW_LAST(7)
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLK(2, 3, 2, s0) SW_BLKS(3, 4, 2, s1, 2)
+                SW_BLK(4, 5, 3, s0) SW_BLKS(5, 6, 3, s1, 4) SW_BLKN(6, 7) SW_LAST(7, 6)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS,
               [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), [s0] "s"(s0), [s1] "s"(s1));
     } else {
         static_assert(R == 4, "rows per lane must be 4, 8 or 16");
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLK(1, 2, 1, s1) SW_BLKN(2, 3) SW_LAST(3)
+        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLKN(2, 3) SW_LAST(3, 2)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS, [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), [s0] "s"(s0), [s1] "s"(s1));
     }
@@ -199,151 +230,178 @@ __device__ __forceinline__ void rows16_packed(s2* H, s2* E, s2& S, s2& F, s2 dia
                                               u2 ge) {
     s2 hd, t, hgo, es, fs;
     if constexpr (R == 16) {
-        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_BLKW(3, 4) SW_BLKW(4, 5) SW_BLKW(5, 6) SW_BLKW(6, 7)
-                SW_BLKW(7, 8) SW_BLKW(8, 9) SW_BLKW(9, 10) SW_BLKW(10, 11) SW_BLKW(11, 12) SW_BLKW(12, 13)
-                    SW_BLKW(13, 14) SW_BLKW(14, 15) SW_LAST(15)
+        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_BLKWS(3, 4, 2) SW_BLKW(4, 5) SW_BLKWS(5, 6, 4)
+                SW_BLKW(6, 7) SW_BLKWS(7, 8, 6) SW_BLKW(8, 9) SW_BLKWS(9, 10, 8) SW_BLKW(10, 11)
+                    SW_BLKWS(11, 12, 10) SW_BLKW(12, 13) SW_BLKWS(13, 14, 12) SW_BLKW(14, 15) SW_LAST(15, 14)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
               SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7), SW_W(8), SW_W(9),
               SW_W(10), SW_W(11), SW_W(12), SW_W(13), SW_W(14), SW_W(15));
     } else if constexpr (R == 8) {
-        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_BLKW(3, 4) SW_BLKW(4, 5) SW_BLKW(5, 6) SW_BLKW(6, 7)
-                SW_LAST(7)
+        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_BLKWS(3, 4, 2) SW_BLKW(4, 5) SW_BLKWS(5, 6, 4)
+                SW_BLKW(6, 7) SW_LAST(7, 6)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7));
     } else {
         static_assert(R == 4, "rows per lane must be 4, 8 or 16");
-        asm(SW_PROW SW_BLK0W SW_BLKW(1, 2) SW_BLKW(2, 3) SW_LAST(3)
+        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_LAST(3, 2)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3));
     }
 }
 
 // ------------------------------------------------------------ one pass of one wave
-// Rows [p*B*R, (p+1)*B*R) of the query against columns [0, ncols) of the
-// wave's pairs.  `lrow` points at this lane's profile rows in LDS, laid out
-// [residue][R] (int16).  State lives in registers; only the boundary row
-// between passes touches memory.
-template <class C, int R, bool COOP>
-__device__ __forceinline__ void sweep_pass(const uint8_t* resp, int ncols, int lgB, int b, int s, int p,
-                                           int passes, const int16_t* lrow, uint32_t* slot,
+// Where a pass reads and writes.  The image resource covers the group's chunk
+// rows; the boundary resource covers the wave's slot for this unit, laid out
+// [chunk][lane group][4 columns][kWords], exactly nchunks chunks long, so that
+// columns at or past the unit's width read as zero and are never written.
+struct PassIO {
+    rsrc_t img;
+    uint32_t img_lane;     // byte offset of this lane's residues within a chunk row
+    rsrc_t bnd;
+    uint32_t rd_lane;      // byte offset of this lane group's boundary words in a chunk, or kNoAccess
+    uint32_t wr_lane;      // same for the writing lane, or kNoAccess
+    uint32_t cstride;      // boundary bytes per chunk (all lane groups)
+};
+
+// Residues of 4 columns: two subjects (x: a, y: b) or one.
+template <bool PACKED> struct Res;
+template <> struct Res<false> {
+    using V = uint2;
+    __device__ static V load(rsrc_t r, uint32_t off) { return ld64(r, off); }
+    __device__ static V align(V hi, V lo, int sh) {
+        return make_uint2(__builtin_amdgcn_alignbyte(hi.x, lo.x, sh), __builtin_amdgcn_alignbyte(hi.y, lo.y, sh));
+    }
+};
+template <> struct Res<true> {
+    using V = uint32_t;
+    __device__ static V load(rsrc_t r, uint32_t off) { return ld32(r, off); }
+    __device__ static V align(V hi, V lo, int sh) { return __builtin_amdgcn_alignbyte(hi, lo, sh); }
+};
+
+// Profile values of one step (R dwords): subject pairs read R int16 of each
+// subject ([residue][R] int16 slice), query pairs read R dwords of their one
+// residue ([residue][R] dword slice, halves already interleaved).
+template <int R, bool PACKED>
+__device__ __forceinline__ void fetch(const int16_t* lrow, typename Res<PACKED>::V rr, int u, uint32_t* out) {
+    if constexpr (PACKED) {
+        const int d = (rr >> (8 * u)) & 0xff;
+        const uint4* q = reinterpret_cast<const uint4*>(reinterpret_cast<const uint32_t*>(lrow) + d * R);
+#pragma unroll
+        for (int v = 0; v < R / 4; ++v) {
+            const uint4 x = q[v];
+            out[4 * v] = x.x; out[4 * v + 1] = x.y; out[4 * v + 2] = x.z; out[4 * v + 3] = x.w;
+        }
+    } else {
+        const int da = (rr.x >> (8 * u)) & 0xff;
+        const int db = (rr.y >> (8 * u)) & 0xff;
+        if constexpr (R % 8 == 0) {
+            const uint4* qa = reinterpret_cast<const uint4*>(lrow + da * R);
+            const uint4* qb = reinterpret_cast<const uint4*>(lrow + db * R);
+#pragma unroll
+            for (int v = 0; v < R / 8; ++v) {
+                const uint4 x = qa[v], y = qb[v];
+                out[4 * v] = x.x; out[4 * v + 1] = x.y; out[4 * v + 2] = x.z; out[4 * v + 3] = x.w;
+                out[R / 2 + 4 * v] = y.x; out[R / 2 + 4 * v + 1] = y.y;
+                out[R / 2 + 4 * v + 2] = y.z; out[R / 2 + 4 * v + 3] = y.w;
+            }
+        } else {
+            static_assert(R == 4, "rows per lane must be 4 or a multiple of 8");
+            const uint2 x = *reinterpret_cast<const uint2*>(lrow + da * R);
+            const uint2 y = *reinterpret_cast<const uint2*>(lrow + db * R);
+            out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
+        }
+    }
+}
+
+// Rows [p*B*R, (p+1)*B*R) of the query (or of both queries) against columns
+// [0, ncols) of the lane's matrices.  `lrow` points at this lane's profile
+// rows in LDS.  H, E, F live in registers; the boundary row between passes
+// goes through the slot.  Profile values of the next step are read from LDS
+// while the current step computes; residues are read two chunks ahead.
+template <class C, int R, bool COOP, bool PACKED>
+__device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, int b, const int16_t* lrow,
                                            typename C::G go, typename C::G ge, typename C::T& S) {
     using T = typename C::T;
-    const int B = 1 << lgB;
-    const int P = kGroupPairs >> lgB;
-    const int nchunks = ncols >> 2;
+    using RV = typename Res<PACKED>::V;
+    constexpr int W = C::kWords;
     const int nsteps = ncols + B - 1;
     const int nloop = (nsteps + 3) >> 2;
     const bool first_lane = (b == 0);
-    const bool last_lane = (b == B - 1);
-    const bool read_bnd = first_lane && p > 0;
-    const bool write_bnd = last_lane && p + 1 < passes;
-    const int cstride = P * 4 * C::kWords;        // words per chunk row of the slot
-    uint32_t* sbase = slot + s * 4 * C::kWords;
 
     T H[R], E[R];      // H and E of this lane's rows at the last column done
 #pragma unroll
     for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
-    T diag_top = C::zero();          // H of the row above this lane's block, previous column
-    T up_h = C::zero(), up_f = C::zero();   // values shifted in from lane b-1
+    T diag = C::zero();          // H of the row above this lane's block, previous column
+    T up_h = C::zero(), up_f = C::zero();   // bottom row of lane b-1, one column back
 
-    // residue stream: this lane works on columns 4c - b .. 4c - b + 3 during loop iteration c
+    // lane b works on columns 4c - b .. 4c - b + 3 during iteration c
     const int coff = COOP ? ((-b) >> 2) : 0;      // floor((-b)/4)
     const int csh = COOP ? ((-b) & 3) : 0;
-    uint2 lo = load_chunk(resp, coff, nchunks);
-    uint2 hi = COOP ? load_chunk(resp, coff + 1, nchunks) : make_uint2(0, 0);
-    // boundary stream (first lane of a pair, passes after the first)
-    T bh[4], bf[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { bh[u] = C::zero(); bf[u] = C::zero(); }
-    if (read_bnd && nchunks > 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) ld_words<C>(sbase + u * C::kWords, bh[u], bf[u]);
-    }
+    auto res_at = [&](int c) { return Res<PACKED>::load(io.img, io.img_lane + (uint32_t)(c * kChunkBytes)); };
+    auto resid = [&](RV lo, RV hi) { return COOP ? Res<PACKED>::align(hi, lo, csh) : lo; };
+    RV c0 = res_at(coff), c1 = res_at(coff + 1), c2 = res_at(coff + 2);
 
+    uint4 bw[W];                 // boundary words of the current 4 columns (first lane of a pass > 0)
+#pragma unroll
+    for (int i = 0; i < W; ++i) bw[i] = ld128(io.bnd, io.rd_lane + 16u * i);
+
+    RV rr = resid(c0, c1);
+    uint32_t cur[R];
+    fetch<R, PACKED>(lrow, rr, 0, cur);
     for (int c = 0; c < nloop; ++c) {
-        // prefetch next chunk of residues and boundary values
-        uint2 nhi = load_chunk(resp, coff + c + (COOP ? 2 : 1), nchunks);
-        T nbh[4], nbf[4];
+        const RV c3 = res_at(coff + c + 3);
+        uint4 nw[W];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { nbh[u] = C::zero(); nbf[u] = C::zero(); }
-        if (read_bnd && c + 1 < nchunks) {
-            const uint32_t* w = sbase + (int64_t)(c + 1) * cstride;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ld_words<C>(w + u * C::kWords, nbh[u], nbf[u]);
-        }
-        uint32_t ra, rb;
-        if (COOP) {
-            ra = __builtin_amdgcn_alignbyte(hi.x, lo.x, csh);
-            rb = __builtin_amdgcn_alignbyte(hi.y, lo.y, csh);
-        } else {
-            ra = lo.x;
-            rb = lo.y;
-        }
+        for (int i = 0; i < W; ++i) nw[i] = ld128(io.bnd, io.rd_lane + (uint32_t)(c + 1) * io.cstride + 16u * i);
+        const RV rn = resid(c1, c2);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int t = 4 * c + u;
-            const int da = (ra >> (8 * u)) & 0xff;
-            const int db = (rb >> (8 * u)) & 0xff;
-            uint32_t pa[R / 2], pb[R / 2];
-            if constexpr (R % 8 == 0) {
-                const uint4* qa = reinterpret_cast<const uint4*>(lrow + da * R);
-                const uint4* qb = reinterpret_cast<const uint4*>(lrow + db * R);
-#pragma unroll
-                for (int v = 0; v < R / 8; ++v) {
-                    uint4 x = qa[v], y = qb[v];
-                    pa[4 * v] = x.x; pa[4 * v + 1] = x.y; pa[4 * v + 2] = x.z; pa[4 * v + 3] = x.w;
-                    pb[4 * v] = y.x; pb[4 * v + 1] = y.y; pb[4 * v + 2] = y.z; pb[4 * v + 3] = y.w;
-                }
-            } else {
-                static_assert(R == 4, "rows per lane must be 4 or a multiple of 8");
-                const uint2 x = *reinterpret_cast<const uint2*>(lrow + da * R);
-                const uint2 y = *reinterpret_cast<const uint2*>(lrow + db * R);
-                pa[0] = x.x; pa[1] = x.y;
-                pb[0] = y.x; pb[1] = y.y;
-            }
+            uint32_t nxt[R];
+            if (u < 3) fetch<R, PACKED>(lrow, rr, u + 1, nxt);
+            else fetch<R, PACKED>(lrow, rn, 0, nxt);
             T htop, ftop;
+            C::col(bw, u, htop, ftop);
             if (COOP) {
-                htop = C::sel(first_lane, bh[u], up_h);
-                ftop = C::sel(first_lane, bf[u], up_f);
-            } else {
-                htop = bh[u];
-                ftop = bf[u];
+                htop = C::sel(first_lane, htop, up_h);
+                ftop = C::sel(first_lane, ftop, up_f);
             }
             T F = ftop;
             if constexpr (std::is_same<C, CellI16>::value) {
-                rows16_pair<R>(H, E, S, F, diag_top, pa, pb, go, ge);
+                if constexpr (PACKED) rows16_packed<R>(H, E, S, F, diag, cur, go, ge);
+                else rows16_pair<R>(H, E, S, F, diag, cur, cur + R / 2, go, ge);
             } else {
-                T diag = diag_top;
+                T dg = diag;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    T hd = C::add(diag, C::sm(pa[r >> 1], pb[r >> 1], r));
+                    T hd = C::add(dg, C::sm(cur[r >> 1], cur[R / 2 + (r >> 1)], r));
                     T h = C::mx(C::mx(hd, E[r]), F);
-                    S = C::mx(S, hd);
-                    diag = H[r];
+                    S = C::mx(S, h);
+                    dg = H[r];
                     H[r] = h;
                     T hgo = C::gap(h, go);
                     E[r] = C::mx(C::gap(E[r], ge), hgo);
                     F = C::mx(C::gap(F, ge), hgo);
                 }
             }
-            diag_top = htop;
+            diag = htop;
             const T hbot = H[R - 1];
-            if (write_bnd) {
-                const int j = t - (B - 1);
-                if (j >= 0 && j < ncols)
-                    C::put(sbase + (int64_t)(j >> 2) * cstride + (j & 3) * C::kWords, hbot, F);
-            }
+            // the last lane of a lane group hands column j = t - (B - 1) to the next pass
+            const int j = 4 * c + u - (B - 1);
+            C::put(io.bnd, io.wr_lane + (uint32_t)((j >> 2) * (int)io.cstride + (j & 3) * 4 * W), hbot, F);
             if (COOP) {
                 up_h = C::shift(hbot);
                 up_f = C::shift(F);
             }
-        }
-        lo = hi;
-        hi = nhi;
-        if (!COOP) lo = nhi;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { bh[u] = nbh[u]; bf[u] = nbf[u]; }
+            for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+        }
+        c0 = c1;
+        c1 = c2;
+        c2 = c3;
+        rr = rn;
+#pragma unroll
+        for (int i = 0; i < W; ++i) bw[i] = nw[i];
     }
 }
 
@@ -364,198 +422,6 @@ __device__ __forceinline__ void load_slice(int16_t* dst, const int16_t* prof, in
         const int ru = rem - bb * (R / U);
         const V v = *reinterpret_cast<const V*>(prof + (int64_t)d * mp + row0 + rem * U);
         *reinterpret_cast<V*>(dst + (bb * kNRes + d) * R + ru * U) = v;
-    }
-}
-
-template <class C, int R>
-__device__ __forceinline__ void run_unit_passes(const SweepArgs& a, int g, int k, int lgB, int q, bool valid,
-                                                bool shared_slice, int16_t* lds, int wave, int lane,
-                                                uint32_t* slot) {
-    using T = typename C::T;
-    const int B = 1 << lgB;
-    const int P = kGroupPairs >> lgB;
-    const int s = lane >> lgB;
-    const int b = lane & (B - 1);
-    const QDesc Q = a.qd[q];
-    const int rows_pp = R << lgB;
-    const int passes = (Q.m + rows_pp - 1) / rows_pp;
-    GroupRec G{0, 0, 0};
-    int ncols = 0;
-    if (valid) {
-        G = a.groups[g];
-        // pairs are sorted by length within the group: the unit's first pair is its widest
-        ncols = a.pair_cols[g * kGroupPairs + k * P];
-    }
-    const int pair = k * P + s;
-    const uint8_t* resp = a.image + G.base + pair * 8;
-    const int16_t* prof = a.prof + Q.prof_off;
-    int16_t* region = shared_slice ? lds : lds + wave * (kNRes * 16 * R);
-    const int16_t* lrow = region + b * kNRes * R;
-    const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
-    T S = C::zero();
-    for (int p = 0; p < passes; ++p) {
-        if (shared_slice) {
-            __syncthreads();
-            load_slice<R>(region, prof, Q.mp, p * rows_pp, lgB, threadIdx.x, blockDim.x);
-            __syncthreads();
-        } else {
-            __builtin_amdgcn_wave_barrier();
-            load_slice<R>(region, prof, Q.mp, p * rows_pp, lgB, lane, 64);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (valid) {
-            if (lgB == 0)
-                sweep_pass<C, R, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
-            else
-                sweep_pass<C, R, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
-    }
-    if (!valid) return;
-    for (int o = 1; o < B; o <<= 1) S = C::xmax(S, o);
-    if (b == 0) {
-        const int slot0 = g * kGroupSubjects + 2 * pair;
-        const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
-        int32_t* out = Q.out ? Q.out : a.scores + Q.out_off;
-        if (o0 >= 0) out[o0] = C::lo(S);
-        if (o1 >= 0) out[o1] = C::hi(S);
-        if (a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) {
-            const int idx = atomicAdd(a.rerun_count, 1);
-            if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, q, (int16_t)pair, 6, 1, 1};
-        }
-    }
-}
-
-template <class C, int R>
-__global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
-    // one shared slice of up to 64*R rows, or four per-wave slices of up to 16*R rows
-    __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
-    __shared__ int s_item;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
-    int n_items = a.n_items;
-    if (a.n_items_dev) {
-        const int c = min(*a.n_items_dev, a.n_items);
-        n_items = c;
-    }
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= n_items) break;
-        if (a.unit_list) {
-            // one unit per workgroup, computed by wave 0 with the whole LDS slice
-            const WgItem I = a.items[it];
-            run_unit_passes<C, R>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
-        } else {
-            const WgItem I = a.items[it];
-            const int B = 1 << I.lgB;
-            int k = I.k0 + wave;
-            const int g = I.g0 + (k >> I.lgB) * I.gstep;
-            k &= B - 1;
-            const bool shared_slice = I.lgB > 4;        // more than 16 lanes per pair
-            run_unit_passes<C, R>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
-        }
-    }
-}
-
-// ------------------------------------------------------------ query-pair sweep
-// Two queries per lane: the two halves of every packed cell are the same
-// subject against query a and query b, so a row's substitution pair is one
-// dword of a pre-interleaved profile slice and needs no permute.  A wave owns
-// P = 64/B subjects of a group (B lanes each, anti-diagonal as above); a group
-// has 2B such units.
-
-__device__ __forceinline__ uint32_t load_chunk1(const uint8_t* resp, int c, int nchunks) {
-    if (c < 0 || c >= nchunks) return 0x14141414u;
-    return *reinterpret_cast<const uint32_t*>(resp + (int64_t)c * kChunkBytes);
-}
-
-template <int R, bool COOP>
-__device__ __forceinline__ void sweep_pass_q2(const uint8_t* resp, int ncols, int lgB, int b, int s, int p, int passes,
-                                              const uint32_t* lrow, uint32_t* slot, u2 go, u2 ge, s2& S) {
-    using C = CellI16;
-    using T = s2;
-    const int B = 1 << lgB;
-    const int P = kGroupPairs >> lgB;
-    const int nchunks = ncols >> 2;
-    const int nsteps = ncols + B - 1;
-    const int nloop = (nsteps + 3) >> 2;
-    const bool first_lane = (b == 0);
-    const bool read_bnd = first_lane && p > 0;
-    const bool write_bnd = (b == B - 1) && p + 1 < passes;
-    const int cstride = P * 4 * C::kWords;
-    uint32_t* sbase = slot + s * 4 * C::kWords;
-
-    T H[R], E[R];      // H and E of this lane's rows at the last column done
-#pragma unroll
-    for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
-    T diag_top = C::zero();
-    T up_h = C::zero(), up_f = C::zero();
-    const int coff = COOP ? ((-b) >> 2) : 0;
-    const int csh = COOP ? ((-b) & 3) : 0;
-    uint32_t lo = load_chunk1(resp, coff, nchunks);
-    uint32_t hi = COOP ? load_chunk1(resp, coff + 1, nchunks) : 0u;
-    T bh[4], bf[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { bh[u] = C::zero(); bf[u] = C::zero(); }
-    if (read_bnd && nchunks > 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) ld_words<C>(sbase + u * C::kWords, bh[u], bf[u]);
-    }
-    for (int c = 0; c < nloop; ++c) {
-        const uint32_t nhi = load_chunk1(resp, coff + c + (COOP ? 2 : 1), nchunks);
-        T nbh[4], nbf[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { nbh[u] = C::zero(); nbf[u] = C::zero(); }
-        if (read_bnd && c + 1 < nchunks) {
-            const uint32_t* w = sbase + (int64_t)(c + 1) * cstride;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ld_words<C>(w + u * C::kWords, nbh[u], nbf[u]);
-        }
-        const uint32_t rr = COOP ? __builtin_amdgcn_alignbyte(hi, lo, csh) : lo;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = 4 * c + u;
-            const int d = (rr >> (8 * u)) & 0xff;
-            uint32_t w[R];
-            if constexpr (R % 4 == 0) {
-                const uint4* q = reinterpret_cast<const uint4*>(lrow + d * R);
-#pragma unroll
-                for (int v = 0; v < R / 4; ++v) {
-                    const uint4 x = q[v];
-                    w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
-                }
-            }
-            T htop, ftop;
-            if (COOP) {
-                htop = C::sel(first_lane, bh[u], up_h);
-                ftop = C::sel(first_lane, bf[u], up_f);
-            } else {
-                htop = bh[u];
-                ftop = bf[u];
-            }
-            T F = ftop;
-            rows16_packed<R>(H, E, S, F, diag_top, w, go, ge);
-            diag_top = htop;
-            const T hbot = H[R - 1];
-            if (write_bnd) {
-                const int j = t - (B - 1);
-                if (j >= 0 && j < ncols)
-                    C::put(sbase + (int64_t)(j >> 2) * cstride + (j & 3) * C::kWords, hbot, F);
-            }
-            if (COOP) {
-                up_h = C::shift(hbot);
-                up_f = C::shift(F);
-            }
-        }
-        lo = COOP ? hi : nhi;
-        hi = nhi;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { bh[u] = nbh[u]; bf[u] = nbf[u]; }
     }
 }
 
@@ -589,90 +455,161 @@ __device__ __forceinline__ void load_slice_q2(uint32_t* dst, const int16_t* pa, 
     }
 }
 
-template <int R>
-__device__ __forceinline__ void run_unit_q2(const SweepArgs& a, int g, int k, int lgB, int qp, bool valid,
-                                            bool shared_slice, int16_t* lds, int wave, int lane, uint32_t* slot) {
-    using T = s2;
+__device__ __forceinline__ void append_rerun(const SweepArgs& a, int g, int q, int pair) {
+    const int idx = atomicAdd(a.rerun_count, 1);
+    if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, q, (int16_t)pair, 6, 1, 1};
+}
+
+// One unit of a wave: lane groups [k*P, (k+1)*P) of group g, all passes.
+// Subject pairs (PACKED = false): P = 64/B pairs, one query.  Query pairs
+// (PACKED = true): P = 64/B subjects, queries qpairs[q].x and .y.
+template <class C, int R, bool PACKED>
+__device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int lgB, int q, bool valid,
+                                         bool shared_slice, int16_t* lds, int wave, int lane, uint32_t* slot) {
+    using T = typename C::T;
     const int B = 1 << lgB;
-    const int P = kGroupPairs >> lgB;                   // subjects per unit
+    const int P = kGroupPairs >> lgB;
     const int s = lane >> lgB;
     const int b = lane & (B - 1);
-    const int2 pr = a.qpairs[qp];
-    const QDesc Qa = a.qd[pr.x];
-    const QDesc Qb = a.qd[pr.y >= 0 ? pr.y : pr.x];
+    int qa = q, qb = -1;
+    if constexpr (PACKED) {
+        const int2 pr = a.qpairs[q];
+        qa = pr.x;
+        qb = pr.y;
+    }
+    const QDesc Qa = a.qd[qa];
+    const QDesc Qb = a.qd[qb >= 0 ? qb : qa];
     const int m = max(Qa.m, Qb.m);
     const int rows_pp = R << lgB;
     const int passes = (m + rows_pp - 1) / rows_pp;
+    const int su = k * P + s;                   // pair (subject pairs) or subject (query pairs) in the group
     GroupRec G{0, 0, 0};
     int ncols = 0;
-    const int su = k * P + s;                           // subject within the group
     if (valid) {
         G = a.groups[g];
-        ncols = a.pair_cols[g * kGroupPairs + ((k * P) >> 1)];
+        // pairs are sorted by length within the group: the unit's first one is its widest
+        ncols = a.pair_cols[g * kGroupPairs + (PACKED ? (k * P) >> 1 : k * P)];
     }
-    const uint8_t* resp = a.image + G.base + (su >> 1) * 8 + (su & 1) * 4;
-    uint32_t* region = reinterpret_cast<uint32_t*>(shared_slice ? lds : lds + wave * (kNRes * 16 * R));
-    const uint32_t* lrow = region + b * kNRes * R;
-    const u2 go = CellI16::gapv(a.go), ge = CellI16::gapv(a.ge);
-    T S = CellI16::zero();
+    PassIO io;
+    io.img = make_rsrc(a.image + G.base, (uint32_t)(G.ncols >> 2) * kChunkBytes);
+    io.img_lane = PACKED ? (uint32_t)((su >> 1) * 8 + (su & 1) * 4) : (uint32_t)(su * 8);
+    io.cstride = (uint32_t)(P * 16 * C::kWords);
+    io.bnd = make_rsrc(slot, (uint32_t)(ncols >> 2) * io.cstride);
+    const uint32_t lane_words = (uint32_t)(s * 16 * C::kWords);
+    uint32_t* region32 = reinterpret_cast<uint32_t*>(shared_slice ? lds : lds + wave * (kNRes * 16 * R));
+    const int16_t* lrow = PACKED ? reinterpret_cast<const int16_t*>(region32 + b * kNRes * R)
+                                 : reinterpret_cast<const int16_t*>(region32) + b * kNRes * R;
+    const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
+    T S = C::zero();
     for (int p = 0; p < passes; ++p) {
         if (shared_slice) {
             __syncthreads();
-            load_slice_q2<R>(region, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
-                             threadIdx.x, blockDim.x);
+            if constexpr (PACKED)
+                load_slice_q2<R>(region32, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
+                                 threadIdx.x, blockDim.x);
+            else
+                load_slice<R>(reinterpret_cast<int16_t*>(region32), a.prof + Qa.prof_off, Qa.mp, p * rows_pp, lgB,
+                              threadIdx.x, blockDim.x);
             __syncthreads();
         } else {
             __builtin_amdgcn_wave_barrier();
-            load_slice_q2<R>(region, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
-                             lane, 64);
+            if constexpr (PACKED)
+                load_slice_q2<R>(region32, a.prof + Qa.prof_off, Qa.mp, a.prof + Qb.prof_off, Qb.mp, p * rows_pp, lgB,
+                                 lane, 64);
+            else
+                load_slice<R>(reinterpret_cast<int16_t*>(region32), a.prof + Qa.prof_off, Qa.mp, p * rows_pp, lgB,
+                              lane, 64);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
         if (valid) {
+            io.rd_lane = (b == 0 && p > 0) ? lane_words : kNoAccess;
+            io.wr_lane = (b == B - 1 && p + 1 < passes) ? lane_words : kNoAccess;
             if (lgB == 0)
-                sweep_pass_q2<R, false>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, R, false, PACKED>(io, ncols, B, b, lrow, go, ge, S);
             else
-                sweep_pass_q2<R, true>(resp, ncols, lgB, b, s, p, passes, lrow, slot, go, ge, S);
+                sweep_pass<C, R, true, PACKED>(io, ncols, B, b, lrow, go, ge, S);
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
     if (!valid) return;
-    for (int o = 1; o < B; o <<= 1) S = CellI16::xmax(S, o);
-    if (b == 0) {
-        const int slot0 = g * kGroupSubjects + su;
-        const int o = a.perm[slot0];
+    for (int o = 1; o < B; o <<= 1) S = C::xmax(S, o);
+    if (b != 0) return;
+    if constexpr (PACKED) {
+        const int o = a.perm[g * kGroupSubjects + su];
         if (o >= 0) {
             int32_t* outa = Qa.out ? Qa.out : a.scores + Qa.out_off;
-            outa[o] = S.x;
-            if (pr.y >= 0) {
+            outa[o] = C::lo(S);
+            if (qb >= 0) {
                 int32_t* outb = Qb.out ? Qb.out : a.scores + Qb.out_off;
-                outb[o] = S.y;
+                outb[o] = C::hi(S);
             }
         }
         if (a.rerun != nullptr) {
-            if (S.x >= a.sat) {
-                const int idx = atomicAdd(a.rerun_count, 1);
-                if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, pr.x, (int16_t)(su >> 1), 6, 1, 1};
-            }
-            if (pr.y >= 0 && S.y >= a.sat) {
-                const int idx = atomicAdd(a.rerun_count, 1);
-                if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, pr.y, (int16_t)(su >> 1), 6, 1, 1};
-            }
+            if (C::lo(S) >= a.sat) append_rerun(a, g, qa, su >> 1);
+            if (qb >= 0 && C::hi(S) >= a.sat) append_rerun(a, g, qb, su >> 1);
+        }
+    } else {
+        const int slot0 = g * kGroupSubjects + 2 * su;
+        const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
+        int32_t* out = Qa.out ? Qa.out : a.scores + Qa.out_off;
+        if (o0 >= 0) out[o0] = C::lo(S);
+        if (o1 >= 0) out[o1] = C::hi(S);
+        if (a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
+    }
+}
+
+template <class C, int R>
+__global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
+    // one shared slice of up to 64*R rows, or four per-wave slices of up to 16*R rows
+    __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: buffer resources stay scalar
+    const int lane = threadIdx.x & 63;
+    uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
+    int n_items = a.n_items;
+    if (a.n_items_dev) {
+        const int c = min(*a.n_items_dev, a.n_items);
+        n_items = c;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= n_items) break;
+        const WgItem I = a.items[it];
+        if (a.unit_list) {
+            // one unit per workgroup, computed by wave 0 with the whole LDS slice
+            run_unit<C, R, false>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
+        } else {
+            const int B = 1 << I.lgB;
+            int k = I.k0 + wave;
+            const int g = I.g0 + (k >> I.lgB) * I.gstep;
+            k &= B - 1;
+            const bool shared_slice = I.lgB > 4;        // more than 16 lanes per pair
+            run_unit<C, R, false>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
         }
     }
 }
 
+// ------------------------------------------------------------ query-pair sweep
+// Two queries per lane: the two halves of every packed cell are the same
+// subject against query a and query b, so a row's substitution pair is one
+// dword of a pre-interleaved profile slice and needs no permute.  A wave owns
+// P = 64/B subjects of a group (B lanes each, anti-diagonal as above); a group
+// has 2B such units.
 template <int R>
 __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
     __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
     __shared__ int s_item;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: buffer resources stay scalar
     const int lane = threadIdx.x & 63;
     uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it >= a.n_items) break;
         const WgItem I = a.items[it];
@@ -681,13 +618,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
         const int g = I.g0 + (k / units) * I.gstep;
         k %= units;
         const bool shared_slice = I.lgB > 3;            // more than 8 lanes per subject
-        run_unit_q2<R>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
+        run_unit<CellI16, R, true>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
     }
 }
 
 // ------------------------------------------------------------ query profile
-// prof[d][i] = SM(Q[i], d) for d < 20 and i < m; kPadScore elsewhere.  One
-// staging buffer holds the 20x20 matrix followed by the query codes.
+// prof[d][i] = SM(Q[i], d - 1) for image codes d = 1..20 and i < m; kPadScore
+// for d = 0 (padding) and past m.  One staging buffer holds the 20x20 matrix
+// followed by the query codes.
 // Thread 0 also zeroes the launch counters (they are consumed by later kernels
 // on the same stream).
 __global__ void k_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff,
@@ -703,7 +641,7 @@ __global__ void k_profile(const int8_t* stage, const QDesc* qd, int nq, const in
         const int d = (int)(e / Q.mp);
         const int i = (int)(e - (int64_t)d * Q.mp);
         int16_t v = kPadScore;
-        if (d < 20 && i < Q.m) v = sm[query[i] * 20 + d];
+        if (d >= 1 && i < Q.m) v = sm[query[i] * 20 + (d - 1)];
         prof[Q.prof_off + e] = v;
     }
 }
@@ -724,18 +662,17 @@ __global__ void k_interleave(const int8_t* res, const int64_t* soff, const int32
         const int64_t c = local / (kChunkBytes / 4);
         const int rem = (int)(local - c * (kChunkBytes / 4));    // 0..127 = 2*pair + half
         const int64_t sidx = (int64_t)g * kGroupSubjects + rem;
-        uint32_t word = 0x14141414u;
+        uint32_t word = 0;                   // padding
         if (sidx < n) {
             const int64_t off = soff[sidx];
             const int len = slen[sidx];
-            word = 0;
             for (int kk = 0; kk < 4; ++kk) {
                 const int64_t col = 4 * c + kk;
                 uint32_t v = kPadCode;
                 if (col < len) {
                     const int r = res[off + col];
-                    if (r < 0 || r >= 20) { atomicOr(err, 1); v = kPadCode; }
-                    else v = (uint32_t)r;
+                    if (r < 0 || r >= 20) atomicOr(err, 1);
+                    else v = (uint32_t)r + 1;
                 }
                 word |= v << (8 * kk);
             }

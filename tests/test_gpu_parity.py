@@ -166,6 +166,42 @@ def test_scores_above_int16_are_exact(gpu, blosum, lanes):
     assert st["rerun_pairs"] >= 2
 
 
+def _threshold_db():
+    """Self scores just below, at and above 0x7C00 = 31744, the first 16-bit
+    pattern that the packed maximum does not order as a number (W scores 11,
+    H 8 and C 9 on the BLOSUM62 diagonal)."""
+    W, H, C = 17, 8, 4
+    rng = np.random.default_rng(23)
+    core = [np.concatenate([np.full(2885, W), [H]]), np.concatenate([np.full(2885, W), [C]]), np.full(2890, W)]
+    subs = [np.asarray(x, np.int8) for x in core] + [rng.integers(0, 20, int(rng.integers(1, 300))).astype(np.int8)
+                                                       for _ in range(60)]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum([x.size for x in subs])
+    return synth.Database(np.concatenate(subs), offs, name="threshold"), core
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 64])
+def test_scores_at_the_16bit_threshold(gpu, blosum, lanes):
+    db, core = _threshold_db()
+    for i, (q, self_score, reruns) in enumerate(zip(core, (31743, 31744, 31790), (False, True, True))):
+        got, st = gpu_scores(gpu, db, q, blosum, 10, 2, force_lanes=lanes)
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
+        assert want[i] == self_score
+        assert_equal_scores(got, want, f"threshold q{i} lanes={lanes}")
+        assert (st["rerun_pairs"] > 0) == reruns, (i, st)
+
+
+def test_query_pairs_at_the_16bit_threshold(gpu, blosum):
+    import torch
+    db, core = _threshold_db()
+    D = gpu.Database(db.residues, db.offsets, lane_pack=2)
+    scores, _, _ = D.search_batch(core, blosum, 10, 2, k=0)
+    torch.cuda.synchronize()
+    for i, q in enumerate(core):
+        assert_equal_scores(scores[i].cpu().numpy(), oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), f"q{i}")
+    D.close()
+
+
 @pytest.mark.parametrize("lanes", [0, 4])
 def test_forced_rerun_everything(gpu, blosum, lanes):
     """With the rerun threshold at 1 every pair goes through the 32-bit sweep."""
