@@ -224,11 +224,14 @@ sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
 }
 
 // ------------------------------------------------------------------ planning
+// Issue slots of one unit (in half instructions): passes x steps x the step's
+// instruction count, 9.5 per row of R plus loads, addressing and, with
+// cooperating lanes, the shift of the bottom row.
 int64_t unit_cost(int m, int ncols, int lgB, int R) {
     const int B = 1 << lgB;
     const int64_t passes = (m + (R << lgB) - 1) / (R << lgB);
     const int64_t steps = round_up(ncols + B - 1, 4);
-    const int64_t per_step = 10 * R + 16 + (lgB ? 6 : 0);
+    const int64_t per_step = 19 * R + 30 + (lgB ? 8 : 0);
     return passes * steps * per_step;
 }
 
@@ -245,80 +248,93 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
                 std::vector<WgItem>& side_out, const std::vector<int>* chunk = nullptr, int nchunks = 1) {
     // query qi covers groups chunk[qi], chunk[qi] + nchunks, ... (all groups when nchunks == 1)
     auto first_group = [&](size_t qi) { return chunk ? (*chunk)[qi] : 0; };
-    int R_main = 16;
-    {
-        int64_t best = -1;
-        for (int R : {8, 16}) {
-            int64_t t = 0;
-            for (size_t qi = 0; qi < qlens.size(); ++qi)
-                if (qlens[qi] > 0)
-                    for (int g = first_group(qi); g < db->ngroups; g += nchunks) t += unit_cost(qlens[qi], db->ncols[g], 0, R);
-            if (best < 0 || t < best) { best = t; R_main = R; }
-        }
-    }
-    if (db->force_R) R_main = db->force_R;
-    const int64_t nwaves = (int64_t)db->wgR[R_main] * kWaves;
-    int64_t total = 0;
-    for (size_t qi = 0; qi < qlens.size(); ++qi)
-        if (qlens[qi] > 0)
-            for (int g = first_group(qi); g < db->ngroups; g += nchunks) total += unit_cost(qlens[qi], db->ncols[g], 0, R_main);
-    const double cap = db->unit_share * (double)total / (double)std::max<int64_t>(nwaves, 1);
-    int R_side = R_main;
     struct Tmp { WgItem it; int64_t cost; };
-    std::vector<Tmp> items, sitems;
-    for (size_t qi = 0; qi < qlens.size(); ++qi) {
-        const int m = qlens[qi];
-        if (m <= 0) continue;
-        int r_long = R_main;
-        if (qlens.size() == 1 && !db->force_R)
-            for (int R : kRowChoices)
-                if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
-        const int g_first = first_group(qi);
-        WgItem cur{0, (int32_t)qi, 0, -1, 0, nchunks}, scur{0, (int32_t)qi, 0, -1, 0, nchunks};
-        int64_t cur_cost = 0, scur_cost = 0;
-        auto flush = [](std::vector<Tmp>& v, WgItem& c, int64_t& cc) {
-            if (c.count > 0) v.push_back({c, cc});
-            c.count = 0;
-            cc = 0;
-        };
-        auto add = [&](std::vector<Tmp>& v, WgItem& c, int64_t& cc, int g, int k, int lgB, int64_t cost) {
-            // position of (group, sub-unit) in this query's unit sequence
-            const int64_t seq_g = (g - g_first) / nchunks, seq_c = (c.g0 - g_first) / nchunks;
-            const bool contiguous = c.count > 0 && c.lgB == lgB && (seq_c << lgB) + c.k0 + c.count == (seq_g << lgB) + k;
-            if (c.count == kWaves || !contiguous) {
-                flush(v, c, cc);
-                c.g0 = g;
-                c.k0 = (int16_t)k;
-                c.lgB = (int8_t)lgB;
-            }
-            c.count++;
-            cc = std::max(cc, cost);
-        };
-        for (int g = g_first; g < db->ngroups; g += nchunks) {
-            const int nc = db->ncols[g];
-            int lgB = 0;
-            for (; lgB < 6; ++lgB) {
-                const int64_t P = kGroupPairs >> lgB;
-                if ((double)unit_cost(m, nc, lgB, R_main) <= cap && (int64_t)nc * P <= db->slot_cap) break;
-            }
-            if (db->force_lgB >= 0) {
-                lgB = db->force_lgB;
-                while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
-            }
-            for (int k = 0; k < (1 << lgB); ++k) {
-                const int uc = db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))];
-                const int64_t c = unit_cost(m, uc, lgB, R_main);
-                if (lgB == 6 && db->force_lgB < 0 && r_long != R_main && (double)c > cap &&
-                    unit_cost(m, uc, 6, r_long) < c) {
-                    add(sitems, scur, scur_cost, g, k, 6, unit_cost(m, uc, 6, r_long));
-                    R_side = r_long;
-                } else {
-                    add(items, cur, cur_cost, g, k, lgB, c);
+    // The plan at R rows per lane; returns its estimated makespan in cost units per wave.
+    auto plan_at = [&](int R_main, std::vector<Tmp>& items, std::vector<Tmp>& sitems, int& R_side) -> double {
+        const int64_t nwaves = std::max<int64_t>((int64_t)db->wgR[R_main] * kWaves, 1);
+        int64_t total = 0;
+        for (size_t qi = 0; qi < qlens.size(); ++qi)
+            if (qlens[qi] > 0)
+                for (int g = first_group(qi); g < db->ngroups; g += nchunks) total += unit_cost(qlens[qi], db->ncols[g], 0, R_main);
+        const double cap = db->unit_share * (double)total / (double)nwaves;
+        R_side = R_main;
+        int64_t sum = 0, biggest = 0, sbiggest = 0;
+        for (size_t qi = 0; qi < qlens.size(); ++qi) {
+            const int m = qlens[qi];
+            if (m <= 0) continue;
+            int r_long = R_main;
+            if (qlens.size() == 1 && !db->force_R)
+                for (int R : kRowChoices)
+                    if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
+            const int g_first = first_group(qi);
+            WgItem cur{0, (int32_t)qi, 0, -1, 0, nchunks}, scur{0, (int32_t)qi, 0, -1, 0, nchunks};
+            int64_t cur_cost = 0, scur_cost = 0;
+            auto flush = [](std::vector<Tmp>& v, WgItem& c, int64_t& cc) {
+                if (c.count > 0) v.push_back({c, cc});
+                c.count = 0;
+                cc = 0;
+            };
+            auto add = [&](std::vector<Tmp>& v, WgItem& c, int64_t& cc, int g, int k, int lgB, int64_t cost) {
+                // position of (group, sub-unit) in this query's unit sequence
+                const int64_t seq_g = (g - g_first) / nchunks, seq_c = (c.g0 - g_first) / nchunks;
+                const bool contiguous = c.count > 0 && c.lgB == lgB && (seq_c << lgB) + c.k0 + c.count == (seq_g << lgB) + k;
+                if (c.count == kWaves || !contiguous) {
+                    flush(v, c, cc);
+                    c.g0 = g;
+                    c.k0 = (int16_t)k;
+                    c.lgB = (int8_t)lgB;
+                }
+                c.count++;
+                cc = std::max(cc, cost);
+            };
+            for (int g = g_first; g < db->ngroups; g += nchunks) {
+                const int nc = db->ncols[g];
+                int lgB = 0;
+                for (; lgB < 6; ++lgB) {
+                    const int64_t P = kGroupPairs >> lgB;
+                    if ((double)unit_cost(m, nc, lgB, R_main) <= cap && (int64_t)nc * P <= db->slot_cap) break;
+                }
+                if (db->force_lgB >= 0) {
+                    lgB = db->force_lgB;
+                    while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
+                }
+                for (int k = 0; k < (1 << lgB); ++k) {
+                    const int uc = db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))];
+                    const int64_t c = unit_cost(m, uc, lgB, R_main);
+                    if (lgB == 6 && db->force_lgB < 0 && r_long != R_main && (double)c > cap &&
+                        unit_cost(m, uc, 6, r_long) < c) {
+                        const int64_t sc = unit_cost(m, uc, 6, r_long);
+                        add(sitems, scur, scur_cost, g, k, 6, sc);
+                        sbiggest = std::max(sbiggest, sc);
+                        R_side = r_long;
+                    } else {
+                        add(items, cur, cur_cost, g, k, lgB, c);
+                        sum += c;
+                        biggest = std::max(biggest, c);
+                    }
                 }
             }
+            flush(items, cur, cur_cost);
+            flush(sitems, scur, scur_cost);
         }
-        flush(items, cur, cur_cost);
-        flush(sitems, scur, scur_cost);
+        // issue time: the SIMDs share the total; a unit shares its SIMD with the other resident waves
+        const double nsimd = 4.0 * db->cus, per_simd = (double)nwaves / nsimd;
+        return std::max({(double)sum / nsimd, (double)biggest * per_simd, (double)sbiggest * per_simd});
+    };
+    std::vector<Tmp> items, sitems;
+    int R_main = db->force_R ? db->force_R : 16, R_side = R_main;
+    const double t_main = plan_at(R_main, items, sitems, R_side);
+    if (!db->force_R) {
+        // fewer rows per lane pay more per cell but pad less when lanes cooperate on a short query
+        std::vector<Tmp> items8, sitems8;
+        int side8 = 8;
+        const double t8 = plan_at(8, items8, sitems8, side8);
+        if (t8 < t_main) {
+            items.swap(items8);
+            sitems.swap(sitems8);
+            R_main = 8;
+            R_side = side8;
+        }
     }
     auto by_cost = [](const Tmp& a, const Tmp& b) { return a.cost > b.cost; };
     std::stable_sort(items.begin(), items.end(), by_cost);
@@ -355,7 +371,7 @@ void plan_units_q2(const sw_db* db, const std::vector<int>& qlens, Plan* plan, s
     auto cost = [&](int m, int nc, int lgB) {
         const int B = 1 << lgB;
         const int64_t passes = (m + (R << lgB) - 1) / (R << lgB);
-        return passes * round_up(nc + B - 1, 4) * (int64_t)(9 * R + 16 + (lgB ? 6 : 0));
+        return passes * round_up(nc + B - 1, 4) * (int64_t)(17 * R + 30 + (lgB ? 8 : 0));
     };
     const int64_t nwaves = (int64_t)db->wgQ[R] * kWaves;
     int64_t total = 0;

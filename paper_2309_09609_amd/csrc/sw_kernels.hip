@@ -501,6 +501,11 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
                                  : reinterpret_cast<const int16_t*>(region32) + b * kNRes * R;
     const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
     T S = C::zero();
+    // A unit with many lanes per matrix is a long subject: its passes are one
+    // serial chain of steps that can outlast the rest of the search, so its
+    // wave issues ahead of the other waves of its SIMD while it runs.
+    const bool chain = lgB >= 5;
+    if (chain) __builtin_amdgcn_s_setprio(2);
     for (int p = 0; p < passes; ++p) {
         if (shared_slice) {
             __syncthreads();
@@ -532,6 +537,7 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
+    if (chain) __builtin_amdgcn_s_setprio(0);
     if (!valid) return;
     for (int o = 1; o < B; o <<= 1) S = C::xmax(S, o);
     if (b != 0) return;
