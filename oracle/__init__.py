@@ -6,6 +6,9 @@ or executes anything here, and nothing here uses the GPU library.
 
 * ``pair`` / ``scores``: the score S of Eq. 1-3 (Sec. II-B) computed by the
   plain C implementation in ``sw_oracle.c`` (int64 cells, one row at a time).
+* ``align``: the alignment behind a score (traceback from the highest H,
+  Sec. II-B), with a stated canonical choice among equal-scoring alignments;
+  full matrices, small inputs only.
 * ``topk``: the top-ranked subjects of a score vector (Sec. II-B, database
   search keeps alignments only for the top-ranked subjects), ordered by score
   descending then subject index ascending, padded with (-1, -1).
@@ -52,6 +55,9 @@ def _load():
         lib.sw_oracle_scores.restype = ctypes.c_int
         lib.sw_oracle_scores.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P,
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
+        lib.sw_oracle_align.restype = ctypes.c_int64
+        lib.sw_oracle_align.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
+                                        P, ctypes.c_char_p, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -128,3 +134,22 @@ def pair_neginf(q, d, sm, go: int, ge: int) -> int:
             S = max(S, Hn[i])
         Hc, Ec = Hn, En
     return int(S)
+
+
+def align(q, d, sm, go: int, ge: int) -> dict:
+    """Optimal local alignment of one pair (see ``sw_oracle_align`` for the
+    canonical choice among equal-scoring alignments).  Returns score, q_begin,
+    q_end, s_begin, s_end (0-based, end exclusive) and ``ops``: 'M' for an
+    aligned residue pair, 'I' for a query residue against a gap, 'D' for a
+    subject residue against a gap."""
+    q, d, sm = _i8(q), _i8(d), _i8(sm)
+    assert sm.shape == (20, 20)
+    out = np.zeros(5, dtype=np.int64)
+    cap = int(q.size + d.size + 1)
+    buf = ctypes.create_string_buffer(cap)
+    n = _load().sw_oracle_align(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, int(go), int(ge),
+                                out.ctypes.data, buf, cap)
+    if n < 0:
+        raise MemoryError("oracle allocation failed")
+    return {"score": int(out[0]), "q_begin": int(out[1]), "q_end": int(out[2]), "s_begin": int(out[3]),
+            "s_end": int(out[4]), "ops": buf.raw[:n].decode()}

@@ -117,3 +117,87 @@ int sw_oracle_scores(const int8_t* q, int64_t m, const int8_t* res, const int64_
     pthread_mutex_destroy(&J.lock);
     return J.failed ? -1 : 0;
 }
+
+/* ---------------- the alignment behind a score (traceback) ----------------
+ * The optimal local alignment of q (m residues) against d (n residues): the
+ * paper keeps alignments for the top-ranked subjects only and recovers them
+ * by tracing back from the cell with the highest H (Sec. II-B).  Here the
+ * full matrices H, E, F of Eq. 1-3 over (m+1) x (n+1) cells are kept (int32
+ * storage, int64 arithmetic: every stored value lies in [-Go, S]), so the
+ * inputs must be small.
+ *
+ * Several alignments may reach S.  This function returns the one fixed by:
+ *   end cell: the first cell with H = S in row-major order (smallest i, then j);
+ *   in H at (i, j): stop if H = 0 or i = 0 or j = 0 (the alignment starts
+ *     after this cell); else the diagonal if H = H[i-1][j-1] + SM(q_i, d_j),
+ *     else E if H = E[i][j], else F;
+ *   in E at (i, j): d_j faces a gap ('D'); continue in H at (i, j-1) if
+ *     E[i][j] = H[i][j-1] - Go (the gap opens there), else in E at (i, j-1);
+ *   in F at (i, j): q_i faces a gap ('I'); continue in H at (i-1, j) if
+ *     F[i][j] = H[i-1][j] - Go, else in F at (i-1, j);
+ *   the diagonal aligns q_i with d_j ('M') and continues in H at (i-1, j-1).
+ * out[0..4] = S, q_begin, q_end, s_begin, s_end (0-based residue indices,
+ * end exclusive); ops[0..len) holds the operations from the first aligned
+ * residue pair to the last.  Returns len, -1 on allocation failure, -2 if
+ * cap < len. */
+int64_t sw_oracle_align(const int8_t* q, int64_t m, const int8_t* d, int64_t n, const int8_t* sm,
+                        int64_t go, int64_t ge, int64_t* out, char* ops, int64_t cap)
+{
+    for (int k = 0; k < 5; ++k) out[k] = 0;
+    if (m <= 0 || n <= 0) return 0;
+    const int64_t w = n + 1;
+    int32_t* H = (int32_t*)calloc((size_t)((m + 1) * w), sizeof(int32_t));
+    int32_t* E = (int32_t*)calloc((size_t)((m + 1) * w), sizeof(int32_t));
+    int32_t* F = (int32_t*)calloc((size_t)((m + 1) * w), sizeof(int32_t));
+    char* rev = (char*)malloc((size_t)(m + n + 1));
+    if (!H || !E || !F || !rev) { free(H); free(E); free(F); free(rev); return -1; }
+    int64_t S = 0, ei = 0, ej = 0;
+    for (int64_t i = 1; i <= m; ++i) {
+        for (int64_t j = 1; j <= n; ++j) {
+            const int64_t e = max2((int64_t)H[i * w + j - 1] - go, (int64_t)E[i * w + j - 1] - ge);      /* Eq. 2 */
+            const int64_t f = max2((int64_t)H[(i - 1) * w + j] - go, (int64_t)F[(i - 1) * w + j] - ge);  /* Eq. 3 */
+            int64_t h = (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * 20 + d[j - 1]];
+            h = max2(max2(h, e), max2(f, 0));                                                          /* Eq. 1 */
+            E[i * w + j] = (int32_t)e;
+            F[i * w + j] = (int32_t)f;
+            H[i * w + j] = (int32_t)h;
+            if (h > S) { S = h; ei = i; ej = j; }
+        }
+    }
+    int64_t len = 0, i = ei, j = ej;
+    int state = 0;                  /* 0: H, 1: E, 2: F */
+    while (S > 0) {
+        if (state == 0) {
+            const int64_t h = H[i * w + j];
+            if (h == 0 || i == 0 || j == 0) break;
+            if (h == (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * 20 + d[j - 1]]) {
+                rev[len++] = 'M';
+                --i; --j;
+            } else if (h == E[i * w + j]) {
+                state = 1;
+            } else {
+                state = 2;
+            }
+        } else if (i < 1 || j < 1 || len >= m + n) {
+            break;                  /* unreachable for a consistent trace; guards the walk */
+        } else if (state == 1) {
+            rev[len++] = 'D';
+            if ((int64_t)E[i * w + j] == (int64_t)H[i * w + j - 1] - go) state = 0;
+            --j;
+        } else {
+            rev[len++] = 'I';
+            if ((int64_t)F[i * w + j] == (int64_t)H[(i - 1) * w + j] - go) state = 0;
+            --i;
+        }
+    }
+    free(H); free(E); free(F);
+    if (len > cap) { free(rev); return -2; }
+    for (int64_t k = 0; k < len; ++k) ops[k] = rev[len - 1 - k];
+    free(rev);
+    out[0] = S;
+    out[1] = S > 0 ? i : 0;
+    out[2] = ei;
+    out[3] = S > 0 ? j : 0;
+    out[4] = ej;
+    return len;
+}

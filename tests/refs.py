@@ -85,3 +85,27 @@ def identity_matrix(match: int = 1, mismatch: int = -128) -> np.ndarray:
     sm = np.full((20, 20), mismatch, dtype=np.int8)
     np.fill_diagonal(sm, match)
     return sm
+
+
+def score_ops(q, d, sm, go: int, ge: int, q_begin: int, s_begin: int, ops: str):
+    """Score of an alignment given as operations from (q_begin, s_begin):
+    'M' pairs q[i] with d[j]; 'I' puts q[i] against a gap, 'D' puts d[j]
+    against a gap.  A maximal run of k gap operations of one kind costs
+    Go + (k-1) * min(Go, Ge), as in ``bf_score``.  Returns (score, q_end, s_end)."""
+    i, j, s, last = q_begin, s_begin, 0, ""
+    ext = min(go, ge)
+    for op in ops:
+        if op == "M":
+            s += int(sm[int(q[i])][int(d[j])])
+            i += 1
+            j += 1
+        elif op == "I":
+            s -= ext if last == "I" else go
+            i += 1
+        elif op == "D":
+            s -= ext if last == "D" else go
+            j += 1
+        else:
+            raise ValueError(op)
+        last = op
+    return s, i, j
