@@ -179,6 +179,41 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
                           int32_t nchunks, sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
                           int32_t* const* h_d_scores, sw_stream stream);
 
+/* One optimal local alignment (see sw_align). */
+typedef struct {
+    int32_t score;            /* S of the pair */
+    int32_t q_begin, q_end;   /* aligned query residues [q_begin, q_end), 0-based */
+    int64_t subject;          /* subject index, as requested */
+    int64_t s_begin, s_end;   /* aligned subject residues [s_begin, s_end), 0-based */
+    int64_t n_ops;            /* operations written for this alignment */
+} sw_alignment;
+
+/*
+ * sw_align - the optimal local alignment of one query against each of nsub
+ * chosen subjects (Sec. II-B: a database search keeps alignments only for its
+ * top-ranked subjects, recovered by tracing back from the cell holding S).
+ *   h_query, qlen : as for sw_search (qlen <= 2^20).
+ *   h_subjects    : host int64[nsub], subject indices 0..n-1 (repeats allowed).
+ *   h_out         : host sw_alignment[nsub].
+ *   h_ops         : host char[nsub * ops_stride]; alignment k's operations go
+ *                   to h_ops[k * ops_stride ...], first aligned residue pair
+ *                   first: 'M' = query and subject residue aligned, 'I' = query
+ *                   residue against a gap, 'D' = subject residue against a gap.
+ *                   A maximal run of k gap operations of one kind costs
+ *                   Go + (k-1) * min(Go, Ge), the cost the recurrence charges.
+ *   ops_stride    : >= qlen + the longest requested subject (SW_E_SIZE otherwise).
+ * Among alignments of equal score the one returned ends at the first cell
+ * with H = S in row-major order and, tracing back, prefers the diagonal, then
+ * the horizontal gap (E), then the vertical gap (F), and a gap that opens
+ * over one that extends.  S = 0 gives an empty alignment (all fields 0).
+ * Synchronous: the work runs on `stream` and the call returns when the host
+ * buffers are filled.  Device memory: about qlen x subject length bytes per
+ * pair, in rounds of pairs that fit 1 GiB (a larger single pair runs alone).
+ */
+sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
+                   const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,
+                   int64_t ops_stride, sw_stream stream);
+
 /* Human-readable name of a status code (static string). */
 const char* sw_status_str(sw_status s);
 /* Description of the most recent error on the calling thread ("" if none). */

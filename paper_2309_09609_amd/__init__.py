@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
-           "sw_search_multi",
+           "sw_search_multi", "sw_align",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -63,6 +63,8 @@ def load():
     lib.sw_search_batch.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P]
     lib.sw_search_multi.restype = I32
     lib.sw_search_multi.argtypes = [P, P, I32, P, I32, P, P, I32, I32, P, P]
+    lib.sw_align.restype = I32
+    lib.sw_align.argtypes = [P, I32, P, P, I32, P, I32, I32, P, P, I64, P]
     lib.sw_status_str.restype = ctypes.c_char_p
     lib.sw_status_str.argtypes = [I32]
     lib.sw_last_error.restype = ctypes.c_char_p
@@ -75,6 +77,13 @@ def load():
     lib.sw_kernel_times.argtypes = [P, P, I32, P]
     _lib = lib
     return lib
+
+
+class Alignment(ctypes.Structure):
+    """sw_alignment of include/swsearch.h."""
+    _fields_ = [("score", ctypes.c_int32), ("q_begin", ctypes.c_int32), ("q_end", ctypes.c_int32),
+                ("subject", ctypes.c_int64), ("s_begin", ctypes.c_int64), ("s_end", ctypes.c_int64),
+                ("n_ops", ctypes.c_int64)]
 
 
 def _check(status: int):
@@ -231,6 +240,14 @@ class Database:
         sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
         return out[: self.n]
 
+    def align(self, query, subjects, subst, gap_open=10, gap_extend=2, stream=None):
+        """Optimal local alignments of ``query`` against the given subject indices
+        (see ``sw_align``)."""
+        subs = _host_i64(subjects)
+        lens = np.diff(self.offsets)
+        longest = int(lens[subs].max()) if subs.size else 0
+        return sw_align(query, self.handle, subs, subst, gap_open, gap_extend, longest, stream)
+
     def search_batch(self, queries, subst, gap_open=10, gap_extend=2, k=10, keep_scores=True, stream=None):
         """(scores [nq, n] or None, top scores [nq, k], top indices [nq, k])."""
         import torch
@@ -246,6 +263,28 @@ class Database:
             ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
         sw_search_batch(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, stream)
         return scores, ts, ti
+
+
+def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stream=None):
+    """List of dicts (score, q_begin, q_end, subject, s_begin, s_end, ops) for
+    ``query`` against each subject index in ``subjects``; ``longest`` bounds
+    the subject lengths (sizes the operation buffer)."""
+    q = _host_i8(query)
+    subs = _host_i64(subjects)
+    sm = _host_i8(subst)
+    assert sm.shape == (20, 20)
+    stride = int(q.size + longest + 1)
+    out = (Alignment * max(subs.size, 1))()
+    ops = ctypes.create_string_buffer(max(subs.size, 1) * stride)
+    _check(load().sw_align(_ptr(q), int(q.size), handle, _ptr(subs), int(subs.size), _ptr(sm), int(gap_open),
+                           int(gap_extend), ctypes.cast(out, ctypes.c_void_p), ops, stride, _stream(stream)))
+    res = []
+    raw = ops.raw
+    for k in range(subs.size):
+        a = out[k]
+        res.append({"score": a.score, "q_begin": a.q_begin, "q_end": a.q_end, "subject": a.subject,
+                    "s_begin": a.s_begin, "s_end": a.s_end, "ops": raw[k * stride: k * stride + a.n_ops].decode()})
+    return res
 
 
 def topk(scores, k, stream=None):

@@ -33,6 +33,10 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
+hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int go,
+                        int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
+                        int64_t* info, hipStream_t st);
+int64_t align_dir_bytes(int m, int64_t n);
 hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
@@ -159,6 +163,10 @@ struct sw_db {
     int32_t ncols_max = 0;
     DevBuf image, groups, perm, pair_cols;
     int64_t image_bytes = 0;
+    // per original subject: length and sorted slot; per group: byte offset in the image (alignments)
+    std::vector<int32_t> lens, slot_of;
+    std::vector<int64_t> gbase;
+    DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
     // launch geometry
     int cus = 0, wg16 = 0, wg32 = 0;  // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
     int wgR[17] = {0};                // persistent workgroups per 16-bit instance, by R
@@ -768,6 +776,11 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         slen[i] = len[order[i]];
     }
     db->image_bytes = base;
+    db->lens = len;
+    db->slot_of.assign(n, 0);
+    for (int64_t i = 0; i < n; ++i) db->slot_of[order[i]] = (int32_t)i;
+    db->gbase.resize(G);
+    for (int g = 0; g < G; ++g) db->gbase[g] = groups[g].base;
     if (G > 0) {
         DevBuf d_soff, d_slen, d_gdw, d_err;
         hipError_t e = hipSuccess;
@@ -822,6 +835,7 @@ void sw_db_free(sw_db* db) {
     hipDeviceSynchronize();
     clear_caches(db);
     db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
+    db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
     db->counters.release(); db->rerun.release(); db->scores_tmp.release();
     db->hstage.release();
@@ -1054,3 +1068,106 @@ sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ alignments
+namespace {
+constexpr int64_t kAlignBudget = (int64_t)1 << 30;   // direction bytes per round of pairs
+}
+
+sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
+                   const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,
+                   int64_t ops_stride, sw_stream stream) {
+    g_err.clear();
+    sw_status s;
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (qlen < 0 || nsub < 0) return fail(SW_E_INVALID, "qlen and nsub must be >= 0");
+    if (qlen > (1 << 20)) return fail(SW_E_UNSUPPORTED, "query longer than 2^20 residues");
+    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
+    if (nsub > 0 && (!h_subjects || !h_out || !h_ops)) return fail(SW_E_INVALID, "NULL subjects or outputs");
+    for (int32_t i = 0; i < qlen; ++i)
+        if (h_query[i] < 0 || h_query[i] >= 20) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..19", h_query[i], i);
+    int64_t longest = 0;
+    for (int32_t k = 0; k < nsub; ++k) {
+        if (h_subjects[k] < 0 || h_subjects[k] >= db->n) return fail(SW_E_INVALID, "subject index %lld outside 0..n-1", (long long)h_subjects[k]);
+        longest = std::max<int64_t>(longest, db->lens[h_subjects[k]]);
+    }
+    if (nsub > 0 && ops_stride < qlen + longest) return fail(SW_E_SIZE, "ops_stride %lld < query + longest subject (%lld)",
+                                                             (long long)ops_stride, (long long)(qlen + longest));
+    for (int32_t k = 0; k < nsub; ++k) {
+        h_out[k] = sw_alignment{0, 0, 0, h_subjects[k], 0, 0, 0};
+    }
+    if (nsub == 0 || qlen == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int32_t k0 = 0;
+    while (k0 < nsub) {
+        // a round: consecutive pairs whose direction bytes fit the budget (at least one pair)
+        int32_t k1 = k0;
+        int64_t dir_total = 0, bnd_total = 0, n_max = 0;
+        std::vector<AlignPair> pairs;
+        while (k1 < nsub) {
+            const int64_t sub = h_subjects[k1];
+            const int32_t nres = db->lens[sub];
+            const int64_t db_bytes = align_dir_bytes(qlen, nres);
+            if (k1 > k0 && dir_total + db_bytes > kAlignBudget) break;
+            const int32_t slot = db->slot_of[sub];
+            const int g = slot / kGroupSubjects, w = slot % kGroupSubjects;
+            AlignPair P;
+            P.residues = db->image.as<uint8_t>() + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
+            P.n = nres;
+            P.dir_off = dir_total;
+            P.bnd_off = bnd_total;
+            pairs.push_back(P);
+            dir_total += round_up(db_bytes, 256);
+            bnd_total += 2 * ((int64_t)nres + 1);
+            n_max = std::max<int64_t>(n_max, nres);
+            ++k1;
+        }
+        const int np = k1 - k0;
+        const int64_t stride = qlen + n_max + 1;
+        // misc: pairs | best (3 int32 each) | info (4 int64 each) | query | matrix | ops
+        const size_t o_pairs = 0;
+        const size_t o_best = round_up(sizeof(AlignPair) * np, 256);
+        const size_t o_info = o_best + round_up(12 * (size_t)np, 256);
+        const size_t o_query = o_info + round_up(32 * (size_t)np, 256);
+        const size_t o_sm = o_query + round_up(qlen, 256);
+        const size_t o_ops = o_sm + 512;
+        const size_t misc = o_ops + (size_t)np * stride;
+        HIP_TRY(db->align_dirs.reserve((size_t)std::max<int64_t>(dir_total, 256)));
+        HIP_TRY(db->align_bnd.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bnd_total, 64)));
+        HIP_TRY(db->align_misc.reserve(misc));
+        char* mb = db->align_misc.as<char>();
+        HIP_TRY(hipMemcpyAsync(mb + o_pairs, pairs.data(), sizeof(AlignPair) * np, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(mb + o_query, h_query, qlen, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(mb + o_sm, h_subst, 400, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, reinterpret_cast<int8_t*>(mb + o_query), qlen,
+                             reinterpret_cast<int8_t*>(mb + o_sm), gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
+                             db->align_bnd.as<int32_t>(), reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
+                             reinterpret_cast<int64_t*>(mb + o_info), st));
+        std::vector<int32_t> best(3 * (size_t)np);
+        std::vector<int64_t> info(4 * (size_t)np);
+        std::vector<char> ops((size_t)np * stride);
+        HIP_TRY(hipMemcpyAsync(best.data(), mb + o_best, 12 * (size_t)np, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(info.data(), mb + o_info, 32 * (size_t)np, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(ops.data(), mb + o_ops, (size_t)np * stride, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int k = 0; k < np; ++k) {
+            if (info[4 * k + 3] != 0) return fail(SW_E_HIP, "inconsistent traceback for subject %lld", (long long)h_subjects[k0 + k]);
+            sw_alignment& A = h_out[k0 + k];
+            const int64_t len = info[4 * k + 2];
+            A.score = best[3 * k];
+            A.q_begin = (int32_t)info[4 * k];
+            A.q_end = best[3 * k + 1];
+            A.s_begin = info[4 * k + 1];
+            A.s_end = best[3 * k + 2];
+            A.n_ops = len;
+            char* dst = h_ops + (int64_t)(k0 + k) * ops_stride;
+            const char* src = ops.data() + (size_t)k * stride;
+            for (int64_t x = 0; x < len; ++x) dst[x] = src[len - 1 - x];     // the walk wrote them last to first
+        }
+        k0 = k1;
+    }
+    return SW_OK;
+}

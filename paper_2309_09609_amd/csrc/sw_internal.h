@@ -75,4 +75,12 @@ struct SweepArgs {
     const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
 };
 
+// One (query, subject) pair of an alignment launch.
+struct AlignPair {
+    const uint8_t* residues;  // the subject's first chunk in the image (+ 8 * pair + 4 * half of its group)
+    int32_t n;                // subject length
+    int64_t dir_off;          // byte offset of the pair's direction bytes
+    int64_t bnd_off;          // int32 offset of the pair's boundary row (2 * (n + 1) words)
+};
+
 }  // namespace sw

@@ -1,0 +1,123 @@
+"""GPU alignments (traceback) against the oracle's: the same alignment,
+operation for operation, under the stated choice among equal-scoring ones."""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import synth
+from refs import score_ops
+
+pytestmark = pytest.mark.gpu
+
+
+def _subject(db, k):
+    return db.residues[db.offsets[k]:db.offsets[k + 1]]
+
+
+def _compare(got, q, db, subjects, sm, go, ge, ctx):
+    assert len(got) == len(subjects)
+    for a, k in zip(got, subjects):
+        d = _subject(db, k)
+        want = oracle.align(q, d, sm, go, ge)
+        assert a["subject"] == k
+        for key in ("score", "q_begin", "q_end", "s_begin", "s_end", "ops"):
+            assert a[key] == want[key], f"{ctx} subject {k} {key}: got {a[key]!r} want {want[key]!r}"
+        s, qe, se = score_ops(q, d, sm, go, ge, a["q_begin"], a["s_begin"], a["ops"])
+        assert (s, qe, se) == (a["score"], a["q_end"], a["s_end"]), ctx
+
+
+def test_alignments_of_a_small_database(gpu, blosum):
+    db = synth.small_db(seed=61, n=120, lo=1, hi=400)
+    q = synth.small_query(seed=61, m=230)
+    D = gpu.Database(db.residues, db.offsets)
+    subs = list(range(db.n))
+    _compare(D.align(q, subs, blosum, 10, 2), q, db, subs, blosum, 10, 2, "small db")
+    D.close()
+
+
+def test_alignments_of_the_top_hits(gpu, blosum):
+    """The intended use: search, take the top 10, align them."""
+    import torch
+    qs, db = synth.workload1()
+    D = gpu.Database(db.residues, db.offsets)
+    scores = D.search(qs[0], blosum, 10, 2)
+    ts, ti = gpu.topk(scores, 10)
+    torch.cuda.synchronize()
+    top = ti.cpu().numpy().tolist()
+    got = D.align(qs[0], top, blosum, 10, 2)
+    assert [a["score"] for a in got] == ts.cpu().numpy().tolist()
+    _compare(got, qs[0], db, top, blosum, 10, 2, "top hits")
+    D.close()
+
+
+@pytest.mark.parametrize("m", [1, 255, 256, 257, 700])
+def test_query_lengths_across_passes(gpu, blosum, m):
+    rng = np.random.default_rng(m)
+    lens = [1, 2, 3, 63, 64, 65, 500, 1500] + list(rng.integers(1, 900, 12))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    q = synth.background_residues(rng, m)
+    for s in subs[6:9]:
+        k = min(s.size, q.size) // 2
+        s[: k] = q[: k]                      # shared segments: long alignments with gaps nearby
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    idx = list(range(db.n))
+    _compare(D.align(q, idx, blosum, 10, 2), q, db, idx, blosum, 10, 2, f"m={m}")
+    D.close()
+
+
+@pytest.mark.parametrize("go,ge", [(0, 0), (3, 5), (11, 1), (50000, 70000)])
+def test_gap_settings(gpu, blosum, go, ge):
+    db = synth.small_db(seed=71, n=40, lo=1, hi=300)
+    q = synth.small_query(seed=72, m=180)
+    D = gpu.Database(db.residues, db.offsets)
+    idx = list(range(db.n))
+    _compare(D.align(q, idx, blosum, go, ge), q, db, idx, blosum, go, ge, f"gaps {go}/{ge}")
+    D.close()
+
+
+def test_long_subject_and_high_scores(gpu, blosum):
+    """A 35,000-residue subject, a score above 2^15 and repeated requests."""
+    rng = np.random.default_rng(3)
+    big = synth.background_residues(rng, 35000)
+    W = np.full(3000, 17, np.int8)
+    subs = [big, W, np.concatenate([big[:100], W[:2000], big[100:300]])]
+    offs = np.zeros(4, np.int64)
+    offs[1:] = np.cumsum([s.size for s in subs])
+    db = synth.Database(np.concatenate(subs), offs)
+    q = np.concatenate([big[20000:20400], W[:2950]])
+    D = gpu.Database(db.residues, db.offsets)
+    idx = [0, 1, 2, 1]
+    got = D.align(q, idx, blosum, 10, 2)
+    assert got[1]["score"] == 2950 * 11
+    _compare(got, q, db, idx, blosum, 10, 2, "long")
+    D.close()
+
+
+def test_empty_and_zero(gpu, blosum):
+    db = synth.small_db(seed=81, n=10, lo=1, hi=50)
+    D = gpu.Database(db.residues, db.offsets)
+    got = D.align(np.zeros(0, np.int8), [0, 1], blosum, 10, 2)
+    assert all(a["score"] == 0 and a["ops"] == "" for a in got)
+    sm = np.full((20, 20), -1, dtype=np.int8)
+    got = D.align(synth.small_query(seed=82, m=30), list(range(10)), sm, 1, 1)
+    assert all(a["score"] == 0 and a["ops"] == "" and a["q_end"] == 0 and a["s_end"] == 0 for a in got)
+    assert D.align(synth.small_query(seed=83, m=30), [], blosum, 10, 2) == []
+    D.close()
+
+
+def test_invalid_requests(gpu, blosum):
+    db = synth.small_db(seed=91, n=10, lo=1, hi=50)
+    D = gpu.Database(db.residues, db.offsets)
+    with pytest.raises(gpu.SwError):
+        D.align(synth.small_query(seed=92, m=10), [10], blosum, 10, 2)
+    with pytest.raises(gpu.SwError):
+        D.align(np.array([1, 25], np.int8), [0], blosum, 10, 2)
+    longest = int(np.argmax(np.diff(db.offsets)))
+    assert np.diff(db.offsets)[longest] >= 2
+    with pytest.raises(gpu.SwError):      # operation buffer too small for query + subject
+        gpu.sw_align(synth.small_query(seed=93, m=10), D.handle, np.array([longest], np.int64), blosum, 10, 2,
+                     longest=0)
+    D.close()
