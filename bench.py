@@ -149,13 +149,49 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     print(json.dumps(res), flush=True)
 
 
+def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
+    """Alignment form: search each query, then align its top 10 (traceback)."""
+    import torch
+    out = torch.empty(db.n, dtype=torch.int32, device="cuda")
+    tops = []
+    for q in queries:
+        D.search(q, sm, 10, 2, out=out)
+        ts, ti = sw.topk(out[: db.n], 10)
+        tops.append(ti.cpu().numpy())
+    lens = np.diff(db.offsets)
+    cells = sum(int(q.size) * int(lens[t].sum()) for q, t in zip(queries, tops))
+    for i in range(args.warmup):
+        for q, t in zip(queries, tops):
+            D.align(q, t, sm, 10, 2)
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        for q, t in zip(queries, tops):
+            al = D.align(q, t, sm, 10, 2)
+        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    n_al = len(queries) * 10
+    res = {
+        "metric": "GCUPS of the traceback (top-10 alignments per query)", "value": round(cells * args.steps / el / 1e9, 2),
+        "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "form": "align", "queries": len(queries), "alignments_per_query": 10,
+                   "subjects": db.n, "residues": total_res, "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
+        "extra": {"alignments_per_s": round(n_al * args.steps / el, 1), "cells_per_step": cells,
+                  "last_alignment": {k: al[-1][k] for k in ("score", "q_begin", "q_end", "s_begin", "s_end")}},
+    }
+    D.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256", "serve10M"])
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "align"])
     ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
@@ -200,6 +236,8 @@ def main():
     total_res = int(db.offsets[-1] - db.offsets[0])
     if args.form == "served":
         return serve_bench(args, sw, D, db, sm, total_res, perfmodel)
+    if args.form == "align":
+        return align_bench(args, sw, D, queries, db, sm, total_res, perfmodel)
     qlens = [int(q.size) for q in queries]
     cells_step = sum(qlens) * total_res
     out = torch.empty(db.n, dtype=torch.int32, device="cuda")

@@ -50,6 +50,14 @@ def test_argument_errors_without_gpu():
     assert lib.sw_topk(None, 0, 2000, None, None, None) == -5
     # batch: NULL handle
     assert lib.sw_search_batch(None, None, 0, None, sm.ctypes.data, 1, 1, 0, None, None, None, None) == -1
+    # alignments: NULL handle, negative gap
+    assert lib.sw_align(q.ctypes.data, 3, None, None, 0, sm.ctypes.data, 10, 2, None, None, 0, None) == -1
+    assert lib.sw_align(q.ctypes.data, 3, None, None, 0, sm.ctypes.data, -1, 2, None, None, 0, None) == -1
+
+
+def test_alignment_record_layout():
+    assert ctypes.sizeof(sw.Alignment) == 48
+    assert sw.Alignment.subject.offset == 16 and sw.Alignment.n_ops.offset == 40
 
 
 def test_pack_opts_layout():
