@@ -22,9 +22,11 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - Residue codes are int8 values 0..19 in the order ARNDCQEGHILKMFPSTWYV.
- *    Any other value in a query or database is an error (SW_E_RESIDUE).
- *  - The substitution matrix is int8[20][20], row-major, indexed
+ *  - Residue codes are int8 values 0..A-1, where A is the database's alphabet
+ *    size (sw_pack_opts.alphabet; by default A = 20, the amino acids in the
+ *    order ARNDCQEGHILKMFPSTWYV).  Any other value in a query or database is
+ *    an error (SW_E_RESIDUE).
+ *  - The substitution matrix is int8[A][A], row-major, indexed
  *    [query residue][subject residue], in host memory.
  *  - Gap penalties are Go = gap_open >= 0 and Ge = gap_extend >= 0; a gap run
  *    of k residues costs Go + (k-1)*Ge when Ge <= Go (the recurrence itself
@@ -55,7 +57,7 @@ typedef int32_t sw_status;
 enum {
     SW_OK = 0,
     SW_E_INVALID = -1,      /* null pointer, negative size or penalty, mismatched database */
-    SW_E_RESIDUE = -2,      /* residue code outside 0..19 */
+    SW_E_RESIDUE = -2,      /* residue code outside the alphabet */
     SW_E_NOMEM = -3,        /* device or host allocation failed */
     SW_E_HIP = -4,          /* a HIP runtime call failed; see sw_last_error() */
     SW_E_UNSUPPORTED = -5,  /* request outside the implemented limits (e.g. k > 1024) */
@@ -81,7 +83,11 @@ typedef struct {
     int32_t lane_pack;        /* tuning, batched and multi-query forms: 0 or 1 = the two 16-bit halves
                                  of a lane hold two subjects; 2 = they hold two queries (queries are
                                  paired by length; a single query always uses subject pairs) */
-    int32_t reserved[2];
+    int32_t alphabet;         /* residue codes 0..alphabet-1: 0 = 20 (the standard amino acids
+                                 ARNDCQEGHILKMFPSTWYV); up to 24 (e.g. plus B, Z, X, *).  Substitution
+                                 matrices passed with this database are int8[alphabet * alphabet].
+                                 Fixed at packing; sw_db_tune ignores it. */
+    int32_t reserved;
 } sw_pack_opts;
 
 /*
@@ -95,7 +101,7 @@ typedef struct {
  * The image sorts subjects by length and interleaves them for coalesced loads;
  * it is independent of the query and the scoring parameters.  This call
  * synchronises the stream (packing is a one-time setup step) and validates
- * every residue code: SW_E_RESIDUE if any is outside 0..19.
+ * every residue code: SW_E_RESIDUE if any is outside 0..alphabet-1.
  */
 sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t n,
                      const sw_pack_opts* opts, sw_stream stream, sw_db** out);
@@ -116,13 +122,13 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
 
 /*
  * sw_search - scores of one query against every subject (the "plain" form).
- *   h_query    : host int8[qlen], codes 0..19 (validated on the host).
+ *   h_query    : host int8[qlen], residue codes (validated on the host).
  *   qlen       : >= 0; qlen == 0 gives all-zero scores.
  *   db         : packed database.
  *   h_offsets  : the offsets the database was packed with (checked against
  *                the handle: same n and same first and last offset), or NULL.
  *   n          : number of subjects; must equal the handle's.
- *   h_subst    : host int8[20*20] substitution matrix.
+ *   h_subst    : host int8[A*A] substitution matrix.
  *   gap_open, gap_extend : Go, Ge >= 0.
  *   d_scores_out : device int32[n]; receives S for each subject in the
  *                original database order.

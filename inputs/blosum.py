@@ -17,8 +17,10 @@ Provenance
   PNAS 88:8880 (1991), the set BLAST uses for its composition statistics.
   The paper does not state a distribution; these only shape synthetic inputs.
 
-Alphabet order and codes: ``ARNDCQEGHILKMFPSTWYV`` -> 0..19.  Code 20 is never
-a valid residue; the GPU library uses it internally for padding.
+Alphabet order and codes: ``ARNDCQEGHILKMFPSTWYV`` -> 0..19.  The extended
+alphabet ``ARNDCQEGHILKMFPSTWYVBZX*`` -> 0..23 adds the ambiguity codes B (N or
+D), Z (Q or E), X (any) and the stop/terminal symbol *, with the extra rows and
+columns of the same NCBI table (``blosum62_24``).
 """
 from __future__ import annotations
 
@@ -50,6 +52,17 @@ Y -2 -2 -2 -3 -2 -1 -2 -3  2 -1 -1 -2 -1  3 -3 -2 -2  2  7 -1
 V  0 -3 -3 -3 -1 -2 -2 -3 -3  3  1 -2  1 -1 -2 -2  0 -3 -1  4
 """
 
+ALPHABET24 = ALPHABET + "BZX*"
+
+# The rows and columns B, Z, X, * of the NCBI BLOSUM62 table, in ALPHABET24
+# column order (the 20 x 20 block above is unchanged).
+_BLOSUM62_EXTRA = """
+B -2 -1  3  4 -3  0  1 -1  0 -3 -4  0 -3 -3 -2  0 -1 -4 -3 -3  4  1 -1 -4
+Z -1  0  0  1 -3  3  4 -2  0 -3 -3  1 -1 -3 -1  0 -1 -3 -2 -2  1  4 -1 -4
+X  0 -1 -1 -1 -2 -1 -1 -1 -1 -1 -1 -1 -1 -1 -2  0  0 -2 -1 -1 -1 -1 -1 -4
+* -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4  1
+"""
+
 # Robinson & Robinson (1991) background frequencies, in ALPHABET order.
 _ROBINSON = {
     "A": 0.07805, "R": 0.05129, "N": 0.04487, "D": 0.05364, "C": 0.01925,
@@ -66,6 +79,19 @@ def blosum62() -> np.ndarray:
     if order != ALPHABET:
         raise AssertionError("BLOSUM62 row order does not match the alphabet")
     return np.array([[int(v) for v in r[1:]] for r in rows], dtype=np.int8)
+
+
+def blosum62_24() -> np.ndarray:
+    """BLOSUM62 over ALPHABET24 as int8[24, 24] (symmetric)."""
+    m = np.zeros((24, 24), dtype=np.int8)
+    m[:20, :20] = blosum62()
+    rows = [ln.split() for ln in _BLOSUM62_EXTRA.strip().splitlines()]
+    if "".join(r[0] for r in rows) != "BZX*":
+        raise AssertionError("extra BLOSUM62 rows out of order")
+    for k, r in enumerate(rows):
+        m[20 + k, :] = [int(v) for v in r[1:]]
+        m[:, 20 + k] = m[20 + k, :]
+    return m
 
 
 def background_frequencies() -> np.ndarray:

@@ -51,13 +51,14 @@ def _load():
         lib = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         lib.sw_oracle_pair.restype = ctypes.c_int64
-        lib.sw_oracle_pair.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64]
+        lib.sw_oracle_pair.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64]
         lib.sw_oracle_scores.restype = ctypes.c_int
-        lib.sw_oracle_scores.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P,
+        lib.sw_oracle_scores.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, ctypes.c_int64,
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
         lib.sw_oracle_align.restype = ctypes.c_int64
         lib.sw_oracle_align.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
-                                        P, ctypes.c_char_p, ctypes.c_int64]
+                                        ctypes.c_int64, P, ctypes.c_char_p, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -66,11 +67,18 @@ def _i8(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.int8))
 
 
+def _matrix(sm):
+    """int8 square substitution matrix (alphabet x alphabet, indexed [query, subject])."""
+    sm = _i8(sm)
+    assert sm.ndim == 2 and sm.shape[0] == sm.shape[1] and sm.shape[0] >= 1
+    return sm
+
+
 def pair(q, d, sm, go: int, ge: int) -> int:
-    """Score of one pair; q, d residue codes 0..19, sm int8[20,20] indexed [query, subject]."""
-    q, d, sm = _i8(q), _i8(d), _i8(sm)
-    assert sm.shape == (20, 20)
-    v = _load().sw_oracle_pair(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, int(go), int(ge))
+    """Score of one pair; q, d residue codes 0..A-1, sm int8[A,A] indexed [query, subject]."""
+    q, d, sm = _i8(q), _i8(d), _matrix(sm)
+    v = _load().sw_oracle_pair(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, sm.shape[0],
+                               int(go), int(ge))
     if v < 0:
         raise MemoryError("oracle allocation failed")
     return int(v)
@@ -79,7 +87,7 @@ def pair(q, d, sm, go: int, ge: int) -> int:
 def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | None = None) -> np.ndarray:
     """int64 scores of query ``q`` against subjects ``idx`` (default: all) of a
     database given by concatenated ``residues`` and ``offsets[n+1]``."""
-    q, residues, sm = _i8(q), _i8(residues), _i8(sm)
+    q, residues, sm = _i8(q), _i8(residues), _matrix(sm)
     offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     n = offsets.size - 1
     if idx is None:
@@ -94,7 +102,7 @@ def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | 
         return out
     threads = threads or os.cpu_count() or 1
     rc = _load().sw_oracle_scores(q.ctypes.data, q.size, residues.ctypes.data, offsets.ctypes.data,
-                                  idx_ptr, count, sm.ctypes.data, int(go), int(ge), int(threads),
+                                  idx_ptr, count, sm.ctypes.data, sm.shape[0], int(go), int(ge), int(threads),
                                   out.ctypes.data)
     if rc != 0:
         raise RuntimeError("oracle failed (allocation or thread creation)")
@@ -142,12 +150,12 @@ def align(q, d, sm, go: int, ge: int) -> dict:
     q_end, s_begin, s_end (0-based, end exclusive) and ``ops``: 'M' for an
     aligned residue pair, 'I' for a query residue against a gap, 'D' for a
     subject residue against a gap."""
-    q, d, sm = _i8(q), _i8(d), _i8(sm)
-    assert sm.shape == (20, 20)
+    q, d, sm = _i8(q), _i8(d), _matrix(sm)
     out = np.zeros(5, dtype=np.int64)
     cap = int(q.size + d.size + 1)
     buf = ctypes.create_string_buffer(cap)
-    n = _load().sw_oracle_align(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, int(go), int(ge),
+    n = _load().sw_oracle_align(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, sm.shape[0],
+                                int(go), int(ge),
                                 out.ctypes.data, buf, cap)
     if n < 0:
         raise MemoryError("oracle allocation failed")

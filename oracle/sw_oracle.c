@@ -27,11 +27,11 @@
 
 static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
 
-/* Score of one (query, subject) pair.  q and d hold residue codes 0..19,
- * sm is the 20x20 substitution matrix row-major with rows indexed by the
- * query residue: SM(a, b) = sm[a * 20 + b].  Returns -1 on allocation failure. */
+/* Score of one (query, subject) pair.  q and d hold residue codes 0..a-1,
+ * sm is the a x a substitution matrix row-major with rows indexed by the
+ * query residue: SM(x, y) = sm[x * a + y].  Returns -1 on allocation failure. */
 int64_t sw_oracle_pair(const int8_t* q, int64_t m, const int8_t* d, int64_t n,
-                       const int8_t* sm, int64_t go, int64_t ge)
+                       const int8_t* sm, int64_t a, int64_t go, int64_t ge)
 {
     if (m <= 0 || n <= 0) return 0;
     /* Hup[j] = H[i-1][j] and Fup[j] = F[i-1][j] for the row above; row 0 is zero. */
@@ -46,7 +46,7 @@ int64_t sw_oracle_pair(const int8_t* q, int64_t m, const int8_t* d, int64_t n,
         for (int64_t j = 1; j <= n; ++j) {
             int64_t E = max2(Hleft - go, Eleft - ge);                 /* Eq. 2 */
             int64_t F = max2(Hup[j] - go, Fup[j] - ge);               /* Eq. 3 */
-            int64_t H = Hdiag + (int64_t)sm[q[i - 1] * 20 + d[j - 1]];
+            int64_t H = Hdiag + (int64_t)sm[q[i - 1] * a + d[j - 1]];
             H = max2(H, E);
             H = max2(H, F);
             H = max2(H, 0);                                           /* Eq. 1 */
@@ -68,7 +68,7 @@ typedef struct {
     const int8_t* q; int64_t m;
     const int8_t* res; const int64_t* offsets;
     const int64_t* idx; int64_t count;
-    const int8_t* sm; int64_t go, ge;
+    const int8_t* sm; int64_t a, go, ge;
     int64_t* out;
     int64_t next;               /* shared work counter */
     pthread_mutex_t lock;
@@ -85,7 +85,7 @@ static void* worker(void* arg)
         if (k >= J->count) break;
         int64_t s = J->idx ? J->idx[k] : k;
         int64_t b = J->offsets[s], e = J->offsets[s + 1];
-        int64_t v = sw_oracle_pair(J->q, J->m, J->res + b, e - b, J->sm, J->go, J->ge);
+        int64_t v = sw_oracle_pair(J->q, J->m, J->res + b, e - b, J->sm, J->a, J->go, J->ge);
         if (v < 0) J->failed = 1;
         J->out[k] = v;
     }
@@ -97,13 +97,13 @@ static void* worker(void* arg)
  * out[k] receives the score of subject idx[k].  nthreads <= 0 means 1.
  * Returns 0 on success, -1 on allocation or thread failure. */
 int sw_oracle_scores(const int8_t* q, int64_t m, const int8_t* res, const int64_t* offsets,
-                     const int64_t* idx, int64_t count, const int8_t* sm, int64_t go, int64_t ge,
+                     const int64_t* idx, int64_t count, const int8_t* sm, int64_t a, int64_t go, int64_t ge,
                      int32_t nthreads, int64_t* out)
 {
     job_t J;
     memset(&J, 0, sizeof J);
     J.q = q; J.m = m; J.res = res; J.offsets = offsets; J.idx = idx; J.count = count;
-    J.sm = sm; J.go = go; J.ge = ge; J.out = out;
+    J.sm = sm; J.a = a; J.go = go; J.ge = ge; J.out = out;
     pthread_mutex_init(&J.lock, NULL);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -140,7 +140,7 @@ int sw_oracle_scores(const int8_t* q, int64_t m, const int8_t* res, const int64_
  * end exclusive); ops[0..len) holds the operations from the first aligned
  * residue pair to the last.  Returns len, -1 on allocation failure, -2 if
  * cap < len. */
-int64_t sw_oracle_align(const int8_t* q, int64_t m, const int8_t* d, int64_t n, const int8_t* sm,
+int64_t sw_oracle_align(const int8_t* q, int64_t m, const int8_t* d, int64_t n, const int8_t* sm, int64_t a,
                         int64_t go, int64_t ge, int64_t* out, char* ops, int64_t cap)
 {
     for (int k = 0; k < 5; ++k) out[k] = 0;
@@ -156,7 +156,7 @@ int64_t sw_oracle_align(const int8_t* q, int64_t m, const int8_t* d, int64_t n, 
         for (int64_t j = 1; j <= n; ++j) {
             const int64_t e = max2((int64_t)H[i * w + j - 1] - go, (int64_t)E[i * w + j - 1] - ge);      /* Eq. 2 */
             const int64_t f = max2((int64_t)H[(i - 1) * w + j] - go, (int64_t)F[(i - 1) * w + j] - ge);  /* Eq. 3 */
-            int64_t h = (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * 20 + d[j - 1]];
+            int64_t h = (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * a + d[j - 1]];
             h = max2(max2(h, e), max2(f, 0));                                                          /* Eq. 1 */
             E[i * w + j] = (int32_t)e;
             F[i * w + j] = (int32_t)f;
@@ -170,7 +170,7 @@ int64_t sw_oracle_align(const int8_t* q, int64_t m, const int8_t* d, int64_t n, 
         if (state == 0) {
             const int64_t h = H[i * w + j];
             if (h == 0 || i == 0 || j == 0) break;
-            if (h == (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * 20 + d[j - 1]]) {
+            if (h == (int64_t)H[(i - 1) * w + j - 1] + sm[q[i - 1] * a + d[j - 1]]) {
                 rev[len++] = 'M';
                 --i; --j;
             } else if (h == E[i * w + j]) {

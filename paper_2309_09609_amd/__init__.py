@@ -105,6 +105,15 @@ def _host_i64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
 
 
+def _square(subst) -> np.ndarray:
+    """Substitution matrix as flat int8, checked to be square (alphabet x alphabet, alphabet <= 24)."""
+    sm = _host_i8(subst)
+    a = int(round(np.sqrt(sm.size)))
+    if sm.size == 0 or a * a != sm.size or a > 24 or (sm.ndim == 2 and sm.shape[0] != sm.shape[1]):
+        raise ValueError("substitution matrix must be square, at most 24 x 24")
+    return sm.reshape(-1)
+
+
 def _ptr(a) -> ctypes.c_void_p:
     return ctypes.c_void_p(a.ctypes.data if isinstance(a, np.ndarray) else a.data_ptr())
 
@@ -113,18 +122,21 @@ def _ptr(a) -> ctypes.c_void_p:
 class PackOpts(ctypes.Structure):
     _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
                 ("rerun_threshold", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
-                ("unit_share", ctypes.c_int32), ("lane_pack", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("unit_share", ctypes.c_int32), ("lane_pack", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
-               unit_share=0, lane_pack=0) -> ctypes.c_void_p:
+               unit_share=0, lane_pack=0, alphabet=0) -> ctypes.c_void_p:
     """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
-    ``force_lanes``, ``rerun_threshold`` and ``rows_per_lane`` are tuning/test hooks (see sw_pack_opts)."""
+    ``alphabet`` is the residue alphabet size (0 = 20); ``force_lanes``, ``rerun_threshold`` and
+    ``rows_per_lane`` are tuning/test hooks (see sw_pack_opts)."""
     lib = load()
     offs = _host_i64(h_offsets)
     n = offs.size - 1
     h = ctypes.c_void_p()
-    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack))
+    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack),
+                    int(alphabet))
     _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
                           _stream(stream), ctypes.byref(h)))
     return h
@@ -133,9 +145,7 @@ def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshol
 def sw_search(query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, stream=None):
     lib = load()
     q = _host_i8(query)
-    sm = _host_i8(subst).reshape(-1)
-    if sm.size != 400:
-        raise ValueError("substitution matrix must be 20x20")
+    sm = _square(subst)
     offs = None if h_offsets is None else _host_i64(h_offsets)
     _check(lib.sw_search(_ptr(q), q.size, handle, None if offs is None else _ptr(offs), int(n), _ptr(sm),
                          int(gap_open), int(gap_extend), ctypes.c_void_p(d_scores_out.data_ptr()), _stream(stream)))
@@ -152,7 +162,7 @@ def sw_search_batch(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, 
     lib = load()
     q = _host_i8(h_queries)
     qo = _host_i64(h_qoffsets)
-    sm = _host_i8(subst).reshape(-1)
+    sm = _square(subst)
     P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
     _check(lib.sw_search_batch(_ptr(q), _ptr(qo), qo.size - 1, handle, _ptr(sm), int(gap_open), int(gap_extend),
                                int(k), P(d_scores), P(d_top_scores), P(d_top_index), _stream(stream)))
@@ -165,7 +175,7 @@ def sw_search_multi(h_queries, h_qoffsets, chunks, nchunks, handle, subst, gap_o
     q = _host_i8(h_queries)
     qo = _host_i64(h_qoffsets)
     ch = np.ascontiguousarray(np.asarray(chunks, dtype=np.int32))
-    sm = _host_i8(subst).reshape(-1)
+    sm = _square(subst)
     ptrs = (ctypes.c_void_p * max(len(d_scores_list), 1))(*[t.data_ptr() for t in d_scores_list])
     _check(lib.sw_search_multi(_ptr(q), _ptr(qo), qo.size - 1, _ptr(ch), int(nchunks), handle, _ptr(sm),
                                int(gap_open), int(gap_extend), ptrs, _stream(stream)))
@@ -176,7 +186,7 @@ class Database:
     """A packed, device-resident protein database."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
-                 rows_per_lane=0, unit_share=0, lane_pack=0):
+                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0):
         import torch
         self.offsets = _host_i64(offsets)
         self.n = self.offsets.size - 1
@@ -189,8 +199,9 @@ class Database:
         if d_res.numel() == 0:
             d_res = torch.zeros(1, dtype=torch.int8, device=device)
         self.device = d_res.device
+        self.alphabet = int(alphabet) if alphabet else 20
         self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
-                                 unit_share, lane_pack)
+                                 unit_share, lane_pack, alphabet)
         del d_res
 
     def close(self):
@@ -232,9 +243,17 @@ class Database:
         _check(load().sw_kernel_times(self.handle, _ptr(buf), 256, ctypes.byref(cnt)))
         return buf[: cnt.value].astype(np.float64)
 
+    def matrix(self, subst) -> np.ndarray:
+        """The substitution matrix as flat int8, checked against this database's alphabet."""
+        sm = _square(subst)
+        if sm.size != self.alphabet * self.alphabet:
+            raise ValueError(f"substitution matrix must be {self.alphabet} x {self.alphabet} for this database")
+        return sm
+
     def search(self, query, subst, gap_open=10, gap_extend=2, out=None, stream=None):
         """int32 tensor [n] of scores in database order."""
         import torch
+        subst = self.matrix(subst)
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
         sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
@@ -243,14 +262,17 @@ class Database:
     def align(self, query, subjects, subst, gap_open=10, gap_extend=2, stream=None):
         """Optimal local alignments of ``query`` against the given subject indices
         (see ``sw_align``)."""
+        subst = self.matrix(subst)
         subs = _host_i64(subjects)
         lens = np.diff(self.offsets)
-        longest = int(lens[subs].max()) if subs.size else 0
+        # out-of-range indices are left for the library to reject
+        longest = int(lens[np.clip(subs, 0, self.n - 1)].max()) if subs.size and self.n > 0 else 0
         return sw_align(query, self.handle, subs, subst, gap_open, gap_extend, longest, stream)
 
     def search_batch(self, queries, subst, gap_open=10, gap_extend=2, k=10, keep_scores=True, stream=None):
         """(scores [nq, n] or None, top scores [nq, k], top indices [nq, k])."""
         import torch
+        subst = self.matrix(subst)
         qs = [_host_i8(q) for q in queries]
         qo = np.zeros(len(qs) + 1, dtype=np.int64)
         qo[1:] = np.cumsum([q.size for q in qs])
@@ -271,8 +293,7 @@ def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stre
     the subject lengths (sizes the operation buffer)."""
     q = _host_i8(query)
     subs = _host_i64(subjects)
-    sm = _host_i8(subst)
-    assert sm.shape == (20, 20)
+    sm = _square(subst)
     stride = int(q.size + longest + 1)
     out = (Alignment * max(subs.size, 1))()
     ops = ctypes.create_string_buffer(max(subs.size, 1) * stride)

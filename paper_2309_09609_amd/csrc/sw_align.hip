@@ -45,12 +45,12 @@ __device__ __forceinline__ bool end_before(int s, int i, int j, int t, int k, in
 }
 
 __global__ __launch_bounds__(64) void k_align_fill(const AlignPair* pairs, const int8_t* query, int m,
-                                                   const int8_t* subst, int go, int ge, uint8_t* dirs,
+                                                   const int8_t* subst, int A, int go, int ge, uint8_t* dirs,
                                                    int32_t* bnd, int32_t* best) {
-    __shared__ int8_t sm[400];
+    __shared__ int8_t sm[kMaxAlphabet * kMaxAlphabet];
     const AlignPair P = pairs[blockIdx.x];
     const int b = threadIdx.x;
-    for (int e = b; e < 400; e += 64) sm[e] = subst[e];
+    for (int e = b; e < A * A; e += 64) sm[e] = subst[e];
     __syncthreads();
     const int n = P.n;
     const uint8_t* res = P.residues;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64) void k_align_fill(const AlignPair* pairs, const
                     const int e = max(eo, ee);                   // Eq. 2
                     const int fo = hu - go, fe = fu - ge;
                     const int f = max(fo, fe);                   // Eq. 3
-                    const int hd = dg + (qc[r] >= 0 ? (int)sm[qc[r] * 20 + d] : 0);
+                    const int hd = dg + (qc[r] >= 0 ? (int)sm[qc[r] * A + d] : 0);
                     const int h = max(max(hd, e), max(f, 0));    // Eq. 1
                     const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
                     bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
@@ -184,11 +184,11 @@ __global__ void k_align_trace(const AlignPair* pairs, int npairs, int m, const u
     info[4 * k + 3] = status;
 }
 
-hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int go,
+hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
                         int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
                         int64_t* info, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64), 0, st, pairs, query, m, subst, go, ge, dirs, bnd, best);
+    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64), 0, st, pairs, query, m, subst, A, go, ge, dirs, bnd, best);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_align_trace, dim3((npairs + 63) / 64), dim3(64), 0, st, pairs, npairs, m, dirs, best, ops,

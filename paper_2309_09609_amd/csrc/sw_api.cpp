@@ -33,13 +33,13 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
-hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int go,
+hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
                         int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
                         int64_t* info, hipStream_t st);
 int64_t align_dir_bytes(int m, int64_t n);
-hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
+hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st);
-hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
+hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err, hipStream_t st);
 hipError_t launch_topk(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
@@ -189,6 +189,7 @@ struct sw_db {
     double unit_share = 0.25;         // largest unit / one wave's share of a search
     int32_t sat = kSat16;             // rerun threshold
     int lane_pack = 1;                // 1: subject pairs per lane; 2: query pairs per lane (several queries)
+    int alphabet = 20;                // residue codes 0..alphabet-1; matrices are alphabet x alphabet
     // statistics and timing
     int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
     bool timing = false;
@@ -528,14 +529,14 @@ sw_status ensure_workspace(sw_db* db) {
     return SW_OK;
 }
 
-// Layout of the staging buffer: [QDesc x nq][qoff x nq][subst 400][queries].
+// Layout of the staging buffer: [QDesc x nq][qoff x nq][subst, kMaxAlphabet^2 bytes][queries].
 struct StageLayout { size_t off_qoff, off_sm, total; int64_t prof_elems; int max_mp; };
 
 StageLayout stage_layout(const int64_t* h_qoffsets, int nq) {
     StageLayout L{};
     L.off_qoff = round_up(sizeof(QDesc) * nq, 64);
     L.off_sm = L.off_qoff + round_up(sizeof(int64_t) * nq, 64);
-    L.total = L.off_sm + 400 + (h_qoffsets[nq] - h_qoffsets[0]);
+    L.total = L.off_sm + kMaxAlphabet * kMaxAlphabet + (h_qoffsets[nq] - h_qoffsets[0]);
     L.max_mp = kProfRowAlign;
     for (int q = 0; q < nq; ++q) {
         const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
@@ -570,9 +571,9 @@ sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries
         prof_off += (int64_t)kNRes * mp;
         qo[q] = h_qoffsets[q] - h_qoffsets[0];
     }
-    memcpy(h + L.off_sm, subst, 400);
+    memcpy(h + L.off_sm, subst, (size_t)db->alphabet * db->alphabet);
     const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
-    if (qbytes) memcpy(h + L.off_sm + 400, h_queries + h_qoffsets[0], qbytes);
+    if (qbytes) memcpy(h + L.off_sm + kMaxAlphabet * kMaxAlphabet, h_queries + h_qoffsets[0], qbytes);
     HIP_TRY(hipMemcpyAsync(db->stage.p, h, L.total, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(db->hstage.done, st));
     db->hstage.pending = true;
@@ -592,7 +593,7 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
                   int64_t n, int64_t rerun_cap, int k, int32_t* top_s, int64_t* top_i, hipStream_t st,
                   bool time_sweep) {
     int32_t* ctr = db->counters.as<int32_t>();
-    HIP_TRY(launch_profile(S.sm_q, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
     const WgItem* d_items = plan.items.as<WgItem>();
     SweepArgs a{};
     a.items = d_items;
@@ -742,6 +743,9 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
     if (hipGetDevice(&db->device) != hipSuccess) return bail(fail(SW_E_HIP, "no current HIP device"));
     sw_status so = apply_opts(db, opts);
     if (so != SW_OK) return bail(so);
+    if (opts && (opts->alphabet < 0 || opts->alphabet > kMaxAlphabet))
+        return bail(fail(SW_E_INVALID, "alphabet must be 0 (= 20) or 1..%d", kMaxAlphabet));
+    db->alphabet = (opts && opts->alphabet > 0) ? opts->alphabet : 20;
     db->n = n;
     db->off_first = n > 0 ? h_offsets[0] : 0;
     db->off_last = n > 0 ? h_offsets[n] : 0;
@@ -803,13 +807,13 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         step(hipMemcpyAsync(d_slen.p, slen.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_gdw.p, gdw.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_err.p, &zero, 4, hipMemcpyHostToDevice, st));
-        step(launch_interleave(d_residues, d_soff.as<int64_t>(), d_slen.as<int32_t>(), n, db->groups.as<GroupRec>(),
+        step(launch_interleave(d_residues, d_soff.as<int64_t>(), d_slen.as<int32_t>(), n, db->alphabet, db->groups.as<GroupRec>(),
                                d_gdw.as<int64_t>(), G, db->image.as<uint32_t>(), base / 4, d_err.as<int32_t>(), st));
         step(hipMemcpyAsync(&herr, d_err.p, 4, hipMemcpyDeviceToHost, st));
         step(hipStreamSynchronize(st));
         d_soff.release(); d_slen.release(); d_gdw.release(); d_err.release();
         if (e != hipSuccess) return bail(fail(SW_E_HIP, "packing: %s", hipGetErrorString(e)));
-        if (herr) return bail(fail(SW_E_RESIDUE, "database residue code outside 0..19"));
+        if (herr) return bail(fail(SW_E_RESIDUE, "database residue code outside 0..%d", db->alphabet - 1));
     }
     *out = db;
     return SW_OK;
@@ -869,7 +873,7 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
     if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
     if (n > 0 && !d_scores_out) return fail(SW_E_INVALID, "scores_out is NULL");
     for (int32_t i = 0; i < qlen; ++i)
-        if (h_query[i] < 0 || h_query[i] >= 20) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..19", h_query[i], i);
+        if (h_query[i] < 0 || h_query[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
     if (n == 0) return SW_OK;
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
@@ -915,7 +919,7 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
     }
     if (nq > 0)
         for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
-            if (h_queries[i] < 0 || h_queries[i] >= 20) return fail(SW_E_RESIDUE, "query residue outside 0..19 at %lld", (long long)i);
+            if (h_queries[i] < 0 || h_queries[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue outside 0..%d at %lld", db->alphabet - 1, (long long)i);
     if (nq == 0) return SW_OK;
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
@@ -1003,7 +1007,7 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
     }
     if (nq > 0)
         for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
-            if (h_queries[i] < 0 || h_queries[i] >= 20) return fail(SW_E_RESIDUE, "query residue outside 0..19 at %lld", (long long)i);
+            if (h_queries[i] < 0 || h_queries[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue outside 0..%d at %lld", db->alphabet - 1, (long long)i);
     if (nq == 0 || db->n == 0) return SW_OK;
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
@@ -1086,7 +1090,7 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
     if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
     if (nsub > 0 && (!h_subjects || !h_out || !h_ops)) return fail(SW_E_INVALID, "NULL subjects or outputs");
     for (int32_t i = 0; i < qlen; ++i)
-        if (h_query[i] < 0 || h_query[i] >= 20) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..19", h_query[i], i);
+        if (h_query[i] < 0 || h_query[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
     int64_t longest = 0;
     for (int32_t k = 0; k < nsub; ++k) {
         if (h_subjects[k] < 0 || h_subjects[k] >= db->n) return fail(SW_E_INVALID, "subject index %lld outside 0..n-1", (long long)h_subjects[k]);
@@ -1133,7 +1137,7 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
         const size_t o_info = o_best + round_up(12 * (size_t)np, 256);
         const size_t o_query = o_info + round_up(32 * (size_t)np, 256);
         const size_t o_sm = o_query + round_up(qlen, 256);
-        const size_t o_ops = o_sm + 512;
+        const size_t o_ops = o_sm + 1024;
         const size_t misc = o_ops + (size_t)np * stride;
         HIP_TRY(db->align_dirs.reserve((size_t)std::max<int64_t>(dir_total, 256)));
         HIP_TRY(db->align_bnd.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bnd_total, 64)));
@@ -1141,9 +1145,9 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
         char* mb = db->align_misc.as<char>();
         HIP_TRY(hipMemcpyAsync(mb + o_pairs, pairs.data(), sizeof(AlignPair) * np, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(mb + o_query, h_query, qlen, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(mb + o_sm, h_subst, 400, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(mb + o_sm, h_subst, (size_t)db->alphabet * db->alphabet, hipMemcpyHostToDevice, st));
         HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, reinterpret_cast<int8_t*>(mb + o_query), qlen,
-                             reinterpret_cast<int8_t*>(mb + o_sm), gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
+                             reinterpret_cast<int8_t*>(mb + o_sm), db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
                              db->align_bnd.as<int32_t>(), reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
                              reinterpret_cast<int64_t*>(mb + o_info), st));
         std::vector<int32_t> best(3 * (size_t)np);

@@ -6,7 +6,8 @@
 namespace sw {
 
 // ---------------------------------------------------------------- constants
-constexpr int kNRes = 21;          // profile rows: padding (image code 0) and the 20 residues (codes 1..20)
+constexpr int kMaxAlphabet = 24;  // residue codes 0..alphabet-1, alphabet <= 24 (20 amino acids + B, Z, X, *)
+constexpr int kNRes = kMaxAlphabet + 1;   // profile rows: padding (image code 0) and residues (codes 1..24)
 constexpr int kPadCode = 0;        // image byte of padding columns (residue codes are stored + 1)
 constexpr int16_t kPadScore = -1024;   // substitution score of padding (any value <= 0 is invisible)
 constexpr int kGroupPairs = 64;    // subject pairs per group (one per lane of a wave)

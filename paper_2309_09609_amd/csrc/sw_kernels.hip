@@ -629,32 +629,32 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
 }
 
 // ------------------------------------------------------------ query profile
-// prof[d][i] = SM(Q[i], d - 1) for image codes d = 1..20 and i < m; kPadScore
-// for d = 0 (padding) and past m.  One staging buffer holds the 20x20 matrix
-// followed by the query codes.
+// prof[d][i] = SM(Q[i], d - 1) for image codes d = 1..A and i < m; kPadScore
+// for d = 0 (padding), d > A and past m.  One staging buffer holds the A x A
+// matrix (in a kMaxAlphabet^2-byte region) followed by the query codes.
 // Thread 0 also zeroes the launch counters (they are consumed by later kernels
 // on the same stream).
-__global__ void k_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff,
+__global__ void k_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff,
                           int16_t* prof, int32_t* counters, int ncounters) {
     const int q = blockIdx.y;
     if (q == 0 && blockIdx.x == 0 && threadIdx.x < ncounters) counters[threadIdx.x] = 0;
     if (q >= nq) return;
     const QDesc Q = qd[q];
     const int8_t* sm = stage;
-    const int8_t* query = stage + 400 + qoff[q];
+    const int8_t* query = stage + kMaxAlphabet * kMaxAlphabet + qoff[q];
     const int64_t total = (int64_t)kNRes * Q.mp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int d = (int)(e / Q.mp);
         const int i = (int)(e - (int64_t)d * Q.mp);
         int16_t v = kPadScore;
-        if (d >= 1 && i < Q.m) v = sm[query[i] * 20 + (d - 1)];
+        if (d >= 1 && d <= A && i < Q.m) v = sm[query[i] * A + (d - 1)];
         prof[Q.prof_off + e] = v;
     }
 }
 
 // ------------------------------------------------------------ database interleave
 // One thread per output dword: 4 consecutive columns of one subject.
-__global__ void k_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
+__global__ void k_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err) {
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total_dw; w += (int64_t)gridDim.x * blockDim.x) {
@@ -677,7 +677,7 @@ __global__ void k_interleave(const int8_t* res, const int64_t* soff, const int32
                 uint32_t v = kPadCode;
                 if (col < len) {
                     const int r = res[off + col];
-                    if (r < 0 || r >= 20) atomicOr(err, 1);
+                    if (r < 0 || r >= A) atomicOr(err, 1);
                     else v = (uint32_t)r + 1;
                 }
                 word |= v << (8 * kk);
@@ -851,20 +851,20 @@ hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
 }
 
-hipError_t launch_profile(const int8_t* stage, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
+hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st) {
     const int bx = (int)std::min<int64_t>(((int64_t)kNRes * max_mp + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_profile, dim3(bx, std::max(nq, 1)), dim3(256), 0, st, stage, qd, nq, qoff, prof,
+    hipLaunchKernelGGL(k_profile, dim3(bx, std::max(nq, 1)), dim3(256), 0, st, stage, A, qd, nq, qoff, prof,
                        counters, ncounters);
     return hipGetLastError();
 }
 
-hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n,
+hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err, hipStream_t st) {
     const int64_t blocks = std::min<int64_t>((total_dw + 255) / 256, 65536);
     hipLaunchKernelGGL(k_interleave, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, res, soff, slen, n,
-                       groups, gdw, ngroups, image, total_dw, err);
+                       A, groups, gdw, ngroups, image, total_dw, err);
     return hipGetLastError();
 }
 

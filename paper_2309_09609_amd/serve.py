@@ -63,7 +63,7 @@ class GpuEngine:
         import torch
         import paper_2309_09609_amd as sw
         self.sw, self.torch = sw, torch
-        self.db, self.subst, self.go, self.ge, self.k, self.stream = db, subst, gap_open, gap_extend, k, stream
+        self.db, self.subst, self.go, self.ge, self.k, self.stream = db, db.matrix(subst), gap_open, gap_extend, k, stream
         self.slot_bytes = 4 * max(db.n, 1)
 
     def new_slot(self):

@@ -121,3 +121,20 @@ def test_invalid_requests(gpu, blosum):
         gpu.sw_align(synth.small_query(seed=93, m=10), D.handle, np.array([longest], np.int64), blosum, 10, 2,
                      longest=0)
     D.close()
+
+
+def test_alignments_with_the_extended_alphabet(gpu):
+    from inputs import blosum62_24
+    sm = blosum62_24()
+    rng = np.random.default_rng(240)
+    lens = rng.integers(1, 500, 30)
+    res = rng.integers(0, 24, int(lens.sum())).astype(np.int8)
+    offs = np.zeros(lens.size + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(res, offs)
+    q = rng.integers(0, 24, 300).astype(np.int8)
+    q[50:150] = res[offs[3]:offs[3] + 100] if lens[3] >= 100 else q[50:150]
+    D = gpu.Database(res, offs, alphabet=24)
+    idx = list(range(db.n))
+    _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24")
+    D.close()

@@ -423,3 +423,57 @@ def test_full_size_workload2_sampled(gpu, blosum):
         if k:
             assert (want[np.isin(idx, db.sentinels)] > 32767).all()
     D.close()
+
+
+def test_extended_alphabet(gpu):
+    """24-letter alphabet (B, Z, X, * after the 20 residues) with the full BLOSUM62."""
+    import torch
+    from inputs import blosum62_24
+    sm = blosum62_24()
+    rng = np.random.default_rng(24)
+    lens = rng.integers(1, 600, 300)
+    res = rng.integers(0, 24, int(lens.sum())).astype(np.int8)
+    offs = np.zeros(lens.size + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    q = rng.integers(0, 24, 333).astype(np.int8)
+    for lanes in (0, 1, 16):
+        D = gpu.Database(res, offs, alphabet=24, force_lanes=lanes)
+        got = D.search(q, sm, 10, 2)
+        torch.cuda.synchronize()
+        assert_equal_scores(got.cpu().numpy(), oracle.scores(q, res, offs, sm, 10, 2), f"alphabet 24 lanes={lanes}")
+        D.close()
+    D = gpu.Database(res, offs, alphabet=24, lane_pack=2)
+    qs = [q, rng.integers(0, 24, 100).astype(np.int8), rng.integers(0, 24, 700).astype(np.int8)]
+    scores, _, _ = D.search_batch(qs, sm, 10, 2, k=0)
+    torch.cuda.synchronize()
+    for i, x in enumerate(qs):
+        assert_equal_scores(scores[i].cpu().numpy(), oracle.scores(x, res, offs, sm, 10, 2), f"alphabet 24 batch q{i}")
+    with pytest.raises(ValueError):
+        D.search(q, np.zeros((20, 20), np.int8), 10, 2)        # matrix of the wrong alphabet
+    D.close()
+
+
+def test_small_alphabet(gpu):
+    """A 4-letter alphabet with a +5/-4 matrix (nucleotide-style scoring)."""
+    import torch
+    sm = np.full((4, 4), -4, np.int8)
+    np.fill_diagonal(sm, 5)
+    rng = np.random.default_rng(4)
+    lens = rng.integers(1, 900, 200)
+    res = rng.integers(0, 4, int(lens.sum())).astype(np.int8)
+    offs = np.zeros(lens.size + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    q = rng.integers(0, 4, 500).astype(np.int8)
+    D = gpu.Database(res, offs, alphabet=4)
+    got = D.search(q, sm, 12, 4)
+    torch.cuda.synchronize()
+    assert_equal_scores(got.cpu().numpy(), oracle.scores(q, res, offs, sm, 12, 4), "alphabet 4")
+    with pytest.raises(gpu.SwError):
+        D.search(np.array([0, 4], np.int8), sm, 12, 4)        # code outside the alphabet
+    D.close()
+    bad = res.copy()
+    bad[7] = 4
+    with pytest.raises(gpu.SwError):
+        gpu.Database(bad, offs, alphabet=4)
+    with pytest.raises(gpu.SwError):
+        gpu.Database(res, offs, alphabet=25)

@@ -111,3 +111,18 @@ def test_golden_closed_forms(blosum):
         assert oracle.pair(expand(q), expand(d), sm, int(go), int(ge)) == int(s), line
         n += 1
     assert n >= 5
+
+
+def test_blosum62_extended_alphabet():
+    from inputs import ALPHABET24, blosum62, blosum62_24
+    m = blosum62_24()
+    assert ALPHABET24 == "ARNDCQEGHILKMFPSTWYVBZX*"
+    assert m.shape == (24, 24) and (m == m.T).all()
+    assert (m[:20, :20] == blosum62()).all()
+    b = blosum62()
+    N, D, Q, E = (ALPHABET24.index(c) for c in "NDQE")
+    # the ambiguity codes lie between the scores of the residues they stand for
+    assert ((m[20, :20] >= np.minimum(b[N], b[D])) & (m[20, :20] <= np.maximum(b[N], b[D]))).all()
+    assert ((m[21, :20] >= np.minimum(b[Q], b[E])) & (m[21, :20] <= np.maximum(b[Q], b[E]))).all()
+    assert (m[22, :23] <= 0).all() and m[22, 22] == -1
+    assert (m[23, :23] == -4).all() and m[23, 23] == 1
