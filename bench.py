@@ -101,7 +101,7 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     """Served form: continuous batching vs plain FIFO on one Poisson trace."""
     import torch
     from inputs import synth
-    from paper_2309_09609_amd.serve import GpuEngine, Server, fifo_run
+    from paper_2309_09609_amd.serve import GpuEngine, Server, batch_run, fifo_run
     warm = 10
     qs = synth.workload5_queries(warm + args.requests + 5)
     cells = lambda q: int(q.size) * total_res  # noqa: E731
@@ -128,8 +128,20 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     rep = srv.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells)
     served = rep.summary()
     print(f"# served: {served}", file=sys.stderr, flush=True)
-    fifo = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells).summary()
+    fifo_rep = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells)
+    fifo = fifo_rep.summary()
     print(f"# plain FIFO: {fifo}", file=sys.stderr, flush=True)
+    D.tune(lane_pack=2)
+    batch_run(D, trace[:warm], arrivals[:warm] - arrivals[0], sm)
+    dyn_rep = batch_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells)
+    dyn = dyn_rep.summary()
+    D.tune()
+    print(f"# dynamic batching: {dyn}", file=sys.stderr, flush=True)
+    # every policy must return the same top-10 for every request
+    same = all(np.array_equal(fifo_rep.results[i][0], dyn_rep.results[i][0]) and
+               np.array_equal(fifo_rep.results[i][1], dyn_rep.results[i][1]) and
+               np.array_equal(fifo_rep.results[i][0], rep.results[i][0]) and
+               np.array_equal(fifo_rep.results[i][1], rep.results[i][1]) for i in fifo_rep.results)
     res = {
         "metric": METRIC, "value": round(served["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.requests,
         "warmup": warm, "ms_per_step": round(served["makespan_s"] / args.requests * 1e3, 3),
@@ -140,9 +152,10 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
                    "load_vs_plain": args.load, "chunks": args.chunks, "mem_budget_bytes": 2 << 30,
                    "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
         "latency": {"served_p50_s": round(served["p50_s"], 4), "served_p99_s": round(served["p99_s"], 4),
+                    "dynamic_batching_p50_s": round(dyn["p50_s"], 4), "dynamic_batching_p99_s": round(dyn["p99_s"], 4),
                     "plain_p50_s": round(fifo["p50_s"], 4), "plain_p99_s": round(fifo["p99_s"], 4),
                     "p99_gain": round(fifo["p99_s"] / served["p99_s"], 3) if served["p99_s"] > 0 else None},
-        "extra": {"served": served, "plain_fifo": fifo,
+        "extra": {"served": served, "plain_fifo": fifo, "dynamic_batching": dyn, "same_top10_all_policies": same,
                   "pct_int32_cell_peak": round(100 * served["gcups"] / perfmodel.mi355x_peak_gcups(), 2)},
     }
     D.close()

@@ -10,6 +10,11 @@ next iteration boundary, as soon as a slot is free and the memory budget
 overlaps on the device with the requests already in flight.  When a request
 has covered all chunks its top-k is taken and it retires, freeing its slot.
 
+``batch_run`` is dynamic batching: whenever the GPU is free, every waiting
+request (up to ``max_batch``) is searched against the whole database in one
+batched launch sequence, two queries per lane (query pairs), so a burst of
+arrivals costs less GPU time than the same requests one by one.
+
 ``fifo_run`` is the plain baseline on the same arrival trace: one search per
 request, in arrival order, each alone on the GPU.
 
@@ -196,3 +201,39 @@ def fifo_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, cloc
     first = float(np.min(arrivals)) if len(arrivals) else 0.0
     cells = int(sum(cells_per_query(q) for q in queries)) if cells_per_query else 0
     return ServeReport(lat, results, len(queries), 1, last - first, cells, [int(i) for i in order], busy)
+
+
+def batch_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, max_batch=16, clock=time.perf_counter,
+              sleep=time.sleep, cells_per_query=None) -> ServeReport:
+    """Dynamic batching (see the module docstring).  ``db`` should be tuned for
+    query pairs (``db.tune(lane_pack=2)``); results are identical either way."""
+    import torch
+    order = [int(i) for i in np.argsort(np.asarray(arrivals, dtype=np.float64), kind="stable")]
+    lat = np.zeros(len(queries))
+    results = {}
+    busy, iterations, biggest = 0.0, 0, 0
+    t0 = clock()
+    nxt, last = 0, 0.0
+    while nxt < len(order):
+        now = clock() - t0
+        if arrivals[order[nxt]] > now:
+            sleep(max(0.0, arrivals[order[nxt]] - now))
+            continue
+        batch = []
+        while nxt < len(order) and len(batch) < max_batch and arrivals[order[nxt]] <= clock() - t0:
+            batch.append(order[nxt])
+            nxt += 1
+        t_it = clock()
+        _, ts, ti = db.search_batch([queries[i] for i in batch], subst, gap_open, gap_extend, k=k, keep_scores=False)
+        torch.cuda.synchronize()
+        busy += clock() - t_it
+        iterations += 1
+        biggest = max(biggest, len(batch))
+        ts, ti = ts.cpu().numpy(), ti.cpu().numpy()
+        last = clock() - t0
+        for r, i in enumerate(batch):
+            results[i] = (ts[r], ti[r])
+            lat[i] = last - arrivals[i]
+    first = float(np.min(arrivals)) if len(arrivals) else 0.0
+    cells = int(sum(cells_per_query(q) for q in queries)) if cells_per_query else 0
+    return ServeReport(lat, results, iterations, biggest, last - first, cells, order, busy)

@@ -65,3 +65,19 @@ def test_server_under_tiny_memory_budget(gpu, blosum):
         ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 5)
         assert (rep.results[i][0] == ws).all() and (rep.results[i][1] == wi).all()
     D.close()
+
+
+def test_dynamic_batching_matches_the_oracle(gpu, blosum):
+    from paper_2309_09609_amd.serve import batch_run
+    db = synth.small_db(seed=79, n=2000, lo=20, hi=900, median=300)
+    D = gpu.Database(db.residues, db.offsets, lane_pack=2)
+    rng = np.random.default_rng(2)
+    qs = [synth.small_query(seed=300 + i, m=int(m)) for i, m in enumerate(rng.integers(1, 600, 11))]
+    arrivals = np.sort(rng.uniform(0, 0.02, len(qs)))
+    rep = batch_run(D, qs, arrivals, blosum, 10, 2, k=10, max_batch=4)
+    assert rep.iterations >= 3 and rep.max_active <= 4
+    for i, q in enumerate(qs):
+        ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 10)
+        s, idx = rep.results[i]
+        assert (s == ws).all() and (idx == wi).all(), i
+    D.close()
