@@ -44,71 +44,110 @@ __device__ __forceinline__ bool end_before(int s, int i, int j, int t, int k, in
     return s > t || (s == t && (i < k || (i == k && j < l)));
 }
 
+typedef __amdgpu_buffer_rsrc_t align_rsrc;
+
+// Raw buffer over [base, base + bytes): out-of-range loads return zeros.
+__device__ __forceinline__ align_rsrc align_buffer(const void* base, uint32_t bytes) {
+    const uint64_t p = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p), hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
+// Residues arrive 4 columns per dword two chunks ahead and the boundary row
+// one chunk ahead, so no step waits for memory.
 __global__ __launch_bounds__(64) void k_align_fill(const AlignPair* pairs, const int8_t* query, int m,
                                                    const int8_t* subst, int A, int go, int ge, uint8_t* dirs,
                                                    int32_t* bnd, int32_t* best) {
-    __shared__ int8_t sm[kMaxAlphabet * kMaxAlphabet];
+    // query profile of the current pass: prof[d][row], rows of lane b at bytes 4b .. 4b + 3 of each residue row
+    __shared__ __attribute__((aligned(16))) int8_t prof[kMaxAlphabet * kAlignPass];
     const AlignPair P = pairs[blockIdx.x];
     const int b = threadIdx.x;
-    for (int e = b; e < A * A; e += 64) sm[e] = subst[e];
-    __syncthreads();
     const int n = P.n;
-    const uint8_t* res = P.residues;
+    const int n4 = (n + 3) & ~3;                // columns rounded up to whole chunks
+    const align_rsrc img = align_buffer(P.residues, (uint32_t)(n4 >> 2) * kChunkBytes);
+    int32_t* bh = bnd + P.bnd_off;              // last row of the previous pass, 0-based columns: H, then F
+    int32_t* bf = bh + n4;
+    const align_rsrc bhr = align_buffer(bh, (uint32_t)n4 * 4), bfr = align_buffer(bf, (uint32_t)n4 * 4);
     uint32_t* dir = reinterpret_cast<uint32_t*>(dirs + P.dir_off);
-    int32_t* bh = bnd + P.bnd_off;              // H of the last row of the previous pass, columns 0..n
-    int32_t* bf = bh + (n + 1);                 // F of the same row
     int best_s = 0, best_i = 0, best_j = 0;     // wave-uniform after each pass
     const int passes = (m + kAlignPass - 1) / kAlignPass;
     const int nsteps = n + 63;
+    const int nloop = (nsteps + 3) >> 2;
+    const int coff = (-b) >> 2, csh = (-b) & 3;  // lane b works on 0-based columns 4c - b .. 4c - b + 3 in iteration c
+    auto chunk = [&](int c) { return __builtin_amdgcn_raw_buffer_load_b32(img, (uint32_t)(c * kChunkBytes), 0, 0); };
     for (int p = 0; p < passes; ++p) {
         const int row0 = p * kAlignPass + b * kAlignRows;     // 0-based first row of this lane
-        int qc[kAlignRows];
+        bool valid[kAlignRows];
 #pragma unroll
-        for (int r = 0; r < kAlignRows; ++r) qc[r] = row0 + r < m ? query[row0 + r] : -1;
+        for (int r = 0; r < kAlignRows; ++r) valid[r] = row0 + r < m;
+        __syncthreads();                        // the previous pass is done with the profile
+        for (int e = b; e < A * kAlignPass; e += 64) {
+            const int d = e / kAlignPass, row = p * kAlignPass + (e - d * kAlignPass);
+            prof[e] = row < m ? subst[query[row] * A + d] : (int8_t)0;
+        }
+        __syncthreads();
         int H[kAlignRows], E[kAlignRows], bs[kAlignRows], bj[kAlignRows];
 #pragma unroll
         for (int r = 0; r < kAlignRows; ++r) { H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
         int diag_top = 0;                       // H of the row above this lane's block, previous column
         int up_h = 0, up_f = 0;                 // bottom row of lane b-1 at this step's column
-        for (int t = 0; t < nsteps; ++t) {
-            const int j = t - b + 1;            // 1-based column of this lane
-            const bool active = j >= 1 && j <= n;
-            int htop = up_h, ftop = up_f;
-            if (b == 0) {
-                htop = (p > 0 && active) ? bh[j] : 0;
-                ftop = (p > 0 && active) ? bf[j] : 0;
-            }
-            int hbot = 0, fbot = 0;
-            if (active) {
-                const int d = (int)res[(int64_t)((j - 1) >> 2) * kChunkBytes + ((j - 1) & 3)] - 1;
-                int dg = diag_top, hu = htop, fu = ftop;
-                uint32_t bits = 0;
+        const uint32_t rd = (b == 0 && p > 0) ? 0u : 0x80000000u;   // only the first lane reads the boundary
+        uint32_t lo = chunk(coff), hi = chunk(coff + 1), nx = chunk(coff + 2);
+        uint4 vh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd, 0, 0));
+        uint4 vf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd, 0, 0));
+        for (int c = 0; c < nloop; ++c) {
+            const uint32_t nn = chunk(coff + c + 3);
+            const uint4 wh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd + 16u * (c + 1), 0, 0));
+            const uint4 wf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd + 16u * (c + 1), 0, 0));
+            const uint32_t rr = __builtin_amdgcn_alignbyte(hi, lo, csh);
+            const int th[4] = {(int)vh.x, (int)vh.y, (int)vh.z, (int)vh.w};
+            const int tf[4] = {(int)vf.x, (int)vf.y, (int)vf.z, (int)vf.w};
 #pragma unroll
-                for (int r = 0; r < kAlignRows; ++r) {
-                    const int hl = H[r];                         // H[i][j-1]
-                    const int eo = hl - go, ee = E[r] - ge;
-                    const int e = max(eo, ee);                   // Eq. 2
-                    const int fo = hu - go, fe = fu - ge;
-                    const int f = max(fo, fe);                   // Eq. 3
-                    const int hd = dg + (qc[r] >= 0 ? (int)sm[qc[r] * A + d] : 0);
-                    const int h = max(max(hd, e), max(f, 0));    // Eq. 1
-                    const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
-                    bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
-                    if (qc[r] >= 0 && h > bs[r]) { bs[r] = h; bj[r] = j; }
-                    dg = hl;
-                    H[r] = h;
-                    E[r] = e;
-                    hu = h;
-                    fu = f;
+            for (int u = 0; u < 4; ++u) {
+                const int t = 4 * c + u;
+                const int j = t - b + 1;        // 1-based column of this lane
+                const bool active = j >= 1 && j <= n;
+                const int htop = b == 0 ? th[u] : up_h;
+                const int ftop = b == 0 ? tf[u] : up_f;
+                int hbot = 0, fbot = 0;
+                if (active) {
+                    const int d = (int)((rr >> (8 * u)) & 0xffu) - 1;
+                    const uint32_t sv = *reinterpret_cast<const uint32_t*>(prof + d * kAlignPass + 4 * b);
+                    int dg = diag_top, hu = htop, fu = ftop;
+                    uint32_t bits = 0;
+#pragma unroll
+                    for (int r = 0; r < kAlignRows; ++r) {
+                        const int hl = H[r];                         // H[i][j-1]
+                        const int eo = hl - go, ee = E[r] - ge;
+                        const int e = max(eo, ee);                   // Eq. 2
+                        const int fo = hu - go, fe = fu - ge;
+                        const int f = max(fo, fe);                   // Eq. 3
+                        const int hd = dg + (int)(int8_t)(sv >> (8 * r));
+                        const int h = max(max(hd, e), max(f, 0));    // Eq. 1
+                        const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
+                        bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
+                        if (valid[r] && h > bs[r]) { bs[r] = h; bj[r] = j; }
+                        dg = hl;
+                        H[r] = h;
+                        E[r] = e;
+                        hu = h;
+                        fu = f;
+                    }
+                    dir[((int64_t)p * nsteps + t) * 64 + b] = bits;
+                    hbot = hu;
+                    fbot = fu;
+                    if (b == 63 && p + 1 < passes) { bh[j - 1] = hbot; bf[j - 1] = fbot; }
                 }
-                dir[((int64_t)p * nsteps + t) * 64 + b] = bits;
-                hbot = hu;
-                fbot = fu;
-                if (b == 63 && p + 1 < passes) { bh[j] = hbot; bf[j] = fbot; }
+                diag_top = htop;
+                up_h = (int)align_shr1((uint32_t)hbot);
+                up_f = (int)align_shr1((uint32_t)fbot);
             }
-            diag_top = htop;
-            up_h = (int)align_shr1((uint32_t)hbot);
-            up_f = (int)align_shr1((uint32_t)fbot);
+            lo = hi;
+            hi = nx;
+            nx = nn;
+            vh = wh;
+            vf = wf;
         }
         // this pass's first end cell, then the first over all passes
         int s = 0, ci = 0, cj = 0;
@@ -195,6 +234,8 @@ hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query,
                        ops_stride, info);
     return hipGetLastError();
 }
+
+int64_t align_bnd_words(int64_t n) { return 2 * ((n + 3) & ~(int64_t)3); }
 
 int64_t align_dir_bytes(int m, int64_t n) {
     const int64_t passes = (m + kAlignPass - 1) / kAlignPass;

@@ -37,6 +37,7 @@ hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query,
                         int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
                         int64_t* info, hipStream_t st);
 int64_t align_dir_bytes(int m, int64_t n);
+int64_t align_bnd_words(int64_t n);
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, int max_mp, hipStream_t st);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
@@ -1125,7 +1126,7 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
             P.bnd_off = bnd_total;
             pairs.push_back(P);
             dir_total += round_up(db_bytes, 256);
-            bnd_total += 2 * ((int64_t)nres + 1);
+            bnd_total += align_bnd_words(nres);
             n_max = std::max<int64_t>(n_max, nres);
             ++k1;
         }

@@ -81,7 +81,7 @@ struct AlignPair {
     const uint8_t* residues;  // the subject's first chunk in the image (+ 8 * pair + 4 * half of its group)
     int32_t n;                // subject length
     int64_t dir_off;          // byte offset of the pair's direction bytes
-    int64_t bnd_off;          // int32 offset of the pair's boundary row (2 * (n + 1) words)
+    int64_t bnd_off;          // int32 offset of the pair's boundary row (H then F, n rounded up to 4 words each)
 };
 
 }  // namespace sw
