@@ -55,7 +55,10 @@ def _load():
                                        ctypes.c_int64]
         lib.sw_oracle_scores.restype = ctypes.c_int
         lib.sw_oracle_scores.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64, P, ctypes.c_int64,
-                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P]
+        lib.sw_oracle_pair_mode.restype = ctypes.c_int64
+        lib.sw_oracle_pair_mode.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_int64]
         lib.sw_oracle_align.restype = ctypes.c_int64
         lib.sw_oracle_align.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int64, P, ctypes.c_char_p, ctypes.c_int64]
@@ -84,7 +87,22 @@ def pair(q, d, sm, go: int, ge: int) -> int:
     return int(v)
 
 
-def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | None = None) -> np.ndarray:
+MODES = {"local": 0, "global": 1, "semiglobal": 2}
+
+
+def pair_mode(q, d, sm, go: int, ge: int, mode: str) -> int:
+    """Score of one pair in ``mode`` ("local", "global" or "semiglobal"; see
+    ``sw_oracle_pair_mode``)."""
+    q, d, sm = _i8(q), _i8(d), _matrix(sm)
+    v = _load().sw_oracle_pair_mode(q.ctypes.data, q.size, d.ctypes.data, d.size, sm.ctypes.data, sm.shape[0],
+                                    int(go), int(ge), MODES[mode])
+    if v == -(1 << 63):
+        raise MemoryError("oracle allocation failed")
+    return int(v)
+
+
+def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | None = None,
+           mode: str = "local") -> np.ndarray:
     """int64 scores of query ``q`` against subjects ``idx`` (default: all) of a
     database given by concatenated ``residues`` and ``offsets[n+1]``."""
     q, residues, sm = _i8(q), _i8(residues), _matrix(sm)
@@ -102,7 +120,8 @@ def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | 
         return out
     threads = threads or os.cpu_count() or 1
     rc = _load().sw_oracle_scores(q.ctypes.data, q.size, residues.ctypes.data, offsets.ctypes.data,
-                                  idx_ptr, count, sm.ctypes.data, sm.shape[0], int(go), int(ge), int(threads),
+                                  idx_ptr, count, sm.ctypes.data, sm.shape[0], int(go), int(ge), MODES[mode],
+                                  int(threads),
                                   out.ctypes.data)
     if rc != 0:
         raise RuntimeError("oracle failed (allocation or thread creation)")

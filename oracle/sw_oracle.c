@@ -63,12 +63,69 @@ int64_t sw_oracle_pair(const int8_t* q, int64_t m, const int8_t* d, int64_t n,
     return S;
 }
 
+/* ---------------- global and semi-global variants ----------------
+ * The same recurrence without the local 0 in Eq. 1 and with gap borders:
+ *   H[i][j] = max(H[i-1][j-1] + SM(Q[i], D[j]), E[i][j], F[i][j])
+ *   E, F as in Eq. 2-3, E[i][0] = F[0][j] = minus infinity,
+ *   H[i][0] = g(i)  and  H[0][j] = g(j) (global) or 0 (semi-global),
+ * where g(k) = -(Go + (k-1) * min(Go, Ge)) for k >= 1 and g(0) = 0: the cost
+ * the recurrence itself charges for a run of k gaps.
+ *   mode 1, global: S = H[m][n], both sequences aligned end to end.
+ *   mode 2, semi-global: S = max over j of H[m][j], the whole query aligned
+ *   to any stretch of the subject (leading and trailing subject residues free).
+ * mode 0 is the local score of sw_oracle_pair.  Returns INT64_MIN on
+ * allocation failure. */
+static int64_t gap_run(int64_t k, int64_t go, int64_t ge)
+{
+    return k <= 0 ? 0 : -(go + (k - 1) * (go < ge ? go : ge));
+}
+
+int64_t sw_oracle_pair_mode(const int8_t* q, int64_t m, const int8_t* d, int64_t n,
+                            const int8_t* sm, int64_t a, int64_t go, int64_t ge, int64_t mode)
+{
+    if (mode == 0) return sw_oracle_pair(q, m, d, n, sm, a, go, ge);
+    const int64_t NEG = INT64_MIN / 4;
+    if (m <= 0) return mode == 1 ? gap_run(n, go, ge) : 0;
+    if (n <= 0) return gap_run(m, go, ge);
+    int64_t* Hup = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t* Fup = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!Hup || !Fup) { free(Hup); free(Fup); return INT64_MIN; }
+    for (int64_t j = 0; j <= n; ++j) {
+        Hup[j] = mode == 1 ? gap_run(j, go, ge) : 0;       /* row 0 */
+        Fup[j] = NEG;
+    }
+    for (int64_t i = 1; i <= m; ++i) {
+        int64_t Hleft = gap_run(i, go, ge);    /* H[i][0] */
+        int64_t Eleft = NEG;                    /* E[i][0] */
+        int64_t Hdiag = Hup[0];                 /* H[i-1][0] */
+        Hup[0] = Hleft;
+        for (int64_t j = 1; j <= n; ++j) {
+            int64_t E = max2(Hleft - go, Eleft - ge);                 /* Eq. 2 */
+            int64_t F = max2(Hup[j] - go, Fup[j] - ge);               /* Eq. 3 */
+            int64_t H = Hdiag + (int64_t)sm[q[i - 1] * a + d[j - 1]];
+            H = max2(H, E);
+            H = max2(H, F);                                           /* Eq. 1 without the 0 */
+            Hdiag = Hup[j];
+            Hup[j] = H;
+            Fup[j] = F;
+            Hleft = H;
+            Eleft = E;
+        }
+    }
+    int64_t S = Hup[n];
+    if (mode == 2)
+        for (int64_t j = 0; j < n; ++j) S = max2(S, Hup[j]);
+    free(Hup);
+    free(Fup);
+    return S;
+}
+
 /* ---------------- one query against many subjects, threads over subjects ---------------- */
 typedef struct {
     const int8_t* q; int64_t m;
     const int8_t* res; const int64_t* offsets;
     const int64_t* idx; int64_t count;
-    const int8_t* sm; int64_t a, go, ge;
+    const int8_t* sm; int64_t a, go, ge, mode;
     int64_t* out;
     int64_t next;               /* shared work counter */
     pthread_mutex_t lock;
@@ -85,25 +142,25 @@ static void* worker(void* arg)
         if (k >= J->count) break;
         int64_t s = J->idx ? J->idx[k] : k;
         int64_t b = J->offsets[s], e = J->offsets[s + 1];
-        int64_t v = sw_oracle_pair(J->q, J->m, J->res + b, e - b, J->sm, J->a, J->go, J->ge);
-        if (v < 0) J->failed = 1;
+        int64_t v = sw_oracle_pair_mode(J->q, J->m, J->res + b, e - b, J->sm, J->a, J->go, J->ge, J->mode);
+        if (J->mode == 0 ? v < 0 : v == INT64_MIN) J->failed = 1;
         J->out[k] = v;
     }
     return NULL;
 }
 
-/* Scores of query q against subjects idx[0..count) (all subjects 0..count if idx
- * is NULL) of a database given as concatenated residues and offsets[n+1].
+/* Scores (mode 0 local, 1 global, 2 semi-global) of query q against subjects idx[0..count)
+ * (all subjects 0..count if idx is NULL) of a database given as concatenated residues and offsets[n+1].
  * out[k] receives the score of subject idx[k].  nthreads <= 0 means 1.
  * Returns 0 on success, -1 on allocation or thread failure. */
 int sw_oracle_scores(const int8_t* q, int64_t m, const int8_t* res, const int64_t* offsets,
                      const int64_t* idx, int64_t count, const int8_t* sm, int64_t a, int64_t go, int64_t ge,
-                     int32_t nthreads, int64_t* out)
+                     int64_t mode, int32_t nthreads, int64_t* out)
 {
     job_t J;
     memset(&J, 0, sizeof J);
     J.q = q; J.m = m; J.res = res; J.offsets = offsets; J.idx = idx; J.count = count;
-    J.sm = sm; J.a = a; J.go = go; J.ge = ge; J.out = out;
+    J.sm = sm; J.a = a; J.go = go; J.ge = ge; J.mode = mode; J.out = out;
     pthread_mutex_init(&J.lock, NULL);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

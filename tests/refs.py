@@ -109,3 +109,55 @@ def score_ops(q, d, sm, go: int, ge: int, q_begin: int, s_begin: int, ops: str):
             raise ValueError(op)
         last = op
     return s, i, j
+
+
+def bf_end_to_end(q, d, sm, go: int, ge: int, semi: bool) -> int:
+    """Best global (every residue of both sequences aligned or gapped) or
+    semi-global (every query residue; the subject's leading and trailing
+    residues free) alignment score by enumerating every path.  A maximal run of
+    k gap steps in one direction costs Go + (k-1) * min(Go, Ge), also at the
+    ends.  Keep m, n <= 5."""
+    q = [int(x) for x in q]
+    d = [int(x) for x in d]
+    m, n = len(q), len(d)
+    ext = min(go, ge)
+    best = None
+    starts = range(n + 1) if semi else [0]
+    for j0 in starts:
+        stack = [(0, j0, 0, 0)]
+        while stack:
+            i, j, s, st = stack.pop()
+            if i == m and (semi or j == n):
+                best = s if best is None else max(best, s)
+            if i < m and j < n:
+                stack.append((i + 1, j + 1, s + int(sm[q[i]][d[j]]), 0))
+            if j < n:
+                stack.append((i, j + 1, s - (ext if st == 1 else go), 1))
+            if i < m:
+                stack.append((i + 1, j, s - (ext if st == 2 else go), 2))
+    return best
+
+
+def edit_distance(a, b) -> int:
+    """Levenshtein distance (unit costs), textbook table."""
+    a, b = list(a), list(b)
+    prev = list(range(len(b) + 1))
+    for i, x in enumerate(a, 1):
+        cur = [i]
+        for j, y in enumerate(b, 1):
+            cur.append(min(prev[j] + 1, cur[j - 1] + 1, prev[j - 1] + (x != y)))
+        prev = cur
+    return prev[-1]
+
+
+def best_substring_distance(a, b) -> int:
+    """Smallest edit distance between a and any substring of b (Sellers' table:
+    row 0 is all zeros, the answer is the minimum of the last row)."""
+    a, b = list(a), list(b)
+    prev = [0] * (len(b) + 1)
+    for i, x in enumerate(a, 1):
+        cur = [i]
+        for j, y in enumerate(b, 1):
+            cur.append(min(prev[j] + 1, cur[j - 1] + 1, prev[j - 1] + (x != y)))
+        prev = cur
+    return min(prev)
