@@ -65,7 +65,7 @@ def measured_traffic(args):
     """HBM bytes per launch of the plain 16-bit sweep from the committed PMC
     summary, if it was taken on the kernel source as it is now (else None)."""
     import hashlib
-    if args.form != "plain" or args.workload != "sp570k":
+    if args.form != "plain" or args.workload != "sp570k" or args.mode != "local":
         return None
     path = os.path.join(ROOT, "profiles", "traffic_k_sweep_i16_sp570k_plain.json")
     try:
@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
+    ap.add_argument("--mode", default="local", choices=["local", "global", "semiglobal"],
+                    help="plain form: alignment mode (global and semi-global run in 32-bit cells)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched-compare", action="store_true",
@@ -274,7 +276,7 @@ def main():
     def step():
         if args.form == "plain":
             for q in queries:
-                D.search(q, sm, 10, 2, out=out)
+                D.search(q, sm, 10, 2, out=out, mode=args.mode)
         else:
             sw.sw_search_batch(qcat, qoff, D.handle, sm, 10, 2, 10, None, top_s, top_i)
 
@@ -301,22 +303,26 @@ def main():
     gcups = cells_step * args.steps / elapsed / 1e9
     kernel_s = float(kt.sum()) / 1e3
     launches = int(kt.size)
-    # the sweep computes in packed 16-bit lanes: two cell operations per VALU lane-op
-    peak_ops = perfmodel.int_valu_lane_ops_per_s() * 2
-    achieved = CELL_OPS * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
+    # the local sweep computes in packed 16-bit lanes: two cell operations per VALU lane-op; the
+    # end-to-end modes in 32-bit lanes with 8 operations per cell (no running maximum)
+    packed = args.mode == "local"
+    peak_ops = perfmodel.int_valu_lane_ops_per_s() * (2 if packed else 1)
+    ops_cell = CELL_OPS if packed else 8
+    achieved = ops_cell * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
     roof = {"bound": "alu", "achieved": round(achieved, 3) if achieved else None,
-            "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s (int16 lane-ops)",
+            "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s (int16 lane-ops)" if packed else "TOP/s (int32 lane-ops)",
             "frac": round(achieved * 1e12 / peak_ops, 4) if achieved else None,
             "traffic": measured_traffic(args),
-            "kernel": "k_sweep<CellI16>" if args.form == "plain" else "batched graph (sweeps + recompute + top-k)",
+            "kernel": ("k_sweep<CellI16>" if packed else f"k_sweep<CellI32, 8, {args.mode}>") if args.form == "plain"
+                      else "batched graph (sweeps + recompute + top-k)",
             "launches": launches,
             "avg_launch_ms": round(kernel_s * 1e3 / max(launches, 1), 3),
-            "ops_per_cell": CELL_OPS}
+            "ops_per_cell": ops_cell}
     res = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int16x2 saturating + int32 recompute", "data": "synthetic",
-        "config": {"workload": args.workload, "form": args.form, "queries": len(queries),
+        "config": {"workload": args.workload, "form": args.form, "mode": args.mode, "queries": len(queries),
                    "qlen_min": min(qlens), "qlen_max": max(qlens), "subjects": db.n, "residues": total_res,
                    "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
         "roofline": roof,
@@ -326,7 +332,7 @@ def main():
                   "rerun_pairs_last_call": st["rerun_pairs"], "waves": st["waves"],
                   "tuned_knobs": tuned["knobs"] if tuned else None},
     }
-    if args.form == "plain" and not args.no_batched_compare:
+    if args.form == "plain" and not args.no_batched_compare and args.mode == "local":
         # the same queries in the batched form: one graph launch for all of them
         from paper_2309_09609_amd import tune as tuner
         print("# batched form on the same queries (autotuned)", file=sys.stderr, flush=True)
@@ -347,7 +353,7 @@ def main():
         res["extra"]["batched_same_queries"] = {"gcups": round(bg, 2), "gain_vs_plain": round(bg / gcups, 3),
                                                 "ms_per_step": round((tb1 - tb0) / args.steps * 1e3, 3),
                                                 "knobs": tb["knobs"], "scores_equal_plain": same}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.mode == "local":
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(queries, db, sm, args.cpu_seconds)
     D.close()

@@ -185,6 +185,27 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
                           int32_t nchunks, sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
                           int32_t* const* h_d_scores, sw_stream stream);
 
+/* Alignment modes of sw_search_mode. */
+enum { SW_LOCAL = 0, SW_GLOBAL = 1, SW_SEMIGLOBAL = 2 };
+
+/*
+ * sw_search_mode - scores of one query against every subject in one of three
+ * modes.  SW_LOCAL is sw_search (Smith-Waterman, Sec. II-B, Eq. 1-3).  The
+ * other two drop the 0 of Eq. 1 and put gap runs on the borders,
+ * H[i][0] = g(i) with g(k) = -(Go + (k-1) * min(Go, Ge)), g(0) = 0, E[i][0] =
+ * F[0][j] = minus infinity:
+ *   SW_GLOBAL      H[0][j] = g(j), S = H[m][n] (both sequences end to end);
+ *   SW_SEMIGLOBAL  H[0][j] = 0, S = max over j of H[m][j] (the whole query
+ *                  against any stretch of the subject).
+ * Scores may be negative.  These modes run in exact 32-bit cells (about a
+ * third of the local search's rate); SW_E_UNSUPPORTED if
+ * Go + (qlen + longest subject) * max(Go, Ge) could leave +-2^29.  Other
+ * arguments and errors as for sw_search.
+ */
+sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
+                         int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
+                         int32_t* d_scores_out, sw_stream stream);
+
 /* One optimal local alignment (see sw_align). */
 typedef struct {
     int32_t score;            /* S of the pair */

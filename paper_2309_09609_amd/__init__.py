@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
-           "sw_search_multi", "sw_align",
+           "sw_search_multi", "sw_align", "sw_search_mode",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -63,6 +63,8 @@ def load():
     lib.sw_search_batch.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P]
     lib.sw_search_multi.restype = I32
     lib.sw_search_multi.argtypes = [P, P, I32, P, I32, P, P, I32, I32, P, P]
+    lib.sw_search_mode.restype = I32
+    lib.sw_search_mode.argtypes = [I32, P, I32, P, P, I64, P, I32, I32, P, P]
     lib.sw_align.restype = I32
     lib.sw_align.argtypes = [P, I32, P, P, I32, P, I32, I32, P, P, I64, P]
     lib.sw_status_str.restype = ctypes.c_char_p
@@ -250,13 +252,18 @@ class Database:
             raise ValueError(f"substitution matrix must be {self.alphabet} x {self.alphabet} for this database")
         return sm
 
-    def search(self, query, subst, gap_open=10, gap_extend=2, out=None, stream=None):
-        """int32 tensor [n] of scores in database order."""
+    def search(self, query, subst, gap_open=10, gap_extend=2, out=None, stream=None, mode="local"):
+        """int32 tensor [n] of scores in database order; ``mode`` is "local"
+        (Smith-Waterman), "global" or "semiglobal" (see sw_search_mode)."""
         import torch
         subst = self.matrix(subst)
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
-        sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
+        if mode == "local":
+            sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
+        else:
+            sw_search_mode(MODES[mode], query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out,
+                           stream)
         return out[: self.n]
 
     def align(self, query, subjects, subst, gap_open=10, gap_extend=2, stream=None):
@@ -285,6 +292,18 @@ class Database:
             ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
         sw_search_batch(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, stream)
         return scores, ts, ti
+
+
+MODES = {"local": 0, "global": 1, "semiglobal": 2}
+
+
+def sw_search_mode(mode, query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, stream=None):
+    lib = load()
+    q = _host_i8(query)
+    sm = _square(subst)
+    offs = None if h_offsets is None else _host_i64(h_offsets)
+    _check(lib.sw_search_mode(int(mode), _ptr(q), q.size, handle, None if offs is None else _ptr(offs), int(n),
+                              _ptr(sm), int(gap_open), int(gap_extend), _ptr(d_scores_out), _stream(stream)))
 
 
 def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stream=None):

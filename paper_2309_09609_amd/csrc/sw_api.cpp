@@ -33,6 +33,8 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
+hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu);
 hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
                         int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
                         int64_t* info, hipStream_t st);
@@ -168,6 +170,11 @@ struct sw_db {
     std::vector<int32_t> lens, slot_of;
     std::vector<int64_t> gbase;
     DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
+    DevBuf slen_sorted;               // subject length per sorted slot (end-to-end modes)
+    DevBuf scratch_mode;              // boundary slots of the end-to-end sweeps
+    int wg_mode = 0;                  // persistent workgroups of an end-to-end sweep
+    int64_t slot_cap_mode = 0;        // (column x pair) capacity of one of its wave slots
+    Plan mode_plan;
     // launch geometry
     int cus = 0, wg16 = 0, wg32 = 0;  // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
     int wgR[17] = {0};                // persistent workgroups per 16-bit instance, by R
@@ -254,14 +261,20 @@ int64_t unit_cost(int m, int ncols, int lgB, int R) {
 // are pairs that a single wave sweeps column by column; for a single short
 // query a smaller R makes them cheaper (most of a 64 x 16-row pass would be
 // padding) and they go to the side list.  Items are ordered longest first.
+// Overrides for sweeps other than the 16-bit ones: fixed R, their slot capacity and wave count.
+struct PlanLimits { int R; int64_t slot_cap; int64_t nwaves; };
+
 void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
-                std::vector<WgItem>& side_out, const std::vector<int>* chunk = nullptr, int nchunks = 1) {
+                std::vector<WgItem>& side_out, const std::vector<int>* chunk = nullptr, int nchunks = 1,
+                const PlanLimits* lim = nullptr) {
+    const int64_t slot_cap = lim ? lim->slot_cap : db->slot_cap;
+    const bool force_R = lim ? true : db->force_R != 0;
     // query qi covers groups chunk[qi], chunk[qi] + nchunks, ... (all groups when nchunks == 1)
     auto first_group = [&](size_t qi) { return chunk ? (*chunk)[qi] : 0; };
     struct Tmp { WgItem it; int64_t cost; };
     // The plan at R rows per lane; returns its estimated makespan in cost units per wave.
     auto plan_at = [&](int R_main, std::vector<Tmp>& items, std::vector<Tmp>& sitems, int& R_side) -> double {
-        const int64_t nwaves = std::max<int64_t>((int64_t)db->wgR[R_main] * kWaves, 1);
+        const int64_t nwaves = std::max<int64_t>(lim ? lim->nwaves : (int64_t)db->wgR[R_main] * kWaves, 1);
         int64_t total = 0;
         for (size_t qi = 0; qi < qlens.size(); ++qi)
             if (qlens[qi] > 0)
@@ -273,7 +286,7 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
             const int m = qlens[qi];
             if (m <= 0) continue;
             int r_long = R_main;
-            if (qlens.size() == 1 && !db->force_R)
+            if (qlens.size() == 1 && !force_R)
                 for (int R : kRowChoices)
                     if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
             const int g_first = first_group(qi);
@@ -302,11 +315,11 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
                 int lgB = 0;
                 for (; lgB < 6; ++lgB) {
                     const int64_t P = kGroupPairs >> lgB;
-                    if ((double)unit_cost(m, nc, lgB, R_main) <= cap && (int64_t)nc * P <= db->slot_cap) break;
+                    if ((double)unit_cost(m, nc, lgB, R_main) <= cap && (int64_t)nc * P <= slot_cap) break;
                 }
                 if (db->force_lgB >= 0) {
                     lgB = db->force_lgB;
-                    while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > db->slot_cap) ++lgB;
+                    while (lgB < 6 && (int64_t)nc * (kGroupPairs >> lgB) > slot_cap) ++lgB;
                 }
                 for (int k = 0; k < (1 << lgB); ++k) {
                     const int uc = db->pcols[(size_t)g * kGroupPairs + (k << (6 - lgB))];
@@ -332,9 +345,9 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
         return std::max({(double)sum / nsimd, (double)biggest * per_simd, (double)sbiggest * per_simd});
     };
     std::vector<Tmp> items, sitems;
-    int R_main = db->force_R ? db->force_R : 16, R_side = R_main;
+    int R_main = lim ? lim->R : db->force_R ? db->force_R : 16, R_side = R_main;
     const double t_main = plan_at(R_main, items, sitems, R_side);
-    if (!db->force_R) {
+    if (!force_R) {
         // fewer rows per lane pay more per cell but pad less when lanes cooperate on a short query
         std::vector<Tmp> items8, sitems8;
         int side8 = 8;
@@ -806,6 +819,13 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
         step(hipMemcpyAsync(db->pair_cols.p, db->pcols.data(), sizeof(int32_t) * db->pcols.size(), hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_soff.p, soff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_slen.p, slen.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        {
+            std::vector<int32_t> sl((size_t)G * kGroupSubjects, 0);
+            std::copy(slen.begin(), slen.end(), sl.begin());
+            if (e == hipSuccess) e = db->slen_sorted.reserve(sizeof(int32_t) * sl.size());
+            step(hipMemcpyAsync(db->slen_sorted.p, sl.data(), sizeof(int32_t) * sl.size(), hipMemcpyHostToDevice, st));
+            step(hipStreamSynchronize(st));
+        }
         step(hipMemcpyAsync(d_gdw.p, gdw.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
         step(hipMemcpyAsync(d_err.p, &zero, 4, hipMemcpyHostToDevice, st));
         step(launch_interleave(d_residues, d_soff.as<int64_t>(), d_slen.as<int32_t>(), n, db->alphabet, db->groups.as<GroupRec>(),
@@ -841,6 +861,7 @@ void sw_db_free(sw_db* db) {
     clear_caches(db);
     db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
+    db->slen_sorted.release(); db->scratch_mode.release(); db->mode_plan.items.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
     db->counters.release(); db->rerun.release(); db->scores_tmp.release();
     db->hstage.release();
@@ -1174,5 +1195,110 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
         }
         k0 = k1;
     }
+    return SW_OK;
+}
+
+// ------------------------------------------------------------------ end-to-end modes
+namespace {
+int64_t gap_run(int64_t k, int64_t go, int64_t ge) { return k <= 0 ? 0 : -(go + (k - 1) * std::min(go, ge)); }
+}
+
+sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
+                         int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out,
+                         sw_stream stream) {
+    if (mode == SW_LOCAL)
+        return sw_search(h_query, qlen, db, h_offsets, n, h_subst, gap_open, gap_extend, d_scores_out, stream);
+    g_err.clear();
+    if (mode != SW_GLOBAL && mode != SW_SEMIGLOBAL) return fail(SW_E_INVALID, "mode must be 0, 1 or 2 (got %d)", mode);
+    sw_status s;
+    if ((s = check_db_args(db, h_offsets, n)) != SW_OK) return s;
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (qlen < 0) return fail(SW_E_INVALID, "qlen must be >= 0");
+    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
+    if (n > 0 && !d_scores_out) return fail(SW_E_INVALID, "scores_out is NULL");
+    for (int32_t i = 0; i < qlen; ++i)
+        if (h_query[i] < 0 || h_query[i] >= db->alphabet)
+            return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
+    // every value of the recurrence stays within +-2^29: gap runs cost at most Go + (m + n) max(Go, Ge)
+    const int64_t span = (int64_t)qlen + db->ncols_max + 1;
+    if ((int64_t)gap_open + span * std::max(gap_open, gap_extend) >= ((int64_t)1 << 29) || span * 127 >= ((int64_t)1 << 29))
+        return fail(SW_E_UNSUPPORTED, "gap penalties x lengths too large for 32-bit end-to-end scores");
+    if (n == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (qlen == 0) {
+        // one gap run per subject (global) or nothing to align (semi-global)
+        std::vector<int32_t> v((size_t)n);
+        for (int64_t k = 0; k < n; ++k) v[k] = mode == SW_GLOBAL ? (int32_t)gap_run(db->lens[k], gap_open, gap_extend) : 0;
+        HIP_TRY(hipMemcpyAsync(d_scores_out, v.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SW_OK;
+    }
+    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    if (db->wg_mode == 0) {
+        int b1 = 0, b2 = 0;
+        HIP_TRY(sweep_occupancy_mode(SW_GLOBAL, &b1));
+        HIP_TRY(sweep_occupancy_mode(SW_SEMIGLOBAL, &b2));
+        const int b = std::min(std::min(b1, b2), 2);
+        if (b < 1) return fail(SW_E_HIP, "end-to-end sweep cannot be resident");
+        db->wg_mode = db->cus * b;
+        db->slot_cap_mode = std::max<int64_t>(16384, db->ncols_max);
+        HIP_TRY(db->scratch_mode.reserve((size_t)db->wg_mode * kWaves * db->slot_cap_mode * 16, &db->gen));
+    }
+    // plan: 32-bit cells at 8 rows per lane, slots of the mode workspace
+    const PlanLimits lim{8, db->slot_cap_mode, (int64_t)db->wg_mode * kWaves};
+    std::vector<WgItem> mi, si;
+    plan_units(db, std::vector<int>{qlen}, &db->mode_plan, mi, si, nullptr, 1, &lim);
+    HIP_TRY(hipStreamSynchronize(st));            // the plan buffer may still be read by an earlier launch
+    HIP_TRY(db->mode_plan.items.reserve(sizeof(WgItem) * std::max<size_t>(mi.size(), 1)));
+    if (!mi.empty()) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * mi.size(), hipMemcpyHostToDevice));
+    const int64_t qo[2] = {0, qlen};
+    const StageLayout L = stage_layout(qo, 1);
+    if ((s = reserve_for(db, L, (int64_t)db->ngroups * kGroupPairs)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
+    int32_t* ctr = db->counters.as<int32_t>();
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
+    SweepArgs a{};
+    a.items = db->mode_plan.items.as<WgItem>();
+    a.n_items = (int32_t)mi.size();
+    a.counter = ctr + 0;
+    a.image = db->image.as<uint8_t>();
+    a.groups = db->groups.as<GroupRec>();
+    a.perm = db->perm.as<int32_t>();
+    a.pair_cols = db->pair_cols.as<int32_t>();
+    a.prof = db->prof.as<int16_t>();
+    a.qd = S.qd;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.scratch = db->scratch_mode.as<uint32_t>();
+    a.slot_words = db->slot_cap_mode * 4;
+    a.scores = d_scores_out;
+    a.unit_list = 0;
+    a.sat = kSat16;
+    a.slen = db->slen_sorted.as<int32_t>();
+    int ev = -1;
+    if (db->timing) {
+        if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
+        ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
+        while ((int)db->ev_pool.size() <= ev) {
+            hipEvent_t x, y;
+            HIP_TRY(hipEventCreate(&x));
+            HIP_TRY(hipEventCreate(&y));
+            db->ev_pool.push_back({x, y});
+        }
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
+    }
+    if (!mi.empty()) HIP_TRY(launch_sweep_mode(mode, a, std::max(1, std::min<int>(db->wg_mode, (int)mi.size())), st));
+    if (ev >= 0) {
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
+        db->ev_used.push_back(ev);
+    }
+    db->last_items = (int)mi.size();
+    db->last_rows = 8;
+    db->last_side_items = 0;
+    db->last_side_rows = 0;
+    db->last_grid = std::max(1, std::min<int>(db->wg_mode, (int)mi.size()));
     return SW_OK;
 }

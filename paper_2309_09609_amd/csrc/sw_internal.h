@@ -74,6 +74,7 @@ struct SweepArgs {
     int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
     int32_t sat;                  // 16-bit scores >= sat are recomputed with 32-bit cells
     const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
+    const int32_t* slen;          // end-to-end modes: subject length per sorted slot (0 for padding slots)
 };
 
 // One (query, subject) pair of an alignment launch.

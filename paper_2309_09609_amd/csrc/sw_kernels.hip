@@ -319,9 +319,24 @@ __device__ __forceinline__ void fetch(const int16_t* lrow, typename Res<PACKED>:
 // rows in LDS.  H, E, F live in registers; the boundary row between passes
 // goes through the slot.  Profile values of the next step are read from LDS
 // while the current step computes; residues are read two chunks ahead.
-template <class C, int R, bool COOP, bool PACKED>
+// Global and semi-global modes (32-bit cells only): no local floor, gap-run
+// borders g(k) = -(Go + (k-1) min(Go, Ge)) on column 0 (and on row 0 for
+// global; 0 for semi-global), S taken on the query's last row: at the
+// subject's last column (global) or its best column (semi-global).
+struct EndCtx {
+    int row0;                 // 0-based first query row of this lane in this pass
+    int m;                    // query length
+    int na, nb;               // lengths of the lane's two subjects
+    int go, ge, ext;          // Go, Ge, min(Go, Ge)
+    bool top;                 // pass 0: row 0 is the border
+    __device__ int border(int k) const { return k <= 0 ? 0 : -(go + (k - 1) * ext); }
+};
+
+template <class C, int R, bool COOP, bool PACKED, int MODE = 0>
 __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, int b, const int16_t* lrow,
-                                           typename C::G go, typename C::G ge, typename C::T& S) {
+                                           typename C::G go, typename C::G ge, typename C::T& S,
+                                           const EndCtx& ec = EndCtx{}) {
+    static_assert(MODE == 0 || std::is_same<C, CellI32>::value, "end-to-end modes use 32-bit cells");
     using T = typename C::T;
     using RV = typename Res<PACKED>::V;
     constexpr int W = C::kWords;
@@ -334,6 +349,18 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
     T diag = C::zero();          // H of the row above this lane's block, previous column
     T up_h = C::zero(), up_f = C::zero();   // bottom row of lane b-1, one column back
+    if constexpr (MODE != 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int hb = ec.border(ec.row0 + r + 1);               // H[i][0]
+            H[r] = T{hb, hb};
+            E[r] = T{hb - ec.go, hb - ec.go};                         // E[i][1]: E[i][0] is minus infinity
+        }
+        const int hb = ec.border(ec.row0);                            // H[row above][0]
+        diag = T{hb, hb};
+        up_h = T{hb, hb};             // what lane b-1 hands over before its first column: its last row's border
+    }
+    const int rcap = ec.m - 1 - ec.row0;    // row of this lane holding the query's last row, if in 0..R-1
 
     // lane b works on columns 4c - b .. 4c - b + 3 during iteration c
     const int coff = COOP ? ((-b) >> 2) : 0;      // floor((-b)/4)
@@ -366,8 +393,39 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                 htop = C::sel(first_lane, htop, up_h);
                 ftop = C::sel(first_lane, ftop, up_f);
             }
+            const int col = 4 * c + u - b;                            // 0-based column of this step
+            if constexpr (MODE != 0) {
+                if (first_lane && ec.top) {                           // row 0 of the matrix
+                    const int h0 = MODE == 1 ? ec.border(col + 1) : 0;
+                    htop = T{h0, h0};
+                    ftop = T{h0 - ec.go, h0 - ec.go};
+                }
+            }
             T F = ftop;
-            if constexpr (std::is_same<C, CellI16>::value) {
+            if constexpr (MODE != 0) {
+                if (col >= 0) {                                       // before its first column a lane keeps the border
+                    T dg = diag;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T sv = C::sm(cur[r >> 1], cur[R / 2 + (r >> 1)], r);
+                        const T hd = T{dg.x + sv.x, dg.y + sv.y};
+                        const T h = T{max(max(hd.x, E[r].x), F.x), max(max(hd.y, E[r].y), F.y)};
+                        dg = H[r];
+                        H[r] = h;
+                        E[r] = T{max(E[r].x - ec.ge, h.x - ec.go), max(E[r].y - ec.ge, h.y - ec.go)};
+                        F = T{max(F.x - ec.ge, h.x - ec.go), max(F.y - ec.ge, h.y - ec.go)};
+                        if (r == rcap) {
+                            if (MODE == 1) {
+                                if (col == ec.na - 1) S.x = h.x;
+                                if (col == ec.nb - 1) S.y = h.y;
+                            } else {
+                                if (col < ec.na) S.x = max(S.x, h.x);
+                                if (col < ec.nb) S.y = max(S.y, h.y);
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (std::is_same<C, CellI16>::value) {
                 if constexpr (PACKED) rows16_packed<R>(H, E, S, F, diag, cur, go, ge);
                 else rows16_pair<R>(H, E, S, F, diag, cur, cur + R / 2, go, ge);
             } else {
@@ -463,7 +521,7 @@ __device__ __forceinline__ void append_rerun(const SweepArgs& a, int g, int q, i
 // One unit of a wave: lane groups [k*P, (k+1)*P) of group g, all passes.
 // Subject pairs (PACKED = false): P = 64/B pairs, one query.  Query pairs
 // (PACKED = true): P = 64/B subjects, queries qpairs[q].x and .y.
-template <class C, int R, bool PACKED>
+template <class C, int R, bool PACKED, int MODE = 0>
 __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int lgB, int q, bool valid,
                                          bool shared_slice, int16_t* lds, int wave, int lane, uint32_t* slot) {
     using T = typename C::T;
@@ -501,6 +559,21 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
                                  : reinterpret_cast<const int16_t*>(region32) + b * kNRes * R;
     const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
     T S = C::zero();
+    EndCtx ec{};
+    if constexpr (MODE != 0) {
+        ec.m = m;
+        ec.go = a.go;
+        ec.ge = a.ge;
+        ec.ext = min(a.go, a.ge);
+        const int slot0 = g * kGroupSubjects + 2 * su;
+        ec.na = valid ? a.slen[slot0] : 0;
+        ec.nb = valid ? a.slen[slot0 + 1] : 0;
+        // the lane holding the query's last row starts S at H[m][0] where that counts
+        const bool cap = (m - 1 - (passes - 1) * rows_pp) / R == b;
+        constexpr int kNeg = -(1 << 30);
+        const int hm = ec.border(m);
+        S = T{cap && (MODE == 2 || ec.na == 0) ? hm : kNeg, cap && (MODE == 2 || ec.nb == 0) ? hm : kNeg};
+    }
     // A unit with many lanes per matrix is a long subject: its passes are one
     // serial chain of steps that can outlast the rest of the search, so its
     // wave issues ahead of the other waves of its SIMD while it runs.
@@ -530,10 +603,12 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         if (valid) {
             io.rd_lane = (b == 0 && p > 0) ? lane_words : kNoAccess;
             io.wr_lane = (b == B - 1 && p + 1 < passes) ? lane_words : kNoAccess;
+            ec.row0 = p * rows_pp + b * R;
+            ec.top = p == 0;
             if (lgB == 0)
-                sweep_pass<C, R, false, PACKED>(io, ncols, B, b, lrow, go, ge, S);
+                sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, ec);
             else
-                sweep_pass<C, R, true, PACKED>(io, ncols, B, b, lrow, go, ge, S);
+                sweep_pass<C, R, true, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, ec);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
@@ -561,11 +636,11 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         int32_t* out = Qa.out ? Qa.out : a.scores + Qa.out_off;
         if (o0 >= 0) out[o0] = C::lo(S);
         if (o1 >= 0) out[o1] = C::hi(S);
-        if (a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
+        if (MODE == 0 && a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
     }
 }
 
-template <class C, int R>
+template <class C, int R, int MODE = 0>
 __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
     // one shared slice of up to 64*R rows, or four per-wave slices of up to 16*R rows
     __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
@@ -587,14 +662,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
         const WgItem I = a.items[it];
         if (a.unit_list) {
             // one unit per workgroup, computed by wave 0 with the whole LDS slice
-            run_unit<C, R, false>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
+            run_unit<C, R, false, MODE>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
         } else {
             const int B = 1 << I.lgB;
             int k = I.k0 + wave;
             const int g = I.g0 + (k >> I.lgB) * I.gstep;
             k &= B - 1;
             const bool shared_slice = I.lgB > 4;        // more than 16 lanes per pair
-            run_unit<C, R, false>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
+            run_unit<C, R, false, MODE>(a, g, k, I.lgB, I.q, wave < I.count, shared_slice, lds, wave, lane, slot);
         }
     }
 }
@@ -843,6 +918,27 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
     SweepArgs copy = a;
     void* args[] = {&copy};
     return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+// Global (mode 1) and semi-global (mode 2) sweeps: 32-bit cells, R = 8.
+static const void* mode_kernel(int mode) {
+    if (mode == 1) return (const void*)k_sweep<CellI32, 8, 1>;
+    if (mode == 2) return (const void*)k_sweep<CellI32, 8, 2>;
+    return nullptr;
+}
+
+hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = mode_kernel(mode);
+    if (!k) return hipErrorInvalidValue;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu) {
+    const void* k = mode_kernel(mode);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
 }
 
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {

@@ -1,0 +1,104 @@
+"""GPU global and semi-global scores against the oracle (tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import synth
+from refs import edit_distance
+
+pytestmark = pytest.mark.gpu
+
+
+def _db(seed, n, lo, hi, extra=()):
+    rng = np.random.default_rng(seed)
+    lens = [0, 1, 2, 3, 4, 5] + list(extra) + list(rng.integers(lo, hi, n))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    return synth.Database(np.concatenate(subs), offs)
+
+
+def _check(gpu, D, db, q, sm, go, ge, mode, ctx):
+    import torch
+    got = D.search(q, sm, go, ge, mode=mode)
+    torch.cuda.synchronize()
+    want = oracle.scores(q, db.residues, db.offsets, sm, go, ge, mode=mode)
+    got = got.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{ctx}: {bad.size} mismatches, first {bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}"
+
+
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+@pytest.mark.parametrize("lanes", [0, 1, 8, 64])
+def test_modes_against_the_oracle(gpu, blosum, mode, lanes):
+    db = _db(31, 200, 1, 700)
+    D = gpu.Database(db.residues, db.offsets, force_lanes=lanes)
+    for m in (1, 7, 8, 9, 200, 513):
+        q = synth.small_query(seed=m, m=m)
+        _check(gpu, D, db, q, blosum, 10, 2, mode, f"{mode} lanes={lanes} m={m}")
+    D.close()
+
+
+@pytest.mark.parametrize("go,ge", [(0, 0), (3, 5), (11, 1), (40, 40)])
+def test_mode_gap_settings(gpu, blosum, go, ge):
+    db = _db(32, 80, 1, 400)
+    D = gpu.Database(db.residues, db.offsets)
+    q = synth.small_query(seed=5, m=150)
+    for mode in ("global", "semiglobal"):
+        _check(gpu, D, db, q, blosum, go, ge, mode, f"{mode} {go}/{ge}")
+    D.close()
+
+
+def test_modes_with_long_subjects(gpu, blosum):
+    db = _db(33, 40, 100, 900, extra=(35000, 12000, 3000))
+    D = gpu.Database(db.residues, db.offsets)
+    q = np.concatenate([db.residues[db.offsets[7] + 100: db.offsets[7] + 600], synth.small_query(seed=9, m=300)])
+    for mode in ("global", "semiglobal"):
+        _check(gpu, D, db, q, blosum, 10, 2, mode, f"{mode} long")
+    D.close()
+
+
+def test_empty_query_and_edit_distance(gpu):
+    import torch
+    db = _db(34, 60, 0, 120)
+    sm = np.full((20, 20), -1, dtype=np.int8)
+    np.fill_diagonal(sm, 0)
+    D = gpu.Database(db.residues, db.offsets)
+    lens = np.diff(db.offsets)
+    got = D.search(np.zeros(0, np.int8), sm, 10, 2, mode="global").cpu().numpy()
+    assert (got == np.where(lens > 0, -(10 + (lens - 1) * 2), 0)).all()
+    assert (D.search(np.zeros(0, np.int8), sm, 10, 2, mode="semiglobal").cpu().numpy() == 0).all()
+    q = synth.small_query(seed=11, m=90)
+    got = D.search(q, sm, 1, 1, mode="global")
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    for k in range(db.n):
+        assert got[k] == -edit_distance(q, db.residues[db.offsets[k]:db.offsets[k + 1]]), k
+    D.close()
+
+
+def test_modes_extended_alphabet(gpu):
+    from inputs import blosum62_24
+    sm = blosum62_24()
+    rng = np.random.default_rng(35)
+    lens = rng.integers(0, 400, 100)
+    res = rng.integers(0, 24, int(lens.sum())).astype(np.int8)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    db = synth.Database(res, offs)
+    D = gpu.Database(res, offs, alphabet=24)
+    q = rng.integers(0, 24, 222).astype(np.int8)
+    for mode in ("global", "semiglobal"):
+        _check(gpu, D, db, q, sm, 10, 2, mode, f"{mode} alphabet 24")
+    D.close()
+
+
+def test_mode_range_and_argument_errors(gpu, blosum):
+    db = _db(36, 10, 1, 50)
+    D = gpu.Database(db.residues, db.offsets)
+    q = synth.small_query(seed=1, m=20)
+    with pytest.raises(gpu.SwError):
+        D.search(q, blosum, 1 << 28, 1 << 28, mode="global")
+    out = __import__("torch").empty(db.n, dtype=__import__("torch").int32, device="cuda")
+    with pytest.raises(gpu.SwError):
+        gpu.sw_search_mode(3, q, D.handle, db.offsets, db.n, blosum, 10, 2, out)
+    D.close()
