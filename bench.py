@@ -321,7 +321,8 @@ def main():
     res = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int16x2 saturating + int32 recompute", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16x2 saturating + int32 recompute" if packed else "int32", "data": "synthetic",
         "config": {"workload": args.workload, "form": args.form, "mode": args.mode, "queries": len(queries),
                    "qlen_min": min(qlens), "qlen_max": max(qlens), "subjects": db.n, "residues": total_res,
                    "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
