@@ -142,11 +142,24 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
  * computed only for top-ranked subjects), ordered by score descending, then by
  * subject index ascending.  When k > n the tail is padded with score -1 and
  * index -1.
- *   d_scores : device int32[n], scores >= 0.      k : 1..1024.
+ *   d_scores : device int32[n].      k : 1..1024.
  *   d_top_scores : device int32[k].   d_top_index : device int64[k].
  */
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k,
                   int32_t* d_top_scores, int64_t* d_top_index, sw_stream stream);
+
+/*
+ * sw_topk_ws - sw_topk with a caller-owned device workspace, which lets a long
+ * score vector be cut into pieces whose own top k are merged in a second
+ * launch (hundreds of workgroups instead of one).  Same results as sw_topk.
+ * sw_topk_ws_bytes gives the workspace size for n and k (0: one launch is
+ * used, the workspace may be NULL).  d_workspace NULL always takes one launch;
+ * a non-NULL workspace smaller than required is SW_E_SIZE.  Any int32 scores
+ * are ordered correctly (sw_topk too), negative ones included.
+ */
+sw_status sw_topk_ws_bytes(int64_t n, int32_t k, int64_t* bytes);
+sw_status sw_topk_ws(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
+                     void* d_workspace, int64_t ws_bytes, sw_stream stream);
 
 /*
  * sw_search_batch - scores of nq queries against every subject in one

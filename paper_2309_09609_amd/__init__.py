@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
-           "sw_search_multi", "sw_align", "sw_search_mode",
+           "sw_search_multi", "sw_align", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -63,6 +63,10 @@ def load():
     lib.sw_search_batch.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P]
     lib.sw_search_multi.restype = I32
     lib.sw_search_multi.argtypes = [P, P, I32, P, I32, P, P, I32, I32, P, P]
+    lib.sw_topk_ws_bytes.restype = I32
+    lib.sw_topk_ws_bytes.argtypes = [I64, I32, P]
+    lib.sw_topk_ws.restype = I32
+    lib.sw_topk_ws.argtypes = [P, I64, I32, P, P, P, I64, P]
     lib.sw_search_mode.restype = I32
     lib.sw_search_mode.argtypes = [I32, P, I32, P, P, I64, P, I32, I32, P, P]
     lib.sw_align.restype = I32
@@ -328,9 +332,17 @@ def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stre
 
 
 def topk(scores, k, stream=None):
-    """(top scores int32[k], indices int64[k]) of a 1-D int32 score tensor."""
+    """(top scores int32[k], indices int64[k]) of a 1-D int32 score tensor; a long
+    vector uses the two-launch form with a workspace from torch's allocator."""
     import torch
+    lib = load()
     ts = torch.empty(k, dtype=torch.int32, device=scores.device)
     ti = torch.empty(k, dtype=torch.int64, device=scores.device)
-    sw_topk(scores, scores.numel(), k, ts, ti, stream)
+    need = ctypes.c_int64()
+    _check(lib.sw_topk_ws_bytes(scores.numel(), int(k), ctypes.byref(need)))
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=scores.device) if need.value > 0 else None
+    if ws is not None and stream is not None:
+        ws.record_stream(stream)
+    _check(lib.sw_topk_ws(_ptr(scores), scores.numel(), int(k), _ptr(ts), _ptr(ti),
+                          None if ws is None else _ptr(ws), need.value, _stream(stream)))
     return ts, ti

@@ -45,6 +45,9 @@ hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, c
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err, hipStream_t st);
+hipError_t launch_topk_ws(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
+                          int64_t* top_i, void* ws, hipStream_t st);
+int64_t topk_ws_bytes(int64_t n, int rows, int k);
 hipError_t launch_topk(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
                        int64_t* top_i, hipStream_t st);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t st);
@@ -171,6 +174,7 @@ struct sw_db {
     std::vector<int64_t> gbase;
     DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
     DevBuf slen_sorted;               // subject length per sorted slot (end-to-end modes)
+    DevBuf topk_ws;                   // candidates of the two-launch top-k of long score rows
     DevBuf scratch_mode;              // boundary slots of the end-to-end sweeps
     int wg_mode = 0;                  // persistent workgroups of an end-to-end sweep
     int64_t slot_cap_mode = 0;        // (column x pair) capacity of one of its wave slots
@@ -570,6 +574,12 @@ sw_status reserve_for(sw_db* db, const StageLayout& L, int64_t rerun_cap) {
     return SW_OK;
 }
 
+sw_status reserve_topk(sw_db* db, int rows, int k) {
+    const int64_t b = k > 0 ? topk_ws_bytes(db->n, rows, k) : 0;
+    if (b > 0) HIP_TRY(db->topk_ws.reserve((size_t)b, &db->gen));
+    return SW_OK;
+}
+
 // Copies the queries (host) into the staging buffer on the device.  No launch.
 sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
                         const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out,
@@ -684,7 +694,9 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
     r.rerun_cap = 0;
     r.unit_list = 1;
     HIP_TRY(launch_sweep(false, kRerunRows, r, db->wg32, st));
-    if (k > 0) HIP_TRY(launch_topk(d_scores, n, n, S.nq, k, top_s, top_i, st));
+    if (k > 0)
+        HIP_TRY(launch_topk_ws(d_scores, n, n, S.nq, k, top_s, top_i,
+                               topk_ws_bytes(n, S.nq, k) > 0 ? db->topk_ws.p : nullptr, st));
     db->last_items = plan.n_main;
     db->last_rows = plan.R_main;
     db->last_side_items = plan.n_side;
@@ -861,7 +873,7 @@ void sw_db_free(sw_db* db) {
     clear_caches(db);
     db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
-    db->slen_sorted.release(); db->scratch_mode.release(); db->mode_plan.items.release();
+    db->slen_sorted.release(); db->scratch_mode.release(); db->mode_plan.items.release(); db->topk_ws.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
     db->counters.release(); db->rerun.release(); db->scores_tmp.release();
     db->hstage.release();
@@ -915,11 +927,28 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
 
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
                   sw_stream stream) {
+    return sw_topk_ws(d_scores, n, k, d_top_scores, d_top_index, nullptr, 0, stream);
+}
+
+sw_status sw_topk_ws_bytes(int64_t n, int32_t k, int64_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(SW_E_INVALID, "bytes is NULL");
+    if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
+    if (k < 1 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 1..1024 (got %d)", k);
+    *bytes = topk_ws_bytes(n, 1, k);
+    return SW_OK;
+}
+
+sw_status sw_topk_ws(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
+                     void* d_workspace, int64_t ws_bytes, sw_stream stream) {
     g_err.clear();
     if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
     if (k < 1 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 1..1024 (got %d)", k);
     if ((n > 0 && !d_scores) || !d_top_scores || !d_top_index) return fail(SW_E_INVALID, "NULL pointer");
-    HIP_TRY(launch_topk(d_scores, n, n, 1, k, d_top_scores, d_top_index, static_cast<hipStream_t>(stream)));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t need = topk_ws_bytes(n, 1, k);
+    if (d_workspace && need > 0 && ws_bytes < need) return fail(SW_E_SIZE, "workspace of %lld bytes < %lld", (long long)ws_bytes, (long long)need);
+    HIP_TRY(launch_topk_ws(d_scores, n, n, 1, k, d_top_scores, d_top_index, need > 0 ? d_workspace : nullptr, st));
     return SW_OK;
 }
 
@@ -971,6 +1000,7 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
     const StageLayout L = stage_layout(h_qoffsets, nq);
     const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
     if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    if ((s = reserve_topk(db, nq, k)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
     GraphEntry& G = db->graph;

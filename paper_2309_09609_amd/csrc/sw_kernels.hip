@@ -34,6 +34,7 @@
 // S >= kSat16 sends the pair to the 32-bit sweep.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <type_traits>
 
 #include "sw_internal.h"
@@ -773,8 +774,15 @@ __device__ __forceinline__ bool key_before(int sa, int64_t ia, int sb, int64_t i
     return sa > sb || (sa == sb && ia < ib);
 }
 
-__global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, int64_t n, int64_t row_stride, int k,
-                                                       int32_t* top_s, int64_t* top_i) {
+// Long rows go in two launches: the row is cut into nchunks pieces whose own
+// top k (sorted) land side by side in a candidate row, then one workgroup takes
+// the top k of the candidates.  Equal scores keep index order across the
+// candidate row (pieces are in index order and each piece's list is sorted by
+// index among equal scores), so the second launch's positional tie rule is
+// the index rule; idx_map turns its positions back into subject indices.
+__global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, int64_t n_all, int64_t row_stride, int k,
+                                                       int32_t* top_s, int64_t* top_i, int nchunks, int64_t chunk_len,
+                                                       const int64_t* idx_map) {
     __shared__ int hist[256];
     __shared__ int s_digit, s_rank;
     __shared__ int c_gt, c_eq;
@@ -782,19 +790,25 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, in
     __shared__ int cand_s[1024];
     __shared__ int64_t cand_i[1024];
     const int tid = threadIdx.x;
-    const int32_t* row = scores + (int64_t)blockIdx.x * row_stride;
+    const int rw = blockIdx.x / nchunks, piece = blockIdx.x - rw * nchunks;
+    const int64_t base = (int64_t)piece * chunk_len;
+    const int64_t n = max<int64_t>(0, min<int64_t>(chunk_len, n_all - base));
+    const int32_t* row = scores + (int64_t)rw * row_stride + base;
+    const int64_t* imap = idx_map ? idx_map + (int64_t)rw * row_stride + base : nullptr;
     int32_t* outs = top_s + (int64_t)blockIdx.x * k;
     int64_t* outi = top_i + (int64_t)blockIdx.x * k;
     const int take = (int)min<int64_t>((int64_t)k, n);
 
+    // radix select on the scores with the sign bit flipped (signed order as unsigned)
     uint32_t prefix = 0, mask = 0;
     int rank = take;                 // rank of the threshold among scores matching the prefix
-    if (take > 0 && take < n) {
+    const bool select = take > 0 && take < n;   // else every score qualifies
+    if (select) {
         for (int shift = 24; shift >= 0; shift -= 8) {
             for (int i = tid; i < 256; i += kTopkThreads) hist[i] = 0;
             __syncthreads();
             for (int64_t i = tid; i < n; i += kTopkThreads) {
-                const uint32_t v = (uint32_t)row[i];
+                const uint32_t v = (uint32_t)row[i] ^ 0x80000000u;
                 if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255], 1);
             }
             __syncthreads();
@@ -814,15 +828,16 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, in
             __syncthreads();
         }
     }
-    const int T = (take > 0 && take < n) ? (int)prefix : -1;   // take == n: every score qualifies
-    const int need_eq = (take > 0 && take < n) ? rank : 0;
+    const int T = (int)(prefix ^ 0x80000000u);                 // the k-th largest score
+    const int need_eq = select ? rank : 0;
     if (tid == 0) { c_gt = 0; c_eq = 0; }
     __syncthreads();
     for (int64_t base = 0; base < n && take > 0; base += kTopkThreads) {
         const int64_t i = base + tid;
-        const int v = i < n ? row[i] : -2;
-        const bool gt = v > T;
-        const bool eq = (v == T) && (T >= 0);
+        const bool in = i < n;
+        const int v = in ? row[i] : 0;
+        const bool gt = in && (!select || v > T);
+        const bool eq = in && select && v == T;
         if (gt) {
             const int pos = atomicAdd(&c_gt, 1);
             if (pos < take) { cand_s[pos] = v; cand_i[pos] = i; }
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, in
     int sz = 1;
     while (sz < take) sz <<= 1;
     for (int i = tid; i < sz; i += kTopkThreads)
-        if (i >= take) { cand_s[i] = -1; cand_i[i] = INT64_MAX; }
+        if (i >= take) { cand_s[i] = INT_MIN; cand_i[i] = INT64_MAX; }
     __syncthreads();
     for (int len = 2; len <= sz; len <<= 1) {
         for (int st = len >> 1; st > 0; st >>= 1) {
@@ -870,7 +885,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* scores, in
         }
     }
     for (int i = tid; i < k; i += kTopkThreads) {
-        if (i < take) { outs[i] = cand_s[i]; outi[i] = cand_i[i]; }
+        if (i < take) { outs[i] = cand_s[i]; outi[i] = imap ? imap[cand_i[i]] : base + cand_i[i]; }
         else { outs[i] = -1; outi[i] = -1; }
     }
 }
@@ -966,7 +981,39 @@ hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32
 
 hipError_t launch_topk(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
                        int64_t* top_i, hipStream_t st) {
-    hipLaunchKernelGGL(k_topk, dim3(rows), dim3(kTopkThreads), 0, st, scores, n, row_stride, k, top_s, top_i);
+    hipLaunchKernelGGL(k_topk, dim3(rows), dim3(kTopkThreads), 0, st, scores, n, row_stride, k, top_s, top_i, 1, n,
+                       nullptr);
+    return hipGetLastError();
+}
+
+// Pieces for the two-launch top-k of rows x n scores (1 = one launch).
+int topk_pieces(int64_t n, int rows, int k) {
+    if (n < (int64_t)4 * kTopkThreads * 32 || rows >= 128) return 1;
+    int64_t p = (n + 32767) / 32768;
+    p = std::min<int64_t>(p, std::max(1, 256 / std::max(rows, 1)));
+    return (int)std::max<int64_t>(p, 1);
+}
+
+int64_t topk_ws_bytes(int64_t n, int rows, int k) {
+    const int p = topk_pieces(n, rows, k);
+    if (p <= 1) return 0;
+    return (int64_t)rows * p * k * (int64_t)(sizeof(int32_t) + sizeof(int64_t)) + 256;
+}
+
+hipError_t launch_topk_ws(const int32_t* scores, int64_t n, int64_t row_stride, int rows, int k, int32_t* top_s,
+                          int64_t* top_i, void* ws, hipStream_t st) {
+    const int p = topk_pieces(n, rows, k);
+    if (p <= 1 || !ws) return launch_topk(scores, n, row_stride, rows, k, top_s, top_i, st);
+    const int64_t cand = (int64_t)p * k;                     // candidates per row
+    int64_t* ci = static_cast<int64_t*>(ws);
+    int32_t* cs = reinterpret_cast<int32_t*>(ci + (int64_t)rows * cand);
+    const int64_t chunk = (n + p - 1) / p;
+    hipLaunchKernelGGL(k_topk, dim3(rows * p), dim3(kTopkThreads), 0, st, scores, n, row_stride, k, cs, ci, p, chunk,
+                       nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk, dim3(rows), dim3(kTopkThreads), 0, st, cs, cand, cand, k, top_s, top_i, 1, cand,
+                       (const int64_t*)ci);
     return hipGetLastError();
 }
 
