@@ -6,14 +6,25 @@
 // (query x subject) matrix of Eq. 1-3 in 32-bit cells stores one direction
 // byte per cell, and one thread then walks the bytes back from the end cell.
 //
-// Fill.  One wave per (query, subject) pair.  Lane b owns 4 consecutive query
-// rows of each pass of 256 rows and at step t updates column j = t - b + 1
-// (1-based), so the 64 lanes form an anti-diagonal wavefront; the bottom row
-// of lane b reaches lane b+1 through a DPP shift, and the bottom row of the
-// pass goes to the next pass through a per-pair boundary buffer.  The 4
-// direction bytes a lane produces per step form one dword, and the 64 lanes
-// write 256 consecutive bytes per step: byte (pass p, step t, lane b, row r)
-// at ((p * (n + 63) + t) * 64 + b) * 4 + r.
+// Fill.  One workgroup of up to 16 waves per (query, subject) pair.  The
+// query is cut into bands of 256 rows; lane b of the wave holding a band owns
+// 4 consecutive rows and at step t updates column j = t - b + 1 (1-based), so
+// the 64 lanes form an anti-diagonal wavefront and the bottom row of lane b
+// reaches lane b+1 through a DPP shift.  Band k goes to wave k mod W, and the
+// bands run as a pipeline: band k processes its 128-step stages k*L, k*L + 1,
+// ... with L >= 2 stages of lag behind band k-1, whose bottom row (H and F per
+// column, in a per-pair row buffer) it reads; a workgroup barrier ends every
+// stage.  Lag 2 covers the 64 steps a column needs to cross a band plus one
+// step of read-ahead; L >= (stages per band) / W keeps a wave from being
+// needed by two bands at once.  The 4 direction bytes a lane produces per
+// step form one dword, and the 64 lanes write 256 consecutive bytes per
+// step: byte (band p, step t, lane b, row r) at ((p * (n + 63) + t) * 64 + b)
+// * 4 + r.
+//
+// Walk.  One wave per pair copies the 256-byte step records of up to 128
+// steps of the current band into LDS, and one lane follows the path through
+// them until it leaves the copied steps; every move keeps or lowers the step
+// index, so each copy serves dozens of moves.
 //
 // Direction byte of cell (i, j):
 //   bits 0-1  where H comes from: 0 H = 0 (an alignment starts after this
@@ -32,7 +43,10 @@
 namespace sw {
 
 constexpr int kAlignRows = 4;                    // query rows per lane
-constexpr int kAlignPass = 64 * kAlignRows;      // query rows per pass
+constexpr int kAlignPass = 64 * kAlignRows;      // query rows per band
+constexpr int kAlignWaves = 16;                  // bands in flight per pair
+constexpr int kAlignStage = 32;                  // iterations of 4 steps per stage
+constexpr int kTraceSteps = 128;                 // steps per LDS copy of the walk
 
 __device__ __forceinline__ uint32_t align_shr1(uint32_t v) {
     // lane l receives lane l-1's value; lane 0 receives 0
@@ -55,127 +69,182 @@ __device__ __forceinline__ align_rsrc align_buffer(const void* base, uint32_t by
 }
 
 // Residues arrive 4 columns per dword two chunks ahead and the boundary row
-// one chunk ahead, so no step waits for memory.
-__global__ __launch_bounds__(64) void k_align_fill(const AlignPair* pairs, const int8_t* query, int m,
-                                                   const int8_t* subst, int A, int go, int ge, uint8_t* dirs,
-                                                   int32_t* bnd, int32_t* best) {
-    // query profile of the current pass: prof[d][row], rows of lane b at bytes 4b .. 4b + 3 of each residue row
-    __shared__ __attribute__((aligned(16))) int8_t prof[kMaxAlphabet * kAlignPass];
+// one iteration ahead, so no step waits for memory.  Dynamic LDS: the query
+// profile of each wave's band, prof[d][row] with the rows of lane b at bytes
+// 4b .. 4b + 3 of each residue row (W * A * 256 bytes), built from a copy of
+// the substitution matrix in LDS.
+__global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair* pairs, const int8_t* query, int m,
+                                                                 const int8_t* subst, int A, int go, int ge,
+                                                                 uint8_t* dirs, int32_t* bnd, int32_t* best) {
+    extern __shared__ __attribute__((aligned(16))) int8_t align_lds[];
+    __shared__ int wbest[kAlignWaves][3];
+    __shared__ int8_t sm[kMaxAlphabet * kMaxAlphabet];
     const AlignPair P = pairs[blockIdx.x];
-    const int b = threadIdx.x;
+    const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int b = threadIdx.x & 63;
+    const int W = (int)(blockDim.x >> 6);
+    int8_t* prof = align_lds + wave * (A * kAlignPass);
+    for (int e = threadIdx.x; e < A * A; e += blockDim.x) sm[e] = subst[e];
+    __syncthreads();
     const int n = P.n;
     const int n4 = (n + 3) & ~3;                // columns rounded up to whole chunks
     const align_rsrc img = align_buffer(P.residues, (uint32_t)(n4 >> 2) * kChunkBytes);
-    int32_t* bh = bnd + P.bnd_off;              // last row of the previous pass, 0-based columns: H, then F
+    int32_t* bh = bnd + P.bnd_off;              // bottom row of the previous band, 0-based columns: H, then F
     int32_t* bf = bh + n4;
     const align_rsrc bhr = align_buffer(bh, (uint32_t)n4 * 4), bfr = align_buffer(bf, (uint32_t)n4 * 4);
     uint32_t* dir = reinterpret_cast<uint32_t*>(dirs + P.dir_off);
-    int best_s = 0, best_i = 0, best_j = 0;     // wave-uniform after each pass
     const int passes = (m + kAlignPass - 1) / kAlignPass;
     const int nsteps = n + 63;
     const int nloop = (nsteps + 3) >> 2;
+    const int nch = (nloop + kAlignStage - 1) / kAlignStage;     // stages per band
+    const int L = max(2, (nch + W - 1) / W);                      // lag between consecutive bands
+    const int nstages = (passes - 1) * L + nch;
     const int coff = (-b) >> 2, csh = (-b) & 3;  // lane b works on 0-based columns 4c - b .. 4c - b + 3 in iteration c
     auto chunk = [&](int c) { return __builtin_amdgcn_raw_buffer_load_b32(img, (uint32_t)(c * kChunkBytes), 0, 0); };
-    for (int p = 0; p < passes; ++p) {
-        const int row0 = p * kAlignPass + b * kAlignRows;     // 0-based first row of this lane
-        bool valid[kAlignRows];
+    int best_s = 0, best_i = 0, best_j = 0;     // wave-uniform after each band
+    // state of the wave's band in progress
+    int row0 = 0;
+    bool valid[kAlignRows];
+    int H[kAlignRows], E[kAlignRows], bs[kAlignRows], bj[kAlignRows];
+    int diag_top = 0;                           // H of the row above this lane's block, previous column
+    int up_h = 0, up_f = 0;                     // bottom row of lane b-1 at this step's column
+    uint32_t rd = 0x80000000u;                  // boundary offset: only the first lane of a band > 0 reads
+    uint32_t lo = 0, hi = 0, nx = 0;
+    uint4 vh = {0, 0, 0, 0}, vf = {0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < kAlignRows; ++r) valid[r] = row0 + r < m;
-        __syncthreads();                        // the previous pass is done with the profile
-        for (int e = b; e < A * kAlignPass; e += 64) {
-            const int d = e / kAlignPass, row = p * kAlignPass + (e - d * kAlignPass);
-            prof[e] = row < m ? subst[query[row] * A + d] : (int8_t)0;
+    for (int r = 0; r < kAlignRows; ++r) { valid[r] = false; H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
+    for (int s = 0; s < nstages; ++s) {
+        // the band of this wave in stage s, if any: bands wave, wave + W, ... start every W * L stages
+        int p = -1, c = 0;
+        if (s >= wave * L) {
+            const int kk = wave + (s - wave * L) / (W * L) * W;
+            const int cc = s - kk * L;
+            if (kk < passes && cc < nch) { p = kk; c = cc; }
         }
-        __syncthreads();
-        int H[kAlignRows], E[kAlignRows], bs[kAlignRows], bj[kAlignRows];
+        if (p >= 0 && c == 0) {
+            row0 = p * kAlignPass + b * kAlignRows;
 #pragma unroll
-        for (int r = 0; r < kAlignRows; ++r) { H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
-        int diag_top = 0;                       // H of the row above this lane's block, previous column
-        int up_h = 0, up_f = 0;                 // bottom row of lane b-1 at this step's column
-        const uint32_t rd = (b == 0 && p > 0) ? 0u : 0x80000000u;   // only the first lane reads the boundary
-        uint32_t lo = chunk(coff), hi = chunk(coff + 1), nx = chunk(coff + 2);
-        uint4 vh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd, 0, 0));
-        uint4 vf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd, 0, 0));
-        for (int c = 0; c < nloop; ++c) {
-            const uint32_t nn = chunk(coff + c + 3);
-            const uint4 wh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd + 16u * (c + 1), 0, 0));
-            const uint4 wf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd + 16u * (c + 1), 0, 0));
-            const uint32_t rr = __builtin_amdgcn_alignbyte(hi, lo, csh);
-            const int th[4] = {(int)vh.x, (int)vh.y, (int)vh.z, (int)vh.w};
-            const int tf[4] = {(int)vf.x, (int)vf.y, (int)vf.z, (int)vf.w};
+            for (int r = 0; r < kAlignRows; ++r) { valid[r] = row0 + r < m; H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
+            int qa[kAlignRows];                 // matrix row offset of each query row, -1 past the query
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = 4 * c + u;
-                const int j = t - b + 1;        // 1-based column of this lane
-                const bool active = j >= 1 && j <= n;
-                const int htop = b == 0 ? th[u] : up_h;
-                const int ftop = b == 0 ? tf[u] : up_f;
-                int hbot = 0, fbot = 0;
-                if (active) {
-                    const int d = (int)((rr >> (8 * u)) & 0xffu) - 1;
-                    const uint32_t sv = *reinterpret_cast<const uint32_t*>(prof + d * kAlignPass + 4 * b);
-                    int dg = diag_top, hu = htop, fu = ftop;
-                    uint32_t bits = 0;
+            for (int r = 0; r < kAlignRows; ++r) qa[r] = valid[r] ? query[row0 + r] * A : -1;
+            for (int d = 0; d < A; ++d) {
+                uint32_t v = 0;
 #pragma unroll
-                    for (int r = 0; r < kAlignRows; ++r) {
-                        const int hl = H[r];                         // H[i][j-1]
-                        const int eo = hl - go, ee = E[r] - ge;
-                        const int e = max(eo, ee);                   // Eq. 2
-                        const int fo = hu - go, fe = fu - ge;
-                        const int f = max(fo, fe);                   // Eq. 3
-                        const int hd = dg + (int)(int8_t)(sv >> (8 * r));
-                        const int h = max(max(hd, e), max(f, 0));    // Eq. 1
-                        const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
-                        bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
-                        if (valid[r] && h > bs[r]) { bs[r] = h; bj[r] = j; }
-                        dg = hl;
-                        H[r] = h;
-                        E[r] = e;
-                        hu = h;
-                        fu = f;
-                    }
-                    dir[((int64_t)p * nsteps + t) * 64 + b] = bits;
-                    hbot = hu;
-                    fbot = fu;
-                    if (b == 63 && p + 1 < passes) { bh[j - 1] = hbot; bf[j - 1] = fbot; }
-                }
-                diag_top = htop;
-                up_h = (int)align_shr1((uint32_t)hbot);
-                up_f = (int)align_shr1((uint32_t)fbot);
+                for (int r = 0; r < kAlignRows; ++r)
+                    if (qa[r] >= 0) v |= (uint32_t)(uint8_t)sm[qa[r] + d] << (8 * r);
+                *reinterpret_cast<uint32_t*>(prof + d * kAlignPass + 4 * b) = v;
             }
-            lo = hi;
-            hi = nx;
-            nx = nn;
-            vh = wh;
-            vf = wf;
+            diag_top = 0;
+            up_h = 0;
+            up_f = 0;
+            rd = (b == 0 && p > 0) ? 0u : 0x80000000u;
+            lo = chunk(coff);
+            hi = chunk(coff + 1);
+            nx = chunk(coff + 2);
+            vh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd, 0, 0));
+            vf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd, 0, 0));
         }
-        // this pass's first end cell, then the first over all passes
-        int s = 0, ci = 0, cj = 0;
+        __syncthreads();                        // the band's profile is in LDS
+        if (p >= 0) {
+            const int it1 = min(nloop, (c + 1) * kAlignStage);
+            for (int it = c * kAlignStage; it < it1; ++it) {
+                const uint32_t nn = chunk(coff + it + 3);
+                const uint4 wh = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bhr, rd + 16u * (it + 1), 0, 0));
+                const uint4 wf = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(bfr, rd + 16u * (it + 1), 0, 0));
+                const uint32_t rr = __builtin_amdgcn_alignbyte(hi, lo, csh);
+                const int th[4] = {(int)vh.x, (int)vh.y, (int)vh.z, (int)vh.w};
+                const int tf[4] = {(int)vf.x, (int)vf.y, (int)vf.z, (int)vf.w};
 #pragma unroll
-        for (int r = 0; r < kAlignRows; ++r)
-            if (bs[r] > 0 && end_before(bs[r], row0 + r + 1, bj[r], s, ci, cj)) { s = bs[r]; ci = row0 + r + 1; cj = bj[r]; }
-        for (int o = 1; o < 64; o <<= 1) {
-            const int s2 = __shfl_xor(s, o, 64), i2 = __shfl_xor(ci, o, 64), j2 = __shfl_xor(cj, o, 64);
-            if (s2 > 0 && (s == 0 || end_before(s2, i2, j2, s, ci, cj))) { s = s2; ci = i2; cj = j2; }
+                for (int u = 0; u < 4; ++u) {
+                    const int t = 4 * it + u;
+                    const int j = t - b + 1;    // 1-based column of this lane
+                    const bool active = j >= 1 && j <= n;
+                    const int htop = b == 0 ? th[u] : up_h;
+                    const int ftop = b == 0 ? tf[u] : up_f;
+                    int hbot = 0, fbot = 0;
+                    if (active) {
+                        const int d = (int)((rr >> (8 * u)) & 0xffu) - 1;
+                        const uint32_t sv = *reinterpret_cast<const uint32_t*>(prof + d * kAlignPass + 4 * b);
+                        int dg = diag_top, hu = htop, fu = ftop;
+                        uint32_t bits = 0;
+#pragma unroll
+                        for (int r = 0; r < kAlignRows; ++r) {
+                            const int hl = H[r];                         // H[i][j-1]
+                            const int eo = hl - go, ee = E[r] - ge;
+                            const int e = max(eo, ee);                   // Eq. 2
+                            const int fo = hu - go, fe = fu - ge;
+                            const int f = max(fo, fe);                   // Eq. 3
+                            const int hd = dg + (int)(int8_t)(sv >> (8 * r));
+                            const int h = max(max(hd, e), max(f, 0));    // Eq. 1
+                            const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
+                            bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
+                            if (valid[r] && h > bs[r]) { bs[r] = h; bj[r] = j; }
+                            dg = hl;
+                            H[r] = h;
+                            E[r] = e;
+                            hu = h;
+                            fu = f;
+                        }
+                        dir[((int64_t)p * nsteps + t) * 64 + b] = bits;
+                        hbot = hu;
+                        fbot = fu;
+                        if (b == 63 && p + 1 < passes) { bh[j - 1] = hbot; bf[j - 1] = fbot; }
+                    }
+                    diag_top = htop;
+                    up_h = (int)align_shr1((uint32_t)hbot);
+                    up_f = (int)align_shr1((uint32_t)fbot);
+                }
+                lo = hi;
+                hi = nx;
+                nx = nn;
+                vh = wh;
+                vf = wf;
+            }
+            if (c == nch - 1) {
+                // this band's first end cell, then the first over the wave's bands
+                int sc = 0, ci = 0, cj = 0;
+#pragma unroll
+                for (int r = 0; r < kAlignRows; ++r)
+                    if (bs[r] > 0 && end_before(bs[r], row0 + r + 1, bj[r], sc, ci, cj)) { sc = bs[r]; ci = row0 + r + 1; cj = bj[r]; }
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int s2 = __shfl_xor(sc, o, 64), i2 = __shfl_xor(ci, o, 64), j2 = __shfl_xor(cj, o, 64);
+                    if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
+                }
+                if (sc > 0 && (best_s == 0 || end_before(sc, ci, cj, best_s, best_i, best_j))) { best_s = sc; best_i = ci; best_j = cj; }
+            }
         }
-        if (s > 0 && (best_s == 0 || end_before(s, ci, cj, best_s, best_i, best_j))) { best_s = s; best_i = ci; best_j = cj; }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary row visible to the next pass
-        __syncthreads();
+        __syncthreads();                        // this stage's bottom rows are visible to the next bands
     }
     if (b == 0) {
-        best[3 * blockIdx.x] = best_s;
-        best[3 * blockIdx.x + 1] = best_i;
-        best[3 * blockIdx.x + 2] = best_j;
+        wbest[wave][0] = best_s;
+        wbest[wave][1] = best_i;
+        wbest[wave][2] = best_j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sc = 0, ci = 0, cj = 0;
+        for (int w = 0; w < W; ++w) {
+            const int s2 = wbest[w][0], i2 = wbest[w][1], j2 = wbest[w][2];
+            if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
+        }
+        best[3 * blockIdx.x] = sc;
+        best[3 * blockIdx.x + 1] = ci;
+        best[3 * blockIdx.x + 2] = cj;
     }
 }
 
-// One thread per pair: walk the direction bytes back from the end cell.
-// Operations are written last to first; begin positions and the count go to
-// info[4 * pair] = (q_begin, s_begin, count, status).
-__global__ void k_align_trace(const AlignPair* pairs, int npairs, int m, const uint8_t* dirs, const int32_t* best,
-                              char* ops, int64_t ops_stride, int64_t* info) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= npairs) return;
+// One wave per pair: walk the direction bytes back from the end cell, one
+// lane following the path through LDS copies of up to kTraceSteps step
+// records of the band it is in.  Operations are written last to first; begin
+// positions and the count go to info[4 * pair] = (q_begin, s_begin, count,
+// status).
+__global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, int npairs, int m, const uint8_t* dirs,
+                                                    const int32_t* best, char* ops, int64_t ops_stride, int64_t* info) {
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kTraceSteps * 256];
+    __shared__ int64_t walk[6];                 // i, j, len, state, done, status
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
     const AlignPair P = pairs[k];
     const int n = P.n;
     const int nsteps = n + 63;
@@ -185,56 +254,94 @@ __global__ void k_align_trace(const AlignPair* pairs, int npairs, int m, const u
     int64_t len = 0;
     int state = 0;                              // 0: H, 1: E, 2: F
     int64_t status = 0;
-    auto byte_at = [&](int ii, int jj) -> uint32_t {
-        const int row = ii - 1;
-        const int p = row / kAlignPass, b = (row % kAlignPass) / kAlignRows, r = row % kAlignRows;
-        const int t = jj - 1 + b;
-        return dir[(((int64_t)p * nsteps + t) * 64 + b) * 4 + r];
-    };
-    if (best[3 * k] > 0) {
-        for (;;) {
-            if (i < 1 || j < 1 || i > m || j > n || len >= ops_stride) {
-                if (state != 0) status = 1;     // a gap cannot reach the border: inconsistent bytes
-                break;
-            }
-            const uint32_t v = byte_at(i, j);
-            if (state == 0) {
-                const uint32_t src = v & 3u;
-                if (src == 0) break;
-                if (src == 1) { out[len++] = 'M'; --i; --j; }
-                else state = (int)src - 1;
-            } else if (state == 1) {
-                out[len++] = 'D';
-                if (v & 4u) state = 0;
-                --j;
-            } else {
-                out[len++] = 'I';
-                if (v & 8u) state = 0;
-                --i;
-            }
-        }
-    } else {
+    bool done = best[3 * k] <= 0;
+    if (done) {
         i = 0;
         j = 0;
     }
-    info[4 * k] = i;
-    info[4 * k + 1] = j;
-    info[4 * k + 2] = len;
-    info[4 * k + 3] = status;
+    while (!done) {                             // wave-uniform
+        if (i < 1 || j < 1 || i > m || j > n || len >= ops_stride) {
+            if (state != 0) status = 1;         // a gap cannot reach the border: inconsistent bytes
+            break;
+        }
+        const int row = i - 1;
+        const int p = row / kAlignPass;
+        const int t = j - 1 + (row % kAlignPass) / kAlignRows;
+        const int t0 = max(0, t - kTraceSteps + 1);
+        // step records t0 .. t of band p: (t - t0 + 1) * 256 contiguous bytes
+        const uint4* src = reinterpret_cast<const uint4*>(dir + ((int64_t)p * nsteps + t0) * 256);
+        const int words = (t - t0 + 1) * 16;
+        for (int x = lane; x < words; x += 64) reinterpret_cast<uint4*>(tile)[x] = src[x];
+        __syncthreads();
+        if (lane == 0) {
+            for (;;) {
+                if (i < 1 || j < 1 || i > m || j > n || len >= ops_stride) {
+                    if (state != 0) status = 1;
+                    done = true;
+                    break;
+                }
+                const int rw = i - 1;
+                if (rw / kAlignPass != p) break;                 // another band: copy again
+                const int bb = (rw % kAlignPass) / kAlignRows;
+                const int tt = j - 1 + bb;
+                if (tt < t0) break;                              // before the copied steps
+                const uint32_t v = tile[((tt - t0) * 64 + bb) * 4 + (rw % kAlignRows)];
+                if (state == 0) {
+                    const uint32_t sr = v & 3u;
+                    if (sr == 0) { done = true; break; }
+                    if (sr == 1) { out[len++] = 'M'; --i; --j; }
+                    else state = (int)sr - 1;
+                } else if (state == 1) {
+                    out[len++] = 'D';
+                    if (v & 4u) state = 0;
+                    --j;
+                } else {
+                    out[len++] = 'I';
+                    if (v & 8u) state = 0;
+                    --i;
+                }
+            }
+            walk[0] = i;
+            walk[1] = j;
+            walk[2] = len;
+            walk[3] = state;
+            walk[4] = done;
+            walk[5] = status;
+        }
+        __syncthreads();
+        i = (int)walk[0];
+        j = (int)walk[1];
+        len = walk[2];
+        state = (int)walk[3];
+        done = walk[4] != 0;
+        status = walk[5];
+        __syncthreads();                        // everyone has read the state before the next copy
+    }
+    if (lane == 0) {
+        info[4 * k] = i;
+        info[4 * k + 1] = j;
+        info[4 * k + 2] = len;
+        info[4 * k + 3] = status;
+    }
 }
 
 hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
                         int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
                         int64_t* info, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64), 0, st, pairs, query, m, subst, A, go, ge, dirs, bnd, best);
+    const int passes = (m + kAlignPass - 1) / kAlignPass;
+    // waves per pair: one per band up to 16, and the profiles within 64 KiB of LDS
+    int W = passes < kAlignWaves ? passes : kAlignWaves;
+    const int fit = (65536 - 1024) / (A * kAlignPass);
+    if (W > fit) W = fit;
+    const size_t lds = (size_t)W * A * kAlignPass;
+    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, query, m, subst, A, go, ge, dirs, bnd,
+                       best);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_align_trace, dim3((npairs + 63) / 64), dim3(64), 0, st, pairs, npairs, m, dirs, best, ops,
-                       ops_stride, info);
+    hipLaunchKernelGGL(k_align_trace, dim3(npairs), dim3(64), 0, st, pairs, npairs, m, dirs, best, ops, ops_stride, info);
     return hipGetLastError();
 }
-
 int64_t align_bnd_words(int64_t n) { return 2 * ((n + 3) & ~(int64_t)3); }
 
 int64_t align_dir_bytes(int m, int64_t n) {

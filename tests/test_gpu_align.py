@@ -138,3 +138,56 @@ def test_alignments_with_the_extended_alphabet(gpu):
     idx = list(range(db.n))
     _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24")
     D.close()
+
+
+def _plant(rng, q, s, a, k):
+    """Copy query residues q[a:a+k] into s with a 3-residue insertion halfway, so
+    the alignment crosses many bands of query rows and includes a gap."""
+    k = min(k, q.size - a, s.size - 13)
+    if k < 8:
+        return
+    h = k // 2
+    seg = np.concatenate([q[a:a + h], synth.background_residues(rng, 3), q[a + h:a + k]])
+    s[10:10 + seg.size] = seg[: s.size - 10]
+
+
+@pytest.mark.parametrize("m,lens", [
+    (1300, [1, 5, 127, 128, 129, 600, 9000]),
+    (3072, [64, 700, 2500]),
+    (4200, [1, 300, 1800, 3000]),
+])
+def test_many_bands_in_flight(gpu, blosum, m, lens):
+    """Queries of several to 17 bands of 256 rows, more bands than waves per
+    pair, subjects from 1 residue to many stages of columns."""
+    rng = np.random.default_rng(m)
+    q = synth.background_residues(rng, m)
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    for s in subs:
+        _plant(rng, q, s, 7, s.size)
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    idx = list(range(db.n))
+    got = D.align(q, idx, blosum, 10, 2)
+    assert max(len(a["ops"]) for a in got) > 1000 or m < 2000
+    _compare(got, q, db, idx, blosum, 10, 2, f"m={m}")
+    D.close()
+
+
+def test_many_bands_with_the_extended_alphabet(gpu):
+    """24 letters leave room for fewer waves per pair: 12 bands wrap around."""
+    from inputs import blosum62_24
+    sm = blosum62_24()
+    rng = np.random.default_rng(2900)
+    q = rng.integers(0, 24, 2900).astype(np.int8)
+    subs = [rng.integers(0, 24, int(L)).astype(np.int8) for L in (2, 900, 2600)]
+    for s in subs:
+        _plant(rng, q, s, 100, s.size)
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum([s.size for s in subs])
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets, alphabet=24)
+    idx = list(range(db.n))
+    _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24, 12 bands")
+    D.close()
