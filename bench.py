@@ -121,27 +121,49 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     print(f"# plain service time {service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
     trace = qs[: warm + args.requests]
     arrivals = synth.poisson_arrivals(rate, len(trace))
+    pols = set(args.policies.split(","))
+    if not {"served", "plain"} <= pols:
+        raise SystemExit("--policies must include served and plain")
+
+    def progress(name):
+        step = max(1, args.requests // 5)
+
+        def cb(done, total):
+            if done % step == 0 or done == total:
+                print(f"# {name}: {done}/{total} requests done", file=sys.stderr, flush=True)
+        return cb
+
+    D.tune(lane_pack=args.lane_pack)
     eng = GpuEngine(D, sm, 10, 2, k=10)
     srv = Server(eng, nchunks=args.chunks, mem_budget=2 << 30)
     srv.run(trace[:warm], arrivals[:warm] - arrivals[0])
     print("# served: warm-up done", file=sys.stderr, flush=True)
-    rep = srv.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells)
+    rep = srv.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells, progress=progress("served"))
     served = rep.summary()
+    D.tune()
     print(f"# served: {served}", file=sys.stderr, flush=True)
-    fifo_rep = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells)
+    fifo_rep = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells,
+                        progress=progress("plain FIFO"))
     fifo = fifo_rep.summary()
     print(f"# plain FIFO: {fifo}", file=sys.stderr, flush=True)
-    D.tune(lane_pack=2)
-    batch_run(D, trace[:warm], arrivals[:warm] - arrivals[0], sm)
-    dyn_rep = batch_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells)
-    dyn = dyn_rep.summary()
-    D.tune()
-    print(f"# dynamic batching: {dyn}", file=sys.stderr, flush=True)
+    dyn_rep, dyn, dyn_reps = None, None, {}
+    for pol, lp in (("dynamic", 1), ("dynamic-q2", 2)):
+        if pol not in pols:
+            continue
+        D.tune(lane_pack=lp)
+        batch_run(D, trace[:warm], arrivals[:warm] - arrivals[0], sm)
+        r = batch_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells,
+                      progress=progress(pol))
+        D.tune()
+        dyn_reps[pol] = r
+        print(f"# {pol}: {r.summary()}", file=sys.stderr, flush=True)
+    if dyn_reps:
+        dyn_rep = dyn_reps.get("dynamic-q2", dyn_reps.get("dynamic"))
+        dyn = dyn_rep.summary()
     # every policy must return the same top-10 for every request
-    same = all(np.array_equal(fifo_rep.results[i][0], dyn_rep.results[i][0]) and
-               np.array_equal(fifo_rep.results[i][1], dyn_rep.results[i][1]) and
-               np.array_equal(fifo_rep.results[i][0], rep.results[i][0]) and
-               np.array_equal(fifo_rep.results[i][1], rep.results[i][1]) for i in fifo_rep.results)
+    others = [rep] + list(dyn_reps.values())
+    same = all(np.array_equal(fifo_rep.results[i][0], o.results[i][0]) and
+               np.array_equal(fifo_rep.results[i][1], o.results[i][1]) for o in others for i in fifo_rep.results)
     res = {
         "metric": METRIC, "value": round(served["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.requests,
         "warmup": warm, "ms_per_step": round(served["makespan_s"] / args.requests * 1e3, 3),
@@ -150,12 +172,16 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
         "config": {"workload": "serve10M", "form": "served (continuous batching)", "subjects": db.n,
                    "residues": total_res, "requests": args.requests, "arrival_rate_per_s": round(rate, 3),
                    "load_vs_plain": args.load, "chunks": args.chunks, "mem_budget_bytes": 2 << 30,
+                   "lane_pack": args.lane_pack,
                    "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
         "latency": {"served_p50_s": round(served["p50_s"], 4), "served_p99_s": round(served["p99_s"], 4),
-                    "dynamic_batching_p50_s": round(dyn["p50_s"], 4), "dynamic_batching_p99_s": round(dyn["p99_s"], 4),
+                    "dynamic_batching_p50_s": round(dyn["p50_s"], 4) if dyn else None,
+                    "dynamic_batching_p99_s": round(dyn["p99_s"], 4) if dyn else None,
                     "plain_p50_s": round(fifo["p50_s"], 4), "plain_p99_s": round(fifo["p99_s"], 4),
                     "p99_gain": round(fifo["p99_s"] / served["p99_s"], 3) if served["p99_s"] > 0 else None},
-        "extra": {"served": served, "plain_fifo": fifo, "dynamic_batching": dyn, "same_top10_all_policies": same,
+        "extra": {"served": served, "plain_fifo": fifo, "dynamic_batching": dyn,
+                  "dynamic_by_lane_pack": {k: v.summary() for k, v in dyn_reps.items()},
+                  "same_top10_all_policies": same,
                   "pct_int32_cell_peak": round(100 * served["gcups"] / perfmodel.mi355x_peak_gcups(), 2)},
     }
     D.close()
@@ -163,7 +189,9 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
 
 
 def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
-    """Alignment form: search each query, then align its top 10 (traceback)."""
+    """Alignment form: search each query, then align the top 10 of every query
+    in one sw_align_batch call per step; one sw_align call per query is timed
+    beside it."""
     import torch
     out = torch.empty(db.n, dtype=torch.int32, device="cuda")
     tops = []
@@ -174,25 +202,31 @@ def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
     lens = np.diff(db.offsets)
     cells = sum(int(q.size) * int(lens[t].sum()) for q, t in zip(queries, tops))
     for i in range(args.warmup):
-        for q, t in zip(queries, tops):
-            D.align(q, t, sm, 10, 2)
+        D.align_batch(queries, tops, sm, 10, 2)
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
-        for q, t in zip(queries, tops):
-            al = D.align(q, t, sm, 10, 2)
+        al = D.align_batch(queries, tops, sm, 10, 2)
         print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for q, t in zip(queries, tops):
+        one = D.align(q, t, sm, 10, 2)
+    el1 = time.perf_counter() - t1
+    same = all(D.align(q, t, sm, 10, 2) == a for q, t, a in zip(queries[:3], tops[:3], al[:3]))
     n_al = len(queries) * 10
     res = {
         "metric": "GCUPS of the traceback (top-10 alignments per query)", "value": round(cells * args.steps / el / 1e9, 2),
         "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(el / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "form": "align", "queries": len(queries), "alignments_per_query": 10,
-                   "subjects": db.n, "residues": total_res, "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
+        "config": {"workload": args.workload, "form": "align (one sw_align_batch call per step)",
+                   "queries": len(queries), "alignments_per_query": 10, "subjects": db.n, "residues": total_res,
+                   "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
         "extra": {"alignments_per_s": round(n_al * args.steps / el, 1), "cells_per_step": cells,
-                  "last_alignment": {k: al[-1][k] for k in ("score", "q_begin", "q_end", "s_begin", "s_end")}},
+                  "one_call_per_query": {"gcups": round(cells / el1 / 1e9, 2), "ms": round(el1 * 1e3, 3)},
+                  "batch_equals_per_query": same,
+                  "last_alignment": {k: al[-1][-1][k] for k in ("score", "q_begin", "q_end", "s_begin", "s_end")}},
     }
     D.close()
     print(json.dumps(res), flush=True)
@@ -208,6 +242,11 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
+    ap.add_argument("--lane-pack", type=int, default=1, choices=[1, 2],
+                    help="served form: 2 = requests that share an iteration share lanes two queries at a time")
+    ap.add_argument("--policies", default="served,plain,dynamic-q2",
+                    help="served form: comma list of served, plain (both required), dynamic (batches of waiting "
+                         "requests, subject pairs per lane), dynamic-q2 (the same with query pairs per lane)")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--mode", default="local", choices=["local", "global", "semiglobal"],
                     help="plain form: alignment mode (global and semi-global run in 32-bit cells)")

@@ -248,11 +248,32 @@ typedef struct {
  * over one that extends.  S = 0 gives an empty alignment (all fields 0).
  * Synchronous: the work runs on `stream` and the call returns when the host
  * buffers are filled.  Device memory: about qlen x subject length bytes per
- * pair, in rounds of pairs that fit 1 GiB (a larger single pair runs alone).
+ * pair, in rounds of pairs that fit 4 GiB (a larger single pair runs alone).
  */
 sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
                    const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,
                    int64_t ops_stride, sw_stream stream);
+
+/*
+ * sw_align_batch - sw_align for several queries in one call, e.g. the top hits
+ * of every query of a batched search (Sec. II-B).  Query q is
+ * h_queries[h_qoffsets[q] .. h_qoffsets[q+1]) and is aligned against the
+ * subjects h_subjects[h_soffsets[q] - h_soffsets[0] .. h_soffsets[q+1] -
+ * h_soffsets[0]).  The pairs of all queries share the launches, longest
+ * first, so many queries' alignments run at once; each result equals what
+ * sw_align returns for that query and subject.
+ *   h_qoffsets : host int64[nq + 1], non-decreasing; each query <= 2^20 residues.
+ *   h_soffsets : host int64[nq + 1], non-decreasing, h_soffsets[0] >= 0;
+ *                P = h_soffsets[nq] - h_soffsets[0] pairs.
+ *   h_out      : host sw_alignment[P], in the order of h_subjects.
+ *   h_ops      : host char[P * ops_stride], as for sw_align.
+ *   ops_stride : >= query length + subject length for every pair (SW_E_SIZE).
+ * Errors as for sw_align; nq = 0 does nothing.  Synchronous, with the same
+ * device memory rounds as sw_align.
+ */
+sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                         const int64_t* h_subjects, const int64_t* h_soffsets, const int8_t* h_subst, int32_t gap_open,
+                         int32_t gap_extend, sw_alignment* h_out, char* h_ops, int64_t ops_stride, sw_stream stream);
 
 /* Human-readable name of a status code (static string). */
 const char* sw_status_str(sw_status s);

@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
-           "sw_search_multi", "sw_align", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws",
+           "sw_search_multi", "sw_align", "sw_align_batch", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -71,6 +71,8 @@ def load():
     lib.sw_search_mode.argtypes = [I32, P, I32, P, P, I64, P, I32, I32, P, P]
     lib.sw_align.restype = I32
     lib.sw_align.argtypes = [P, I32, P, P, I32, P, I32, I32, P, P, I64, P]
+    lib.sw_align_batch.restype = I32
+    lib.sw_align_batch.argtypes = [P, P, I32, P, P, P, P, I32, I32, P, P, I64, P]
     lib.sw_status_str.restype = ctypes.c_char_p
     lib.sw_status_str.argtypes = [I32]
     lib.sw_last_error.restype = ctypes.c_char_p
@@ -280,6 +282,18 @@ class Database:
         longest = int(lens[np.clip(subs, 0, self.n - 1)].max()) if subs.size and self.n > 0 else 0
         return sw_align(query, self.handle, subs, subst, gap_open, gap_extend, longest, stream)
 
+    def align_batch(self, queries, subjects, subst, gap_open=10, gap_extend=2, stream=None):
+        """Alignments of each query against its own list of subject indices, in
+        one call (see ``sw_align_batch``): a list per query of ``align``'s dicts."""
+        subst = self.matrix(subst)
+        lens = np.diff(self.offsets)
+        subs = [_host_i64(s) for s in subjects]
+        if len(subs) != len(queries):
+            raise ValueError("one subject list per query")
+        # out-of-range indices are left for the library to reject
+        longest = max([int(lens[np.clip(s, 0, self.n - 1)].max()) for s in subs if s.size and self.n > 0] or [0])
+        return sw_align_batch(queries, self.handle, subs, subst, gap_open, gap_extend, longest, stream)
+
     def search_batch(self, queries, subst, gap_open=10, gap_extend=2, k=10, keep_scores=True, stream=None):
         """(scores [nq, n] or None, top scores [nq, k], top indices [nq, k])."""
         import torch
@@ -328,6 +342,37 @@ def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stre
         a = out[k]
         res.append({"score": a.score, "q_begin": a.q_begin, "q_end": a.q_end, "subject": a.subject,
                     "s_begin": a.s_begin, "s_end": a.s_end, "ops": raw[k * stride: k * stride + a.n_ops].decode()})
+    return res
+
+
+def sw_align_batch(queries, handle, subjects, subst, gap_open, gap_extend, longest, stream=None):
+    """``sw_align`` for several queries: ``subjects[q]`` are the subject indices
+    of query ``q``; returns one list of alignment dicts per query."""
+    qs = [_host_i8(q) for q in queries]
+    subs = [_host_i64(s) for s in subjects]
+    qo = np.zeros(len(qs) + 1, dtype=np.int64)
+    qo[1:] = np.cumsum([q.size for q in qs])
+    so = np.zeros(len(subs) + 1, dtype=np.int64)
+    so[1:] = np.cumsum([s.size for s in subs])
+    cat_q = np.concatenate(qs) if qs else np.zeros(0, np.int8)
+    cat_s = np.concatenate(subs) if subs else np.zeros(0, np.int64)
+    sm = _square(subst)
+    npairs = int(so[-1])
+    stride = int(max([q.size for q in qs] or [0]) + longest + 1)
+    out = (Alignment * max(npairs, 1))()
+    ops = ctypes.create_string_buffer(max(npairs, 1) * stride)
+    _check(load().sw_align_batch(_ptr(cat_q), _ptr(qo), len(qs), handle, _ptr(cat_s), _ptr(so), _ptr(sm),
+                                 int(gap_open), int(gap_extend), ctypes.cast(out, ctypes.c_void_p), ops, stride,
+                                 _stream(stream)))
+    raw = ops.raw
+    res = []
+    for q in range(len(qs)):
+        row = []
+        for k in range(int(so[q]), int(so[q + 1])):
+            a = out[k]
+            row.append({"score": a.score, "q_begin": a.q_begin, "q_end": a.q_end, "subject": a.subject,
+                        "s_begin": a.s_begin, "s_end": a.s_end, "ops": raw[k * stride: k * stride + a.n_ops].decode()})
+        res.append(row)
     return res
 
 

@@ -38,6 +38,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sw_internal.h"
 
 namespace sw {
@@ -73,16 +75,19 @@ __device__ __forceinline__ align_rsrc align_buffer(const void* base, uint32_t by
 // profile of each wave's band, prof[d][row] with the rows of lane b at bytes
 // 4b .. 4b + 3 of each residue row (W * A * 256 bytes), built from a copy of
 // the substitution matrix in LDS.
-__global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair* pairs, const int8_t* query, int m,
-                                                                 const int8_t* subst, int A, int go, int ge,
-                                                                 uint8_t* dirs, int32_t* bnd, int32_t* best) {
+// A pair with fewer bands than the workgroup has waves leaves the other waves
+// idle (they still take part in every barrier).
+__global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair* pairs, const int8_t* subst, int A,
+                                                                 int go, int ge, uint8_t* dirs, int32_t* bnd,
+                                                                 int32_t* best) {
     extern __shared__ __attribute__((aligned(16))) int8_t align_lds[];
     __shared__ int wbest[kAlignWaves][3];
     __shared__ int8_t sm[kMaxAlphabet * kMaxAlphabet];
     const AlignPair P = pairs[blockIdx.x];
     const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int b = threadIdx.x & 63;
-    const int W = (int)(blockDim.x >> 6);
+    const int8_t* query = P.query;
+    const int m = P.m;
     int8_t* prof = align_lds + wave * (A * kAlignPass);
     for (int e = threadIdx.x; e < A * A; e += blockDim.x) sm[e] = subst[e];
     __syncthreads();
@@ -94,6 +99,7 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     const align_rsrc bhr = align_buffer(bh, (uint32_t)n4 * 4), bfr = align_buffer(bf, (uint32_t)n4 * 4);
     uint32_t* dir = reinterpret_cast<uint32_t*>(dirs + P.dir_off);
     const int passes = (m + kAlignPass - 1) / kAlignPass;
+    const int W = min((int)(blockDim.x >> 6), passes);            // waves of this pair
     const int nsteps = n + 63;
     const int nloop = (nsteps + 3) >> 2;
     const int nch = (nloop + kAlignStage - 1) / kAlignStage;     // stages per band
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     for (int s = 0; s < nstages; ++s) {
         // the band of this wave in stage s, if any: bands wave, wave + W, ... start every W * L stages
         int p = -1, c = 0;
-        if (s >= wave * L) {
+        if (wave < W && s >= wave * L) {
             const int kk = wave + (s - wave * L) / (W * L) * W;
             const int cc = s - kk * L;
             if (kk < passes && cc < nch) { p = kk; c = cc; }
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
         }
         __syncthreads();                        // this stage's bottom rows are visible to the next bands
     }
-    if (b == 0) {
+    if (b == 0 && wave < W) {
         wbest[wave][0] = best_s;
         wbest[wave][1] = best_i;
         wbest[wave][2] = best_j;
@@ -236,17 +242,22 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
 
 // One wave per pair: walk the direction bytes back from the end cell, one
 // lane following the path through LDS copies of up to kTraceSteps step
-// records of the band it is in.  Operations are written last to first; begin
-// positions and the count go to info[4 * pair] = (q_begin, s_begin, count,
-// status).
-__global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, int npairs, int m, const uint8_t* dirs,
-                                                    const int32_t* best, char* ops, int64_t ops_stride, int64_t* info) {
+// records of the band it is in; the byte of (row rb of the band, 0-based
+// column c) sits at ((c + rb / 4 - t0) * 256 + rb) in a copy that starts at
+// step t0.  Operations, last to first, collect in LDS and the wave writes
+// them out after each copy; begin positions and the count go to
+// info[4 * pair] = (q_begin, s_begin, count, status).
+constexpr int kTraceOps = 1024;                  // operations buffered in LDS per copy
+
+__global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, const uint8_t* dirs, const int32_t* best,
+                                                    char* ops, int64_t ops_stride, int64_t* info) {
     __shared__ __attribute__((aligned(16))) uint8_t tile[kTraceSteps * 256];
-    __shared__ int64_t walk[6];                 // i, j, len, state, done, status
+    __shared__ char obuf[kTraceOps];
+    __shared__ int64_t walk[7];                 // i, j, len, state, done, status, buffered operations
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
     const AlignPair P = pairs[k];
-    const int n = P.n;
+    const int n = P.n, m = P.m;
     const int nsteps = n + 63;
     const uint8_t* dir = dirs + P.dir_off;
     char* out = ops + (int64_t)k * ops_stride;
@@ -274,48 +285,50 @@ __global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, int 
         for (int x = lane; x < words; x += 64) reinterpret_cast<uint4*>(tile)[x] = src[x];
         __syncthreads();
         if (lane == 0) {
-            for (;;) {
-                if (i < 1 || j < 1 || i > m || j > n || len >= ops_stride) {
-                    if (state != 0) status = 1;
-                    done = true;
-                    break;
-                }
-                const int rw = i - 1;
-                if (rw / kAlignPass != p) break;                 // another band: copy again
-                const int bb = (rw % kAlignPass) / kAlignRows;
-                const int tt = j - 1 + bb;
-                if (tt < t0) break;                              // before the copied steps
-                const uint32_t v = tile[((tt - t0) * 64 + bb) * 4 + (rw % kAlignRows)];
+            int rb = row - p * kAlignPass;      // row within the band
+            int c = j - 1;                      // 0-based column
+            int cnt = 0;
+            const int64_t room = ops_stride - len;
+            const int cap = room < kTraceOps ? (int)room : kTraceOps;
+            // leaves at the band's top, the matrix border, a full buffer or the copy's first step;
+            // the outer loop sorts these out
+            while (rb >= 0 && c >= 0 && cnt < cap) {
+                const int tt = c + (rb >> 2);
+                if (tt < t0) break;
+                const uint32_t v = tile[(tt - t0) * 256 + rb];
                 if (state == 0) {
                     const uint32_t sr = v & 3u;
                     if (sr == 0) { done = true; break; }
-                    if (sr == 1) { out[len++] = 'M'; --i; --j; }
+                    if (sr == 1) { obuf[cnt++] = 'M'; --rb; --c; }
                     else state = (int)sr - 1;
                 } else if (state == 1) {
-                    out[len++] = 'D';
+                    obuf[cnt++] = 'D';
                     if (v & 4u) state = 0;
-                    --j;
+                    --c;
                 } else {
-                    out[len++] = 'I';
+                    obuf[cnt++] = 'I';
                     if (v & 8u) state = 0;
-                    --i;
+                    --rb;
                 }
             }
-            walk[0] = i;
-            walk[1] = j;
-            walk[2] = len;
+            walk[0] = rb + p * kAlignPass + 1;
+            walk[1] = c + 1;
+            walk[2] = len + cnt;
             walk[3] = state;
             walk[4] = done;
             walk[5] = status;
+            walk[6] = cnt;
         }
         __syncthreads();
+        const int cnt = (int)walk[6];
+        for (int x = lane; x < cnt; x += 64) out[len + x] = obuf[x];
         i = (int)walk[0];
         j = (int)walk[1];
         len = walk[2];
         state = (int)walk[3];
         done = walk[4] != 0;
         status = walk[5];
-        __syncthreads();                        // everyone has read the state before the next copy
+        __syncthreads();                        // everyone has read the state and the buffer before the next copy
     }
     if (lane == 0) {
         info[4 * k] = i;
@@ -325,23 +338,29 @@ __global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, int 
     }
 }
 
-hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
-                        int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
-                        int64_t* info, hipStream_t st) {
+// W = waves per workgroup: the most bands of a pair in the launch, at most 16
+// and at most align_waves_fit(A).
+hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
+                        uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
+                        hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    const int passes = (m + kAlignPass - 1) / kAlignPass;
-    // waves per pair: one per band up to 16, and the profiles within 64 KiB of LDS
-    int W = passes < kAlignWaves ? passes : kAlignWaves;
-    const int fit = (65536 - 1024) / (A * kAlignPass);
-    if (W > fit) W = fit;
+    if (W < 1 || W > kAlignWaves || (size_t)W * A * kAlignPass > 65536 - 1024) return hipErrorInvalidValue;
     const size_t lds = (size_t)W * A * kAlignPass;
-    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, query, m, subst, A, go, ge, dirs, bnd,
-                       best);
+    hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, subst, A, go, ge, dirs, bnd, best);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_align_trace, dim3(npairs), dim3(64), 0, st, pairs, npairs, m, dirs, best, ops, ops_stride, info);
+    hipLaunchKernelGGL(k_align_trace, dim3(npairs), dim3(64), 0, st, pairs, dirs, best, ops, ops_stride, info);
     return hipGetLastError();
 }
+
+// Waves per pair: one per band of 256 query rows, up to 16, with the bands'
+// profiles (A x 256 bytes each) within 64 KiB of LDS.
+int align_waves(int m, int A) {
+    const int passes = (m + kAlignPass - 1) / kAlignPass;
+    const int fit = (65536 - 1024) / (A * kAlignPass);
+    return std::max(1, std::min(std::min(passes, kAlignWaves), fit));
+}
+
 int64_t align_bnd_words(int64_t n) { return 2 * ((n + 3) & ~(int64_t)3); }
 
 int64_t align_dir_bytes(int m, int64_t n) {

@@ -35,9 +35,10 @@ hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
 hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu);
-hipError_t launch_align(const AlignPair* pairs, int npairs, const int8_t* query, int m, const int8_t* subst, int A, int go,
-                        int ge, uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride,
-                        int64_t* info, hipStream_t st);
+hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
+                        uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
+                        hipStream_t st);
+int align_waves(int m, int A);
 int64_t align_dir_bytes(int m, int64_t n);
 int64_t align_bnd_words(int64_t n);
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
@@ -1127,80 +1128,123 @@ sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
 
 // ------------------------------------------------------------------ alignments
 namespace {
-constexpr int64_t kAlignBudget = (int64_t)1 << 30;   // direction bytes per round of pairs
+constexpr int64_t kAlignBudget = (int64_t)4 << 30;   // direction bytes per round of pairs
 }
 
-sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
-                   const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,
-                   int64_t ops_stride, sw_stream stream) {
+sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                         const int64_t* h_subjects, const int64_t* h_soffsets, const int8_t* h_subst, int32_t gap_open,
+                         int32_t gap_extend, sw_alignment* h_out, char* h_ops, int64_t ops_stride, sw_stream stream) {
     g_err.clear();
     sw_status s;
     if (!db) return fail(SW_E_INVALID, "db is NULL");
     if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
-    if (qlen < 0 || nsub < 0) return fail(SW_E_INVALID, "qlen and nsub must be >= 0");
-    if (qlen > (1 << 20)) return fail(SW_E_UNSUPPORTED, "query longer than 2^20 residues");
-    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
-    if (nsub > 0 && (!h_subjects || !h_out || !h_ops)) return fail(SW_E_INVALID, "NULL subjects or outputs");
-    for (int32_t i = 0; i < qlen; ++i)
-        if (h_query[i] < 0 || h_query[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
-    int64_t longest = 0;
-    for (int32_t k = 0; k < nsub; ++k) {
-        if (h_subjects[k] < 0 || h_subjects[k] >= db->n) return fail(SW_E_INVALID, "subject index %lld outside 0..n-1", (long long)h_subjects[k]);
-        longest = std::max<int64_t>(longest, db->lens[h_subjects[k]]);
+    if (nq < 0) return fail(SW_E_INVALID, "nq must be >= 0");
+    if (nq > 0 && (!h_qoffsets || !h_soffsets)) return fail(SW_E_INVALID, "NULL offsets");
+    if (nq == 0) return SW_OK;
+    if (h_soffsets[0] < 0) return fail(SW_E_INVALID, "subject offsets start below 0");
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t m = h_qoffsets[q + 1] - h_qoffsets[q];
+        if (m < 0) return fail(SW_E_INVALID, "query offsets decrease at %d", q);
+        if (m > (1 << 20)) return fail(SW_E_UNSUPPORTED, "query %d longer than 2^20 residues", q);
+        if (h_soffsets[q + 1] < h_soffsets[q]) return fail(SW_E_INVALID, "subject offsets decrease at %d", q);
+        if (m > 0 && !h_queries) return fail(SW_E_INVALID, "queries is NULL");
+        for (int64_t i = h_qoffsets[q]; i < h_qoffsets[q + 1]; ++i)
+            if (h_queries[i] < 0 || h_queries[i] >= db->alphabet)
+                return fail(SW_E_RESIDUE, "query %d residue %d at %lld outside 0..%d", q, h_queries[i],
+                            (long long)(i - h_qoffsets[q]), db->alphabet - 1);
     }
-    if (nsub > 0 && ops_stride < qlen + longest) return fail(SW_E_SIZE, "ops_stride %lld < query + longest subject (%lld)",
-                                                             (long long)ops_stride, (long long)(qlen + longest));
-    for (int32_t k = 0; k < nsub; ++k) {
-        h_out[k] = sw_alignment{0, 0, 0, h_subjects[k], 0, 0, 0};
+    const int64_t s0 = h_soffsets[0], npairs = h_soffsets[nq] - s0;
+    if (npairs > 0 && (!h_subjects || !h_out || !h_ops)) return fail(SW_E_INVALID, "NULL subjects or outputs");
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t m = h_qoffsets[q + 1] - h_qoffsets[q];
+        for (int64_t k = h_soffsets[q]; k < h_soffsets[q + 1]; ++k) {
+            const int64_t sub = h_subjects[k - s0];
+            if (sub < 0 || sub >= db->n) return fail(SW_E_INVALID, "subject index %lld outside 0..n-1", (long long)sub);
+            if (ops_stride < m + db->lens[sub])
+                return fail(SW_E_SIZE, "ops_stride %lld < query + subject (%lld) for query %d", (long long)ops_stride,
+                            (long long)(m + db->lens[sub]), q);
+            h_out[k - s0] = sw_alignment{0, 0, 0, sub, 0, 0, 0};
+        }
     }
-    if (nsub == 0 || qlen == 0) return SW_OK;
+    // pairs with a non-empty query, longest first, so that the biggest fills start first
+    struct Job { int64_t k; int32_t q; int32_t m; int32_t n; int64_t cost; };
+    std::vector<Job> jobs;
+    for (int32_t q = 0; q < nq; ++q) {
+        const int32_t m = (int32_t)(h_qoffsets[q + 1] - h_qoffsets[q]);
+        if (m == 0) continue;
+        for (int64_t k = h_soffsets[q]; k < h_soffsets[q + 1]; ++k) {
+            const int32_t n = db->lens[h_subjects[k - s0]];
+            jobs.push_back({k - s0, q, m, n, align_dir_bytes(m, n)});
+        }
+    }
+    if (jobs.empty()) return SW_OK;
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int32_t k0 = 0;
-    while (k0 < nsub) {
-        // a round: consecutive pairs whose direction bytes fit the budget (at least one pair)
-        int32_t k1 = k0;
-        int64_t dir_total = 0, bnd_total = 0, n_max = 0;
-        std::vector<AlignPair> pairs;
-        while (k1 < nsub) {
-            const int64_t sub = h_subjects[k1];
-            const int32_t nres = db->lens[sub];
-            const int64_t db_bytes = align_dir_bytes(qlen, nres);
-            if (k1 > k0 && dir_total + db_bytes > kAlignBudget) break;
-            const int32_t slot = db->slot_of[sub];
-            const int g = slot / kGroupSubjects, w = slot % kGroupSubjects;
-            AlignPair P;
-            P.residues = db->image.as<uint8_t>() + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
-            P.n = nres;
-            P.dir_off = dir_total;
-            P.bnd_off = bnd_total;
-            pairs.push_back(P);
-            dir_total += round_up(db_bytes, 256);
-            bnd_total += align_bnd_words(nres);
-            n_max = std::max<int64_t>(n_max, nres);
-            ++k1;
+    size_t j0 = 0;
+    while (j0 < jobs.size()) {
+        // a round: pairs whose direction bytes fit the budget (at least one pair)
+        size_t j1 = j0;
+        int64_t dir_total = 0, bnd_total = 0, stride = 1;
+        int W = 1;
+        std::vector<int32_t> qs_used;
+        while (j1 < jobs.size()) {
+            const Job& J = jobs[j1];
+            if (j1 > j0 && dir_total + J.cost > kAlignBudget) break;
+            dir_total += round_up(J.cost, 256);
+            bnd_total += align_bnd_words(J.n);
+            stride = std::max<int64_t>(stride, (int64_t)J.m + J.n + 1);
+            W = std::max(W, align_waves(J.m, db->alphabet));
+            qs_used.push_back(J.q);
+            ++j1;
         }
-        const int np = k1 - k0;
-        const int64_t stride = qlen + n_max + 1;
-        // misc: pairs | best (3 int32 each) | info (4 int64 each) | query | matrix | ops
+        std::sort(qs_used.begin(), qs_used.end());
+        qs_used.erase(std::unique(qs_used.begin(), qs_used.end()), qs_used.end());
+        const int np = (int)(j1 - j0);
+        // misc: pairs | best (3 int32 each) | info (4 int64 each) | matrix | queries | ops
         const size_t o_pairs = 0;
         const size_t o_best = round_up(sizeof(AlignPair) * np, 256);
         const size_t o_info = o_best + round_up(12 * (size_t)np, 256);
-        const size_t o_query = o_info + round_up(32 * (size_t)np, 256);
-        const size_t o_sm = o_query + round_up(qlen, 256);
-        const size_t o_ops = o_sm + 1024;
+        const size_t o_sm = o_info + round_up(32 * (size_t)np, 256);
+        const size_t o_query = o_sm + 1024;
+        std::vector<int64_t> qpos(nq, -1);
+        size_t qbytes = 0;
+        for (int32_t q : qs_used) {
+            qpos[q] = (int64_t)qbytes;
+            qbytes += (size_t)round_up(h_qoffsets[q + 1] - h_qoffsets[q], 256);
+        }
+        const size_t o_ops = o_query + qbytes;
         const size_t misc = o_ops + (size_t)np * stride;
         HIP_TRY(db->align_dirs.reserve((size_t)std::max<int64_t>(dir_total, 256)));
         HIP_TRY(db->align_bnd.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bnd_total, 64)));
         HIP_TRY(db->align_misc.reserve(misc));
         char* mb = db->align_misc.as<char>();
+        std::vector<AlignPair> pairs(np);
+        int64_t dir_off = 0, bnd_off = 0;
+        for (int i = 0; i < np; ++i) {
+            const Job& J = jobs[j0 + i];
+            const int64_t sub = h_subjects[J.k];
+            const int32_t slot = db->slot_of[sub];
+            const int g = slot / kGroupSubjects, w = slot % kGroupSubjects;
+            AlignPair& P = pairs[i];
+            P.residues = db->image.as<uint8_t>() + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
+            P.n = J.n;
+            P.m = J.m;
+            P.query = reinterpret_cast<const int8_t*>(mb + o_query + qpos[J.q]);
+            P.dir_off = dir_off;
+            P.bnd_off = bnd_off;
+            dir_off += round_up(J.cost, 256);
+            bnd_off += align_bnd_words(J.n);
+        }
         HIP_TRY(hipMemcpyAsync(mb + o_pairs, pairs.data(), sizeof(AlignPair) * np, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(mb + o_query, h_query, qlen, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(mb + o_sm, h_subst, (size_t)db->alphabet * db->alphabet, hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, reinterpret_cast<int8_t*>(mb + o_query), qlen,
-                             reinterpret_cast<int8_t*>(mb + o_sm), db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
-                             db->align_bnd.as<int32_t>(), reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
+        for (int32_t q : qs_used)
+            HIP_TRY(hipMemcpyAsync(mb + o_query + qpos[q], h_queries + h_qoffsets[q], (size_t)(h_qoffsets[q + 1] - h_qoffsets[q]),
+                                   hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, W, reinterpret_cast<int8_t*>(mb + o_sm),
+                             db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(), db->align_bnd.as<int32_t>(),
+                             reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
                              reinterpret_cast<int64_t*>(mb + o_info), st));
         std::vector<int32_t> best(3 * (size_t)np);
         std::vector<int64_t> info(4 * (size_t)np);
@@ -1209,23 +1253,37 @@ sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t
         HIP_TRY(hipMemcpyAsync(info.data(), mb + o_info, 32 * (size_t)np, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(ops.data(), mb + o_ops, (size_t)np * stride, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        for (int k = 0; k < np; ++k) {
-            if (info[4 * k + 3] != 0) return fail(SW_E_HIP, "inconsistent traceback for subject %lld", (long long)h_subjects[k0 + k]);
-            sw_alignment& A = h_out[k0 + k];
-            const int64_t len = info[4 * k + 2];
-            A.score = best[3 * k];
-            A.q_begin = (int32_t)info[4 * k];
-            A.q_end = best[3 * k + 1];
-            A.s_begin = info[4 * k + 1];
-            A.s_end = best[3 * k + 2];
+        for (int i = 0; i < np; ++i) {
+            const Job& J = jobs[j0 + i];
+            if (info[4 * i + 3] != 0)
+                return fail(SW_E_HIP, "inconsistent traceback for subject %lld", (long long)h_subjects[J.k]);
+            sw_alignment& A = h_out[J.k];
+            const int64_t len = info[4 * i + 2];
+            A.score = best[3 * i];
+            A.q_begin = (int32_t)info[4 * i];
+            A.q_end = best[3 * i + 1];
+            A.s_begin = info[4 * i + 1];
+            A.s_end = best[3 * i + 2];
             A.n_ops = len;
-            char* dst = h_ops + (int64_t)(k0 + k) * ops_stride;
-            const char* src = ops.data() + (size_t)k * stride;
+            char* dst = h_ops + J.k * ops_stride;
+            const char* src = ops.data() + (size_t)i * stride;
             for (int64_t x = 0; x < len; ++x) dst[x] = src[len - 1 - x];     // the walk wrote them last to first
         }
-        k0 = k1;
+        j0 = j1;
     }
     return SW_OK;
+}
+
+sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
+                   const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,
+                   int64_t ops_stride, sw_stream stream) {
+    g_err.clear();
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if (qlen < 0 || nsub < 0) return fail(SW_E_INVALID, "qlen and nsub must be >= 0");
+    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
+    const int64_t qo[2] = {0, qlen}, so[2] = {0, nsub};
+    return sw_align_batch(h_query, qo, 1, db, h_subjects, so, h_subst, gap_open, gap_extend, h_out, h_ops, ops_stride,
+                          stream);
 }
 
 // ------------------------------------------------------------------ end-to-end modes

@@ -81,6 +81,8 @@ struct SweepArgs {
 struct AlignPair {
     const uint8_t* residues;  // the subject's first chunk in the image (+ 8 * pair + 4 * half of its group)
     int32_t n;                // subject length
+    int32_t m;                // query length (>= 1)
+    const int8_t* query;      // the query's residue codes on the device
     int64_t dir_off;          // byte offset of the pair's direction bytes
     int64_t bnd_off;          // int32 offset of the pair's boundary row (H then F, n rounded up to 4 words each)
 };

@@ -9,6 +9,10 @@ next iteration boundary, as soon as a slot is free and the memory budget
 (one score vector of n int32 per active request) allows, so their work
 overlaps on the device with the requests already in flight.  When a request
 has covered all chunks its top-k is taken and it retires, freeing its slot.
+Under the oldest-first policy with no cap on active requests, every active
+request runs in every iteration, so all of them score the same chunk (the
+iteration count mod ``nchunks``); on a database tuned for query pairs
+(``db.tune(lane_pack=2)``) they then share lanes two queries at a time.
 
 ``batch_run`` is dynamic batching: whenever the GPU is free, every waiting
 request (up to ``max_batch``) is searched against the whole database in one
@@ -115,7 +119,8 @@ class Server:
         self.allocated += 1
         return self.engine.new_slot()
 
-    def run(self, queries, arrivals, clock=time.perf_counter, sleep=time.sleep, cells_per_query=None) -> ServeReport:
+    def run(self, queries, arrivals, clock=time.perf_counter, sleep=time.sleep, cells_per_query=None,
+            progress=None) -> ServeReport:
         order = np.argsort(np.asarray(arrivals, dtype=np.float64), kind="stable")
         reqs = [Request(int(i), queries[int(i)], float(arrivals[int(i)])) for i in order]
         nxt = 0
@@ -166,6 +171,8 @@ class Server:
                 r.finished = now
                 self.free.append(r.slot)
                 r.slot = None
+                if progress:
+                    progress(len(results), len(reqs))
             active = [r for r in active if r.done_chunks < self.nchunks]
         lat = np.array([r.finished - r.arrival for r in sorted(reqs, key=lambda r: r.rid)])
         makespan = (max(r.finished for r in reqs) - first_arrival) if reqs else 0.0
@@ -174,7 +181,7 @@ class Server:
 
 
 def fifo_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, clock=time.perf_counter,
-             sleep=time.sleep, cells_per_query=None) -> ServeReport:
+             sleep=time.sleep, cells_per_query=None, progress=None) -> ServeReport:
     """Plain baseline: requests served one at a time in arrival order (sw_search + sw_topk)."""
     import torch
     import paper_2309_09609_amd as sw
@@ -198,13 +205,15 @@ def fifo_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, cloc
         results[i] = (ts.cpu().numpy(), ti.cpu().numpy())
         last = clock() - t0
         lat[i] = last - arrivals[i]
+        if progress:
+            progress(len(results), len(queries))
     first = float(np.min(arrivals)) if len(arrivals) else 0.0
     cells = int(sum(cells_per_query(q) for q in queries)) if cells_per_query else 0
     return ServeReport(lat, results, len(queries), 1, last - first, cells, [int(i) for i in order], busy)
 
 
 def batch_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, max_batch=16, clock=time.perf_counter,
-              sleep=time.sleep, cells_per_query=None) -> ServeReport:
+              sleep=time.sleep, cells_per_query=None, progress=None) -> ServeReport:
     """Dynamic batching (see the module docstring).  ``db`` should be tuned for
     query pairs (``db.tune(lane_pack=2)``); results are identical either way."""
     import torch
@@ -234,6 +243,8 @@ def batch_run(db, queries, arrivals, subst, gap_open=10, gap_extend=2, k=10, max
         for r, i in enumerate(batch):
             results[i] = (ts[r], ti[r])
             lat[i] = last - arrivals[i]
+        if progress:
+            progress(len(results), len(queries))
     first = float(np.min(arrivals)) if len(arrivals) else 0.0
     cells = int(sum(cells_per_query(q) for q in queries)) if cells_per_query else 0
     return ServeReport(lat, results, iterations, biggest, last - first, cells, order, busy)

@@ -53,6 +53,9 @@ def test_argument_errors_without_gpu():
     # alignments: NULL handle, negative gap
     assert lib.sw_align(q.ctypes.data, 3, None, None, 0, sm.ctypes.data, 10, 2, None, None, 0, None) == -1
     assert lib.sw_align(q.ctypes.data, 3, None, None, 0, sm.ctypes.data, -1, 2, None, None, 0, None) == -1
+    qo = np.array([0, 3], dtype=np.int64)
+    assert lib.sw_align_batch(q.ctypes.data, qo.ctypes.data, 1, None, None, qo.ctypes.data, sm.ctypes.data, 10, 2,
+                              None, None, 0, None) == -1
 
 
 def test_alignment_record_layout():

@@ -191,3 +191,29 @@ def test_many_bands_with_the_extended_alphabet(gpu):
     idx = list(range(db.n))
     _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24, 12 bands")
     D.close()
+
+
+def test_align_batch_equals_one_call_per_query(gpu, blosum):
+    """Several queries (one empty, one of 17 bands) with their own subject lists
+    (one empty, repeats) in one call: each alignment equals sw_align's and the
+    oracle's."""
+    rng = np.random.default_rng(515)
+    lens = [1, 40, 300, 700, 2000, 3500]
+    subs = [synth.background_residues(rng, L) for L in lens]
+    qs = [synth.background_residues(rng, m) for m in (0, 120, 900, 4200, 260)]
+    for i, s in enumerate(subs):
+        _plant(rng, qs[1 + i % 4], s, 3, s.size)
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    lists = [[0, 1], [0, 1, 2, 3, 4, 5], [], [5, 4, 3, 2, 1, 0, 5], [2, 2, 3]]
+    got = D.align_batch(qs, lists, blosum, 10, 2)
+    assert [len(g) for g in got] == [len(x) for x in lists]
+    for q, idx, g in zip(qs, lists, got):
+        assert g == D.align(q, idx, blosum, 10, 2)
+        _compare(g, q, db, idx, blosum, 10, 2, f"batch m={q.size}")
+    assert D.align_batch([], [], blosum, 10, 2) == []
+    with pytest.raises(gpu.SwError):
+        D.align_batch([qs[1]], [[len(lens)]], blosum, 10, 2)
+    D.close()

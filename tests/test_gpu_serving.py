@@ -32,10 +32,13 @@ def test_search_multi_covers_all_chunks(gpu, blosum, nchunks, lane_pack):
     D.close()
 
 
-def test_server_results_alone_and_in_mix(gpu, blosum):
+@pytest.mark.parametrize("lane_pack", [1, 2])
+def test_server_results_alone_and_in_mix(gpu, blosum, lane_pack):
+    """lane_pack 2: requests that share an iteration score the same chunk and
+    share lanes two queries at a time."""
     from paper_2309_09609_amd.serve import GpuEngine, Server
     db = synth.small_db(seed=77, n=3000, lo=20, hi=1500, median=300)
-    D = gpu.Database(db.residues, db.offsets)
+    D = gpu.Database(db.residues, db.offsets, lane_pack=lane_pack)
     rng = np.random.default_rng(1)
     qs = [synth.small_query(seed=100 + i, m=int(m)) for i, m in enumerate(rng.integers(30, 700, 12))]
     arrivals = np.sort(rng.uniform(0, 0.05, len(qs)))
