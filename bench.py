@@ -25,12 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GCUPS on 1 MI355X (plain vs batched), % int-VALU peak; p50/p99 query latency"
-# Algorithmic lane operations per cell in the minimal form of Eq. 1-3 (H - Go
-# shared by E and F, no move): hd = Hdiag + SM; H = max(hd, E, F) (2 max);
-# hgo = H - Go; E' = max(E - Ge, hgo); F' = max(F - Ge, hgo) -- 8 two-input
-# operations -- plus S = max(S, H), which a three-input maximum folds in for
-# two cells at a time: 8.5.
-CELL_OPS = 8.5
+# Algorithmic lane operations per cell of the 16-bit sweep, in the minimal form
+# of Eq. 1-3 (H - Go shared by E and F, no move): hd = Hdiag + SM;
+# H = max(hd, E, F) (one three-input maximum); hgo = H - Go; E - Ge; F - Ge;
+# E' = max(E - Ge, hgo, floor); F' = max(F - Ge, hgo) -- 7 operations -- plus
+# S = max(S, H), which a three-input maximum folds in for two cells at a
+# time: 7.5.
+CELL_OPS = 7.5
 
 
 def host_cores() -> int:

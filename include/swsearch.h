@@ -75,8 +75,10 @@ typedef struct {
     int32_t max_qlen;         /* unused hint, 0 */
     int32_t force_lanes;      /* test hook: 0 = planner decides; 1,2,4,...,64 = every pair of
                                  subjects is swept by this many cooperating lanes */
-    int32_t rerun_threshold;  /* test hook: 0 = 31744 (0x7C00); a smaller value sends every pair whose
-                                 16-bit score reaches it to the exact 32-bit recompute */
+    int32_t rerun_threshold;  /* test hook: 0 = the largest, 31744 (0x7C00) minus the search's 16-bit
+                                 bias c = minus the matrix's lowest score (4 for BLOSUM62); a smaller
+                                 value sends every pair whose 16-bit score reaches it to the exact
+                                 32-bit recompute */
     int32_t rows_per_lane;    /* tuning: 0 = planner decides; 4, 8 or 16 query rows per lane */
     int32_t unit_share;       /* tuning: largest work unit as a fraction of one persistent wave's
                                  share of a search, in 1/1000; 0 = default (250) */

@@ -134,11 +134,12 @@ struct Staged {
     const int8_t* sm_q = nullptr;
     int nq = 0;
     int max_mp = 0;
+    int bias = 0;                 // 16-bit cell bias: minus the lowest substitution score, at least 0
 };
 
 struct GraphEntry {
     std::vector<int> qlens;
-    int32_t go = 0, ge = 0, k = 0;
+    int32_t go = 0, ge = 0, k = 0, bias = 0;
     const void* scores = nullptr;
     const void* top_s = nullptr;
     const void* top_i = nullptr;
@@ -597,6 +598,9 @@ sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries
         qo[q] = h_qoffsets[q] - h_qoffsets[0];
     }
     memcpy(h + L.off_sm, subst, (size_t)db->alphabet * db->alphabet);
+    int lowest = 0;
+    for (int e = 0; e < db->alphabet * db->alphabet; ++e) lowest = std::min<int>(lowest, subst[e]);
+    out->bias = -lowest;
     const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
     if (qbytes) memcpy(h + L.off_sm + kMaxAlphabet * kMaxAlphabet, h_queries + h_qoffsets[0], qbytes);
     HIP_TRY(hipMemcpyAsync(db->stage.p, h, L.total, hipMemcpyHostToDevice, st));
@@ -641,7 +645,8 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
     a.rerun_count = ctr + 1;
     a.rerun_cap = (int32_t)rerun_cap;
     a.unit_list = 0;
-    a.sat = db->sat;
+    a.bias = S.bias;
+    a.sat = std::min<int32_t>(db->sat + S.bias, kSat16);
     a.qpairs = plan.qpack ? plan.qpairs.as<int2>() : nullptr;
     // the side launch takes the first slots; the bulk launch fills the rest of the GPU
     const int wg_main = plan.qpack ? db->wgQ[plan.R_main] : db->wgR[plan.R_main];
@@ -1006,7 +1011,7 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
     if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
     GraphEntry& G = db->graph;
     const bool hit = G.exec && G.gen == db->gen && G.qlens == qlens && G.go == gap_open && G.ge == gap_extend &&
-                     G.k == k && G.scores == scores && G.top_s == d_top_scores && G.top_i == d_top_index &&
+                     G.bias == S.bias && G.k == k && G.scores == scores && G.top_s == d_top_scores && G.top_i == d_top_index &&
                      G.stream == st;
     if (!hit) {
         // captured on the library's own stream (the caller's may be the legacy
@@ -1027,6 +1032,7 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
         G.qlens = qlens;
         G.go = gap_open;
         G.ge = gap_extend;
+        G.bias = S.bias;
         G.k = k;
         G.scores = scores;
         G.top_s = d_top_scores;

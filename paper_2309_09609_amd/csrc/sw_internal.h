@@ -9,7 +9,8 @@ namespace sw {
 constexpr int kMaxAlphabet = 24;  // residue codes 0..alphabet-1, alphabet <= 24 (20 amino acids + B, Z, X, *)
 constexpr int kNRes = kMaxAlphabet + 1;   // profile rows: padding (image code 0) and residues (codes 1..24)
 constexpr int kPadCode = 0;        // image byte of padding columns (residue codes are stored + 1)
-constexpr int16_t kPadScore = -1024;   // substitution score of padding (any value <= 0 is invisible)
+constexpr int16_t kPadScore = -32768;  // substitution score of padding: any biased 16-bit H plus it stays
+                                       // at or below -1025, a finite negative half float
 constexpr int kGroupPairs = 64;    // subject pairs per group (one per lane of a wave)
 constexpr int kGroupSubjects = 2 * kGroupPairs;
 constexpr int kChunkCols = 4;      // columns per interleaved chunk (one dword per subject)
@@ -72,7 +73,8 @@ struct SweepArgs {
     int32_t* rerun_count;
     int32_t rerun_cap;
     int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
-    int32_t sat;                  // 16-bit scores >= sat are recomputed with 32-bit cells
+    int32_t sat;                  // 16-bit scores >= sat (biased) are recomputed with 32-bit cells
+    int32_t bias;                 // 16-bit cells carry H, E, F + bias (>= minus the lowest substitution score)
     const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
     const int32_t* slen;          // end-to-end modes: subject length per sorted slot (0 for padding slots)
 };

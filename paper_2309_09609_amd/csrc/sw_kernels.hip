@@ -25,13 +25,19 @@
 // column and F to the next row, so H - Go is computed once and shared:
 //   hd = Hdiag + SM;  H = max(hd, E, F);  S = max(S, H)
 //   hgo = max(H - Go, 0);  E' = max(E - Ge, hgo);  F' = max(F - Ge, hgo)
-// Flooring E and F at zero leaves every H unchanged (H >= 0 already).  The
-// 16-bit form uses saturating v_pk_add_i16 / v_pk_sub_u16 / v_pk_max_i16, and
-// folds two rows' H into S with one v_pk_maximum3_f16: H >= 0, and non-negative
-// 16-bit integers below 0x7C00 order like the half floats with the same bits,
-// while 0x7C00 and above are infinity or NaN, which the maximum propagates.
-// So S < kSat16 (0x7C00) is exact (no H reached it, so no sum was clamped), and
-// S >= kSat16 sends the pair to the 32-bit sweep.
+// Flooring E and F at zero leaves every H unchanged (H >= 0 already).
+// The 16-bit form keeps H, E and F plus a bias c >= -min SM (c = 4 for
+// BLOSUM62), so that every value it compares, hd included, is a non-negative
+// 16-bit integer; those below 0x7C00 order like the half floats with the same
+// bits, while 0x7C00 and above are infinity or NaN, which v_pk_maximum3_f16
+// propagates.  One maximum3 then gives H = max(hd, E, F), another E' with the
+// floor c (E >= c keeps every H >= c, the local floor; F needs none), and one
+// more folds two rows' H into S.  Subtractions saturate at zero
+// (v_pk_sub_u16), so a value that drops below c only stands for one below
+// zero, which the floors make irrelevant.  Padding scores -32768, which keeps
+// its sums finite and negative.  So S < kSat16 (0x7C00) is exact (no H reached
+// it, so no sum was clamped) and the score is S - c; S >= kSat16 sends the
+// pair to the 32-bit sweep.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -152,74 +158,78 @@ struct CellI32 {
 // whose order never lets an instruction read the result of the packed (VOP3P)
 // instruction just before it: gfx950 needs a wait state there, and the
 // compiler, whose scheduler does not model that hazard, otherwise pays it with
-// an s_nop on nearly every row.  Per row r the block interleaves the chain
-// H -> H-Go -> F' -> next H with independent work of the neighbouring rows:
-//   hd   = H[r] + SM(r+1)        next row's diagonal term, read before H[r] changes
-//   H[r] = max(t, F)             t = max(hd_r, E[r]) from the row before
+// an s_nop on nearly every row.  Values carry the bias c (see the header
+// comment), so the three-way maximum of Eq. 1 is one v_pk_maximum3_f16.  Per
+// row r the block interleaves the chain H -> H-Go -> F' -> next H with
+// independent work of the neighbouring rows:
+//   hd'  = H[r] + SM(r+1)        next row's diagonal term, read before H[r] changes
+//   H[r] = maximum3(hd, E[r], F)
 //   es   = E[r] -sat Ge
 //   hgo  = H[r] -sat Go
 //   fs   = F -sat Ge
 //   (permute of row r+2's substitution pair, subject-pair form only)
-//   t    = max(hd, E[r+1])
-//   E[r] = max(es, hgo)
+//   E[r] = maximum3(es, hgo, c)  the floor c keeps every H at c or above
 //   F    = max(fs, hgo)
 //   S    = maximum3(S, H[r-1], H[r])   after every odd row
-// This is the arithmetic of the generic row loop in sweep_pass, reordered.
-#define SWA(r) "v_pk_add_i16 %[hd], %[h" #r "], %[sm] clamp\n"
-#define SWAW(r, n) "v_pk_add_i16 %[hd], %[h" #r "], %[w" #n "] clamp\n"
-#define SWD(r) "v_pk_max_i16 %[h" #r "], %[t], %[f]\n"
+// hd and hd' alternate between two registers from row to row.  This is the
+// arithmetic of the generic row loop in sweep_pass, reordered and biased.
+#define SWA(r, n) "v_pk_add_i16 %[d" #n "], %[h" #r "], %[sm] clamp\n"
+#define SWAW(r, n, w) "v_pk_add_i16 %[d" #n "], %[h" #r "], %[w" #w "] clamp\n"
+#define SWD(r, c) "v_pk_maximum3_f16 %[h" #r "], %[d" #c "], %[e" #r "], %[f]\n"
 #define SWF(r) "v_pk_sub_u16 %[es], %[e" #r "], %[ge] clamp\n"
 #define SWE(r) "v_pk_sub_u16 %[hgo], %[h" #r "], %[go] clamp\n"
 #define SWH "v_pk_sub_u16 %[fs], %[f], %[ge] clamp\n"
 #define SWP(k, sel) "v_perm_b32 %[sm], %[b" #k "], %[a" #k "], %[" #sel "]\n"
-#define SWB(n) "v_pk_max_i16 %[t], %[hd], %[e" #n "]\n"
-#define SWG(r) "v_pk_max_i16 %[e" #r "], %[es], %[hgo]\n"
+#define SWG(r) "v_pk_maximum3_f16 %[e" #r "], %[es], %[hgo], %[c]\n"
 #define SWI "v_pk_max_i16 %[f], %[fs], %[hgo]\n"
 #define SWM(a, b) "v_pk_maximum3_f16 %[s], %[s], %[h" #a "], %[h" #b "]\n"
-// subject-pair form: row r's pair is perm(b[r/2], a[r/2]) with selector s0 (even r) or s1 (odd r)
-#define SW_PRO "v_perm_b32 %[sm], %[b0], %[a0], %[s0]\n" "v_pk_add_i16 %[hd], %[dt], %[sm] clamp\n" SWP(0, s1) SWB(0)
-#define SW_BLK(r, n, k2, sel2) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWP(k2, sel2) SWB(n) SWG(r) SWI
-#define SW_BLKS(r, n, k2, sel2, rp) SW_BLK(r, n, k2, sel2) SWM(rp, r)
-#define SW_BLKN(r, n) SWA(r) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI
+// subject-pair form: row r's pair is perm(b[r/2], a[r/2]) with selector s0 (even r) or s1 (odd r);
+// the prologue forms row 0's hd (register d0) and row 1's pair
+#define SW_PRO "v_perm_b32 %[sm], %[b0], %[a0], %[s0]\n" "v_pk_add_i16 %[d0], %[dt], %[sm] clamp\n" SWP(0, s1)
+// row r reads hd from d(r%2) and writes row r+1's into d((r+1)%2)
+#define SW_BLK(r, c, n, k2, sel2) SWA(r, n) SWD(r, c) SWF(r) SWE(r) SWH SWP(k2, sel2) SWG(r) SWI
+#define SW_BLKS(r, c, n, k2, sel2, rp) SW_BLK(r, c, n, k2, sel2) SWM(rp, r)
+#define SW_BLKN(r, c, n) SWA(r, n) SWD(r, c) SWF(r) SWE(r) SWH SWG(r) SWI
 // the last row starts with E[r] - Ge, as the block before it ends with the write of F
-#define SW_LAST(r, rp) SWF(r) SWD(r) SWH SWE(r) SWM(rp, r) SWG(r) SWI
-// pre-packed form: row r's pair is w[r]; the prologue takes row 0's F - Ge
-#define SW_PROW "v_pk_add_i16 %[hd], %[dt], %[w0] clamp\n" SWH SWB(0)
-#define SW_BLK0W SWAW(0, 1) SWD(0) SWF(0) SWE(0) SWB(1) SWG(0) SWI
-#define SW_BLKW(r, n) SWAW(r, n) SWD(r) SWF(r) SWE(r) SWH SWB(n) SWG(r) SWI
-#define SW_BLKWS(r, n, rp) SW_BLKW(r, n) SWM(rp, r)
+#define SW_LAST(r, c, rp) SWF(r) SWD(r, c) SWH SWE(r) SWM(rp, r) SWG(r) SWI
+// pre-packed form: row r's pair is w[r]
+#define SW_PROW "v_pk_add_i16 %[d0], %[dt], %[w0] clamp\n"
+#define SW_BLKW(r, c, n, w) SWAW(r, n, w) SWD(r, c) SWF(r) SWE(r) SWH SWG(r) SWI
+#define SW_BLKWS(r, c, n, w, rp) SW_BLKW(r, c, n, w) SWM(rp, r)
 
 #define SW_HE(i) [h##i] "+v"(H[i]), [e##i] "+v"(E[i])
 #define SW_AB(i) [a##i] "v"(pa[i]), [b##i] "v"(pb[i])
 #define SW_W(i) [w##i] "v"(w[i])
-#define SW_OUTS [s] "+v"(S), [f] "+v"(F), [hd] "=&v"(hd), [t] "=&v"(t), [hgo] "=&v"(hgo), [es] "=&v"(es), \
+#define SW_OUTS [s] "+v"(S), [f] "+v"(F), [d0] "=&v"(d0), [d1] "=&v"(d1), [hgo] "=&v"(hgo), [es] "=&v"(es), \
                 [fs] "=&v"(fs)
-#define SW_INS [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge)
+#define SW_INS [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge), [c] "s"(c)
 
 // Subject-pair form: pa/pb hold rows 2k, 2k+1 of subject a and of subject b.
 template <int R>
 __device__ __forceinline__ void rows16_pair(s2* H, s2* E, s2& S, s2& F, s2 diag, const uint32_t* pa,
-                                            const uint32_t* pb, u2 go, u2 ge) {
-    s2 hd, t, hgo, es, fs, sm;
+                                            const uint32_t* pb, u2 go, u2 ge, u2 c) {
+    s2 d0, d1, hgo, es, fs, sm;
     const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
     if constexpr (R == 16) {
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLK(2, 3, 2, s0) SW_BLKS(3, 4, 2, s1, 2)
-                SW_BLK(4, 5, 3, s0) SW_BLKS(5, 6, 3, s1, 4) SW_BLK(6, 7, 4, s0) SW_BLKS(7, 8, 4, s1, 6)
-                    SW_BLK(8, 9, 5, s0) SW_BLKS(9, 10, 5, s1, 8) SW_BLK(10, 11, 6, s0) SW_BLKS(11, 12, 6, s1, 10)
-                        SW_BLK(12, 13, 7, s0) SW_BLKS(13, 14, 7, s1, 12) SW_BLKN(14, 15) SW_LAST(15, 14)
+        asm(SW_PRO SW_BLK(0, 0, 1, 1, s0) SW_BLKS(1, 1, 0, 1, s1, 0) SW_BLK(2, 0, 1, 2, s0)
+                SW_BLKS(3, 1, 0, 2, s1, 2) SW_BLK(4, 0, 1, 3, s0) SW_BLKS(5, 1, 0, 3, s1, 4) SW_BLK(6, 0, 1, 4, s0)
+                    SW_BLKS(7, 1, 0, 4, s1, 6) SW_BLK(8, 0, 1, 5, s0) SW_BLKS(9, 1, 0, 5, s1, 8)
+                        SW_BLK(10, 0, 1, 6, s0) SW_BLKS(11, 1, 0, 6, s1, 10) SW_BLK(12, 0, 1, 7, s0)
+                            SW_BLKS(13, 1, 0, 7, s1, 12) SW_BLKN(14, 0, 1) SW_LAST(15, 1, 14)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
               SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS, [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5), SW_AB(6), SW_AB(7),
               [s0] "s"(s0), [s1] "s"(s1));
     } else if constexpr (R == 8) {
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLK(2, 3, 2, s0) SW_BLKS(3, 4, 2, s1, 2)
-                SW_BLK(4, 5, 3, s0) SW_BLKS(5, 6, 3, s1, 4) SW_BLKN(6, 7) SW_LAST(7, 6)
+        asm(SW_PRO SW_BLK(0, 0, 1, 1, s0) SW_BLKS(1, 1, 0, 1, s1, 0) SW_BLK(2, 0, 1, 2, s0)
+                SW_BLKS(3, 1, 0, 2, s1, 2) SW_BLK(4, 0, 1, 3, s0) SW_BLKS(5, 1, 0, 3, s1, 4) SW_BLKN(6, 0, 1)
+                    SW_LAST(7, 1, 6)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS,
               [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), [s0] "s"(s0), [s1] "s"(s1));
     } else {
         static_assert(R == 4, "rows per lane must be 4, 8 or 16");
-        asm(SW_PRO SW_BLK(0, 1, 1, s0) SW_BLKS(1, 2, 1, s1, 0) SW_BLKN(2, 3) SW_LAST(3, 2)
+        asm(SW_PRO SW_BLK(0, 0, 1, 1, s0) SW_BLKS(1, 1, 0, 1, s1, 0) SW_BLKN(2, 0, 1) SW_LAST(3, 1, 2)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS, [sm] "=&v"(sm)
             : SW_INS, SW_AB(0), SW_AB(1), [s0] "s"(s0), [s1] "s"(s1));
     }
@@ -228,24 +238,25 @@ __device__ __forceinline__ void rows16_pair(s2* H, s2* E, s2& S, s2& F, s2 diag,
 // Pre-packed form: w[r] is row r's substitution pair.
 template <int R>
 __device__ __forceinline__ void rows16_packed(s2* H, s2* E, s2& S, s2& F, s2 diag, const uint32_t* w, u2 go,
-                                              u2 ge) {
-    s2 hd, t, hgo, es, fs;
+                                              u2 ge, u2 c) {
+    s2 d0, d1, hgo, es, fs;
     if constexpr (R == 16) {
-        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_BLKWS(3, 4, 2) SW_BLKW(4, 5) SW_BLKWS(5, 6, 4)
-                SW_BLKW(6, 7) SW_BLKWS(7, 8, 6) SW_BLKW(8, 9) SW_BLKWS(9, 10, 8) SW_BLKW(10, 11)
-                    SW_BLKWS(11, 12, 10) SW_BLKW(12, 13) SW_BLKWS(13, 14, 12) SW_BLKW(14, 15) SW_LAST(15, 14)
+        asm(SW_PROW SW_BLKW(0, 0, 1, 1) SW_BLKWS(1, 1, 0, 2, 0) SW_BLKW(2, 0, 1, 3) SW_BLKWS(3, 1, 0, 4, 2)
+                SW_BLKW(4, 0, 1, 5) SW_BLKWS(5, 1, 0, 6, 4) SW_BLKW(6, 0, 1, 7) SW_BLKWS(7, 1, 0, 8, 6)
+                    SW_BLKW(8, 0, 1, 9) SW_BLKWS(9, 1, 0, 10, 8) SW_BLKW(10, 0, 1, 11) SW_BLKWS(11, 1, 0, 12, 10)
+                        SW_BLKW(12, 0, 1, 13) SW_BLKWS(13, 1, 0, 14, 12) SW_BLKW(14, 0, 1, 15) SW_LAST(15, 1, 14)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
               SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7), SW_W(8), SW_W(9),
               SW_W(10), SW_W(11), SW_W(12), SW_W(13), SW_W(14), SW_W(15));
     } else if constexpr (R == 8) {
-        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_BLKWS(3, 4, 2) SW_BLKW(4, 5) SW_BLKWS(5, 6, 4)
-                SW_BLKW(6, 7) SW_LAST(7, 6)
+        asm(SW_PROW SW_BLKW(0, 0, 1, 1) SW_BLKWS(1, 1, 0, 2, 0) SW_BLKW(2, 0, 1, 3) SW_BLKWS(3, 1, 0, 4, 2)
+                SW_BLKW(4, 0, 1, 5) SW_BLKWS(5, 1, 0, 6, 4) SW_BLKW(6, 0, 1, 7) SW_LAST(7, 1, 6)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3), SW_W(4), SW_W(5), SW_W(6), SW_W(7));
     } else {
         static_assert(R == 4, "rows per lane must be 4, 8 or 16");
-        asm(SW_PROW SW_BLK0W SW_BLKWS(1, 2, 0) SW_BLKW(2, 3) SW_LAST(3, 2)
+        asm(SW_PROW SW_BLKW(0, 0, 1, 1) SW_BLKWS(1, 1, 0, 2, 0) SW_BLKW(2, 0, 1, 3) SW_LAST(3, 1, 2)
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3));
     }
@@ -335,7 +346,7 @@ struct EndCtx {
 
 template <class C, int R, bool COOP, bool PACKED, int MODE = 0>
 __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, int b, const int16_t* lrow,
-                                           typename C::G go, typename C::G ge, typename C::T& S,
+                                           typename C::G go, typename C::G ge, typename C::T& S, typename C::T bias,
                                            const EndCtx& ec = EndCtx{}) {
     static_assert(MODE == 0 || std::is_same<C, CellI32>::value, "end-to-end modes use 32-bit cells");
     using T = typename C::T;
@@ -345,10 +356,10 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     const int nloop = (nsteps + 3) >> 2;
     const bool first_lane = (b == 0);
 
-    T H[R], E[R];      // H and E of this lane's rows at the last column done
+    T H[R], E[R];      // H and E of this lane's rows at the last column done (biased, 16-bit cells)
 #pragma unroll
-    for (int r = 0; r < R; ++r) { H[r] = C::zero(); E[r] = C::zero(); }
-    T diag = C::zero();          // H of the row above this lane's block, previous column
+    for (int r = 0; r < R; ++r) { H[r] = bias; E[r] = bias; }
+    T diag = bias;               // H of the row above this lane's block, previous column
     T up_h = C::zero(), up_f = C::zero();   // bottom row of lane b-1, one column back
     if constexpr (MODE != 0) {
 #pragma unroll
@@ -394,6 +405,8 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                 htop = C::sel(first_lane, htop, up_h);
                 ftop = C::sel(first_lane, ftop, up_f);
             }
+            // the zero border of a first pass reads as zeros: raise it to the bias (F may stay below it)
+            if constexpr (std::is_same<C, CellI16>::value) htop = C::mx(htop, bias);
             const int col = 4 * c + u - b;                            // 0-based column of this step
             if constexpr (MODE != 0) {
                 if (first_lane && ec.top) {                           // row 0 of the matrix
@@ -427,8 +440,8 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                     }
                 }
             } else if constexpr (std::is_same<C, CellI16>::value) {
-                if constexpr (PACKED) rows16_packed<R>(H, E, S, F, diag, cur, go, ge);
-                else rows16_pair<R>(H, E, S, F, diag, cur, cur + R / 2, go, ge);
+                if constexpr (PACKED) rows16_packed<R>(H, E, S, F, diag, cur, go, ge, bits<u2>(bias));
+                else rows16_pair<R>(H, E, S, F, diag, cur, cur + R / 2, go, ge, bits<u2>(bias));
             } else {
                 T dg = diag;
 #pragma unroll
@@ -559,7 +572,13 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
     const int16_t* lrow = PACKED ? reinterpret_cast<const int16_t*>(region32 + b * kNRes * R)
                                  : reinterpret_cast<const int16_t*>(region32) + b * kNRes * R;
     const typename C::G go = C::gapv(a.go), ge = C::gapv(a.ge);
-    T S = C::zero();
+    T bias = C::zero();
+    int ub = 0;                                 // subtracted from every score on the way out
+    if constexpr (std::is_same<C, CellI16>::value) {
+        bias = bits<T>((uint32_t)(uint16_t)a.bias * 0x10001u);
+        ub = a.bias;
+    }
+    T S = bias;
     EndCtx ec{};
     if constexpr (MODE != 0) {
         ec.m = m;
@@ -607,9 +626,9 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
             ec.row0 = p * rows_pp + b * R;
             ec.top = p == 0;
             if (lgB == 0)
-                sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, ec);
+                sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
             else
-                sweep_pass<C, R, true, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, ec);
+                sweep_pass<C, R, true, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
@@ -621,10 +640,10 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         const int o = a.perm[g * kGroupSubjects + su];
         if (o >= 0) {
             int32_t* outa = Qa.out ? Qa.out : a.scores + Qa.out_off;
-            outa[o] = C::lo(S);
+            outa[o] = C::lo(S) - ub;
             if (qb >= 0) {
                 int32_t* outb = Qb.out ? Qb.out : a.scores + Qb.out_off;
-                outb[o] = C::hi(S);
+                outb[o] = C::hi(S) - ub;
             }
         }
         if (a.rerun != nullptr) {
@@ -635,8 +654,8 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         const int slot0 = g * kGroupSubjects + 2 * su;
         const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
         int32_t* out = Qa.out ? Qa.out : a.scores + Qa.out_off;
-        if (o0 >= 0) out[o0] = C::lo(S);
-        if (o1 >= 0) out[o1] = C::hi(S);
+        if (o0 >= 0) out[o0] = C::lo(S) - ub;
+        if (o1 >= 0) out[o1] = C::hi(S) - ub;
         if (MODE == 0 && a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
     }
 }

@@ -167,12 +167,13 @@ def test_scores_above_int16_are_exact(gpu, blosum, lanes):
 
 
 def _threshold_db():
-    """Self scores just below, at and above 0x7C00 = 31744, the first 16-bit
-    pattern that the packed maximum does not order as a number (W scores 11,
-    H 8 and C 9 on the BLOSUM62 diagonal)."""
-    W, H, C = 17, 8, 4
+    """Self scores just below, at and above 31740: 16-bit cells carry the score
+    plus the bias 4 (minus BLOSUM62's lowest score), and 0x7C00 = 31744 is the
+    first 16-bit pattern that the packed maximum does not order as a number
+    (W scores 11, A 4 and R 5 on the BLOSUM62 diagonal)."""
+    W, A, R = 17, 0, 1
     rng = np.random.default_rng(23)
-    core = [np.concatenate([np.full(2885, W), [H]]), np.concatenate([np.full(2885, W), [C]]), np.full(2890, W)]
+    core = [np.concatenate([np.full(2885, W), [A]]), np.concatenate([np.full(2885, W), [R]]), np.full(2890, W)]
     subs = [np.asarray(x, np.int8) for x in core] + [rng.integers(0, 20, int(rng.integers(1, 300))).astype(np.int8)
                                                        for _ in range(60)]
     offs = np.zeros(len(subs) + 1, np.int64)
@@ -183,7 +184,7 @@ def _threshold_db():
 @pytest.mark.parametrize("lanes", [0, 1, 64])
 def test_scores_at_the_16bit_threshold(gpu, blosum, lanes):
     db, core = _threshold_db()
-    for i, (q, self_score, reruns) in enumerate(zip(core, (31743, 31744, 31790), (False, True, True))):
+    for i, (q, self_score, reruns) in enumerate(zip(core, (31739, 31740, 31790), (False, True, True))):
         got, st = gpu_scores(gpu, db, q, blosum, 10, 2, force_lanes=lanes)
         want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2)
         assert want[i] == self_score
@@ -314,6 +315,15 @@ def test_batch_graph_replay(gpu, blosum):
             ws, wi = oracle.topk(want, 10)
             assert (ts[i].cpu().numpy() == ws).all() and (ti[i].cpu().numpy() == wi).all()
         assert int(eager) == 499500
+    # the same shapes with matrices of other lowest scores (the 16-bit bias): no stale replay
+    for rep, sm in enumerate([identity_matrix(1, -128), identity_matrix(2, 0), blosum]):
+        queries = [synth.small_query(seed=7000 + 10 * rep + i, m=L) for i, L in enumerate(lens)]
+        qo = np.concatenate([[0], np.cumsum(lens)])
+        gpu.sw_search_batch(np.concatenate(queries), qo, D.handle, sm, 3, 1, 10, scores, ts, ti)
+        torch.cuda.synchronize()
+        S = scores.cpu().numpy()
+        for i, q in enumerate(queries):
+            assert_equal_scores(S[i], oracle.scores(q, db.residues, db.offsets, sm, 3, 1), f"matrix {rep} query {i}")
     D.close()
 
 
