@@ -22,9 +22,11 @@
 // * 4 + r.
 //
 // Walk.  One wave per pair copies the 256-byte step records of up to 128
-// steps of the current band into LDS, and one lane follows the path through
-// them until it leaves the copied steps; every move keeps or lowers the step
-// index, so each copy serves dozens of moves.
+// steps of the current band into LDS and follows the path through them until
+// it leaves the copied steps; every move keeps or lowers the step index, so
+// each copy serves dozens of moves.  The wave takes a run of equal moves (a
+// diagonal stretch, a gap) at once: each lane checks one cell of the run and
+// a ballot finds where it ends.
 //
 // Direction byte of cell (i, j):
 //   bits 0-1  where H comes from: 0 H = 0 (an alignment starts after this
@@ -240,9 +242,9 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     }
 }
 
-// One wave per pair: walk the direction bytes back from the end cell, one
-// lane following the path through LDS copies of up to kTraceSteps step
-// records of the band it is in; the byte of (row rb of the band, 0-based
+// One wave per pair: walk the direction bytes back from the end cell, through
+// LDS copies of up to kTraceSteps step records of the band it is in, a run of
+// equal moves at a time; the byte of (row rb of the band, 0-based
 // column c) sits at ((c + rb / 4 - t0) * 256 + rb) in a copy that starts at
 // step t0.  Operations, last to first, collect in LDS and the wave writes
 // them out after each copy; begin positions and the count go to
@@ -284,40 +286,55 @@ __global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, cons
         const int words = (t - t0 + 1) * 16;
         for (int x = lane; x < words; x += 64) reinterpret_cast<uint4*>(tile)[x] = src[x];
         __syncthreads();
-        if (lane == 0) {
+        {
+            // the wave follows runs of equal moves: lane k looks at the k-th cell of the run (down the
+            // diagonal in H, along the row in E, up the column in F) and the first lane whose cell ends
+            // the run, or lies outside the copy, the band, the matrix or the room left, decides
             int rb = row - p * kAlignPass;      // row within the band
             int c = j - 1;                      // 0-based column
             int cnt = 0;
             const int64_t room = ops_stride - len;
             const int cap = room < kTraceOps ? (int)room : kTraceOps;
-            // leaves at the band's top, the matrix border, a full buffer or the copy's first step;
-            // the outer loop sorts these out
-            while (rb >= 0 && c >= 0 && cnt < cap) {
-                const int tt = c + (rb >> 2);
-                if (tt < t0) break;
-                const uint32_t v = tile[(tt - t0) * 256 + rb];
+            for (;;) {
+                const int rk = state == 1 ? rb : rb - lane;
+                const int ck = state == 2 ? c : c - lane;
+                const int tk = ck + (rk >> 2);
+                const bool ok = rk >= 0 && ck >= 0 && tk >= t0 && cnt + lane < cap;
+                const uint32_t v = ok ? tile[(tk - t0) * 256 + rk] : 0u;
+                const bool stop = !ok || (state == 0 ? (v & 3u) != 1u : (v & (state == 1 ? 4u : 8u)) != 0u);
+                const uint64_t mask = __ballot(stop);
+                const int K = mask ? (int)__builtin_ctzll(mask) : 64;
+                const bool okK = K < 64 && __shfl((int)ok, K, 64) != 0;
+                const uint32_t vK = (uint32_t)__shfl((int)v, K < 64 ? K : 0, 64);
                 if (state == 0) {
-                    const uint32_t sr = v & 3u;
+                    if (lane < K) obuf[cnt + lane] = 'M';
+                    cnt += K;
+                    rb -= K;
+                    c -= K;
+                    if (K == 64) continue;
+                    if (!okK) break;                             // the outer loop decides
+                    const uint32_t sr = vK & 3u;
                     if (sr == 0) { done = true; break; }
-                    if (sr == 1) { obuf[cnt++] = 'M'; --rb; --c; }
-                    else state = (int)sr - 1;
-                } else if (state == 1) {
-                    obuf[cnt++] = 'D';
-                    if (v & 4u) state = 0;
-                    --c;
+                    state = (int)sr - 1;
                 } else {
-                    obuf[cnt++] = 'I';
-                    if (v & 8u) state = 0;
-                    --rb;
+                    const char op = state == 1 ? 'D' : 'I';
+                    const int moves = okK ? K + 1 : K;           // the gap's opening cell is its last move
+                    if (lane < moves) obuf[cnt + lane] = op;
+                    cnt += moves;
+                    if (state == 1) c -= moves; else rb -= moves;
+                    if (okK) state = 0;
+                    else if (K < 64) break;                      // the outer loop decides
                 }
             }
-            walk[0] = rb + p * kAlignPass + 1;
-            walk[1] = c + 1;
-            walk[2] = len + cnt;
-            walk[3] = state;
-            walk[4] = done;
-            walk[5] = status;
-            walk[6] = cnt;
+            if (lane == 0) {
+                walk[0] = rb + p * kAlignPass + 1;
+                walk[1] = c + 1;
+                walk[2] = len + cnt;
+                walk[3] = state;
+                walk[4] = done;
+                walk[5] = status;
+                walk[6] = cnt;
+            }
         }
         __syncthreads();
         const int cnt = (int)walk[6];
@@ -338,14 +355,17 @@ __global__ __launch_bounds__(64) void k_align_trace(const AlignPair* pairs, cons
     }
 }
 
+constexpr int kFillStaticLds = 1024;             // k_align_fill's own LDS (matrix copy, per-wave end cells), rounded up
+
 // W = waves per workgroup: the most bands of a pair in the launch, at most 16
-// and at most align_waves_fit(A).
+// and at most align_waves(., A, lds_max) allows; lds_max = LDS bytes a
+// workgroup may use on the device.
 hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
                         uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
-                        hipStream_t st) {
+                        int lds_max, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    if (W < 1 || W > kAlignWaves || (size_t)W * A * kAlignPass > 65536 - 1024) return hipErrorInvalidValue;
     const size_t lds = (size_t)W * A * kAlignPass;
+    if (W < 1 || W > kAlignWaves || lds + kFillStaticLds > (size_t)lds_max) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, subst, A, go, ge, dirs, bnd, best);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -354,10 +374,10 @@ hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t*
 }
 
 // Waves per pair: one per band of 256 query rows, up to 16, with the bands'
-// profiles (A x 256 bytes each) within 64 KiB of LDS.
-int align_waves(int m, int A) {
+// profiles (A x 256 bytes each) and the kernel's own LDS within lds_max.
+int align_waves(int m, int A, int lds_max) {
     const int passes = (m + kAlignPass - 1) / kAlignPass;
-    const int fit = (65536 - 1024) / (A * kAlignPass);
+    const int fit = (lds_max - kFillStaticLds) / (A * kAlignPass);
     return std::max(1, std::min(std::min(passes, kAlignWaves), fit));
 }
 

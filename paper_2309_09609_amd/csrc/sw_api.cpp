@@ -37,8 +37,8 @@ hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t
 hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu);
 hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
                         uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
-                        hipStream_t st);
-int align_waves(int m, int A);
+                        int lds_max, hipStream_t st);
+int align_waves(int m, int A, int lds_max);
 int64_t align_dir_bytes(int m, int64_t n);
 int64_t align_bnd_words(int64_t n);
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
@@ -1188,6 +1188,8 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    int lds_max = 0;                                // LDS a workgroup may use (64 KiB on older parts, 160 KiB on gfx950)
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, db->device));
     size_t j0 = 0;
     while (j0 < jobs.size()) {
         // a round: pairs whose direction bytes fit the budget (at least one pair)
@@ -1201,7 +1203,7 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
             dir_total += round_up(J.cost, 256);
             bnd_total += align_bnd_words(J.n);
             stride = std::max<int64_t>(stride, (int64_t)J.m + J.n + 1);
-            W = std::max(W, align_waves(J.m, db->alphabet));
+            W = std::max(W, align_waves(J.m, db->alphabet, lds_max));
             qs_used.push_back(J.q);
             ++j1;
         }
@@ -1251,7 +1253,7 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
         HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, W, reinterpret_cast<int8_t*>(mb + o_sm),
                              db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(), db->align_bnd.as<int32_t>(),
                              reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
-                             reinterpret_cast<int64_t*>(mb + o_info), st));
+                             reinterpret_cast<int64_t*>(mb + o_info), lds_max, st));
         std::vector<int32_t> best(3 * (size_t)np);
         std::vector<int64_t> info(4 * (size_t)np);
         std::vector<char> ops((size_t)np * stride);

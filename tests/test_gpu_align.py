@@ -176,11 +176,11 @@ def test_many_bands_in_flight(gpu, blosum, m, lens):
 
 
 def test_many_bands_with_the_extended_alphabet(gpu):
-    """24 letters leave room for fewer waves per pair: 12 bands wrap around."""
+    """24 letters: larger per-wave profiles; 18 bands wrap around the waves."""
     from inputs import blosum62_24
     sm = blosum62_24()
     rng = np.random.default_rng(2900)
-    q = rng.integers(0, 24, 2900).astype(np.int8)
+    q = rng.integers(0, 24, 4400).astype(np.int8)
     subs = [rng.integers(0, 24, int(L)).astype(np.int8) for L in (2, 900, 2600)]
     for s in subs:
         _plant(rng, q, s, 100, s.size)
@@ -189,7 +189,7 @@ def test_many_bands_with_the_extended_alphabet(gpu):
     db = synth.Database(np.concatenate(subs), offs)
     D = gpu.Database(db.residues, db.offsets, alphabet=24)
     idx = list(range(db.n))
-    _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24, 12 bands")
+    _compare(D.align(q, idx, sm, 10, 2), q, db, idx, sm, 10, 2, "alphabet 24, 18 bands")
     D.close()
 
 
