@@ -94,8 +94,17 @@ def cpu_baseline(queries, db, sm, seconds: float):
         cells += int(q.size) * int(lengths[idx].sum())
         done += idx.size
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over a quarter of the time
+    done1, cells1, t2 = 0, 0, time.perf_counter()
+    while done1 < db.n and time.perf_counter() - t2 < seconds / 4:
+        idx = np.arange(done1, min(db.n, done1 + block // 8), dtype=np.int64)
+        oracle.scores(q, db.residues, db.offsets, sm, 10, 2, idx=idx, threads=1)
+        cells1 += int(q.size) * int(lengths[idx].sum())
+        done1 += idx.size
+    dt1 = time.perf_counter() - t2
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": f"query 0 (m={q.size}) vs the first {done} subjects ({cells:.3e} cells) in {dt:.1f} s"}
+            "sample": f"query 0 (m={q.size}) vs the first {done} subjects ({cells:.3e} cells) in {dt:.1f} s",
+            "single_thread_gcups": round(cells1 / dt1 / 1e9, 4)}
 
 
 def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
@@ -328,11 +337,14 @@ def main():
     D.kernel_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [t0]
     for i in range(args.steps):
         step()
         torch.cuda.synchronize()
+        marks.append(time.perf_counter())
         print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
+    step_ms = np.diff(marks) * 1e3
     kt = D.kernel_times()           # ms per 16-bit sweep launch in the timed region
     st = D.stats()
     if args.form == "plain" and kt.size == args.steps * len(queries):
@@ -371,6 +383,8 @@ def main():
                   "pct_packed16_cell_peak": round(100 * gcups / perfmodel.mi355x_peak_gcups(cells_per_lane_op=2), 2),
                   "kernel_gcups": round(cells_step * args.steps / kernel_s / 1e9, 2) if kernel_s > 0 else None,
                   "rerun_pairs_last_call": st["rerun_pairs"], "waves": st["waves"],
+                  "step_ms": {"mean": round(float(step_ms.mean()), 3), "min": round(float(step_ms.min()), 3),
+                              "stdev": round(float(step_ms.std(ddof=1)), 3) if step_ms.size > 1 else 0.0},
                   "tuned_knobs": tuned["knobs"] if tuned else None},
     }
     if args.form == "plain" and not args.no_batched_compare and args.mode == "local":
