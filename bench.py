@@ -170,6 +170,15 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     if dyn_reps:
         dyn_rep = dyn_reps.get("dynamic-q2", dyn_reps.get("dynamic"))
         dyn = dyn_rep.summary()
+    if "srpt" in pols:
+        # one request on the GPU at a time, chosen at every chunk boundary by least remaining work:
+        # a short query that arrives overtakes a long one within 1/chunks of a search
+        srv1 = Server(GpuEngine(D, sm, 10, 2, k=10), nchunks=args.chunks, mem_budget=2 << 30, max_active=1,
+                      policy="srpt")
+        srv1.run(trace[:warm], arrivals[:warm] - arrivals[0])
+        r = srv1.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells, progress=progress("srpt"))
+        dyn_reps["srpt"] = r
+        print(f"# srpt: {r.summary()}", file=sys.stderr, flush=True)
     # every policy must return the same top-10 for every request
     others = [rep] + list(dyn_reps.values())
     same = all(np.array_equal(fifo_rep.results[i][0], o.results[i][0]) and
@@ -190,7 +199,7 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
                     "plain_p50_s": round(fifo["p50_s"], 4), "plain_p99_s": round(fifo["p99_s"], 4),
                     "p99_gain": round(fifo["p99_s"] / served["p99_s"], 3) if served["p99_s"] > 0 else None},
         "extra": {"served": served, "plain_fifo": fifo, "dynamic_batching": dyn,
-                  "dynamic_by_lane_pack": {k: v.summary() for k, v in dyn_reps.items()},
+                  "other_policies": {k: v.summary() for k, v in dyn_reps.items()},
                   "same_top10_all_policies": same,
                   "pct_int32_cell_peak": round(100 * served["gcups"] / perfmodel.mi355x_peak_gcups(), 2)},
     }
@@ -256,7 +265,8 @@ def main():
                     help="served form: 2 = requests that share an iteration share lanes two queries at a time")
     ap.add_argument("--policies", default="served,plain,dynamic-q2",
                     help="served form: comma list of served, plain (both required), dynamic (batches of waiting "
-                         "requests, subject pairs per lane), dynamic-q2 (the same with query pairs per lane)")
+                         "requests, subject pairs per lane), dynamic-q2 (the same with query pairs per lane), srpt "
+                         "(one request at a time, least remaining work first at every chunk boundary)")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--mode", default="local", choices=["local", "global", "semiglobal"],
                     help="plain form: alignment mode (global and semi-global run in 32-bit cells)")

@@ -102,3 +102,24 @@ def test_idle_server_waits_for_arrivals():
     eng, srv, rep = run(2, 2, 10 ** 6, arr)
     assert eng.steps == 4 and max(eng.sizes) == 1
     assert rep.latencies.max() < 0.1
+
+
+def test_srpt_one_at_a_time_lets_short_requests_overtake():
+    """max_active=1 with least-remaining-work order: preemptive shortest-first at
+    chunk boundaries; every request still scores every chunk exactly once."""
+    clock = FakeClock()
+    eng = FakeEngine(clock)
+    srv = Server(eng, nchunks=4, mem_budget=10 ** 6, max_active=1, policy="srpt")
+    qs = [np.zeros(1000, np.int8), np.zeros(10, np.int8), np.zeros(400, np.int8)]   # 400 x 4 < 1000 x 2 left
+    arr = np.array([0.0, 0.015, 0.015])      # the long one is one chunk in when the others arrive
+    rep = srv.run(qs, arr, clock=clock, sleep=clock.sleep, cells_per_query=lambda q: q.size)
+    assert max(eng.sizes) == 1 and rep.max_active == 1
+    order = [rid for _, rid, _ in eng.log]
+    assert order[:2] == [0, 0]                # the long request ran alone until the others arrived
+    assert order[2:6] == [1, 1, 1, 1]         # then the shortest runs to completion
+    assert order[6:10] == [2, 2, 2, 2] and order[10:] == [0, 0]
+    seen = {}
+    for _, rid, c in eng.log:
+        seen.setdefault(rid, []).append(c)
+    assert all(sorted(cs) == [0, 1, 2, 3] for cs in seen.values())
+    assert rep.latencies[1] < rep.latencies[2] < rep.latencies[0]
