@@ -401,7 +401,7 @@ def main():
         # the same queries in the batched form: one graph launch for all of them
         from paper_2309_09609_amd import tune as tuner
         print("# batched form on the same queries (autotuned)", file=sys.stderr, flush=True)
-        tb = tuner.tune(D, queries, sm, 10, 2, use_cache=False)
+        tb = tuner.tune(D, queries, sm, 10, 2, use_cache=False, sample=len(queries), repeats=1)   # the whole batch
         qcat = np.concatenate(queries)
         qoff = np.concatenate([[0], np.cumsum(qlens)]).astype(np.int64)
         bs = torch.empty((len(queries), db.n), dtype=torch.int32, device="cuda")
