@@ -288,8 +288,8 @@ def main():
         print(json.dumps({"copy_bytes": n, "copies": 3}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the search would shard the database across GPUs; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a search would shard the database across GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -324,8 +324,7 @@ def main():
             tuned = {"knobs": json.loads(args.knobs)}
         else:
             print("# autotuning on a sample of the batch", file=sys.stderr, flush=True)
-            tuned = tuner.tune(D, queries, sm, 10, 2, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"),
-                               use_cache=False, verbose=True)
+            tuned = tuner.tune(D, queries, sm, 10, 2, use_cache=False, verbose=True)
         print(f"# tuned: {tuned['knobs']}", file=sys.stderr, flush=True)
         top_s = torch.empty((len(queries), 10), dtype=torch.int32, device="cuda")
         top_i = torch.empty((len(queries), 10), dtype=torch.int64, device="cuda")
