@@ -365,10 +365,11 @@ def main():
     kernel_s = float(kt.sum()) / 1e3
     launches = int(kt.size)
     # the local sweep computes in packed 16-bit lanes: two cell operations per VALU lane-op; the
-    # end-to-end modes in 32-bit lanes with 8 operations per cell (no running maximum)
+    # end-to-end modes in 32-bit lanes with 7 operations per cell (H as one three-input maximum,
+    # no running maximum)
     packed = args.mode == "local"
     peak_ops = perfmodel.int_valu_lane_ops_per_s() * (2 if packed else 1)
-    ops_cell = CELL_OPS if packed else 8
+    ops_cell = CELL_OPS if packed else 7
     achieved = ops_cell * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
     roof = {"bound": "alu", "achieved": round(achieved, 3) if achieved else None,
             "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s (int16 lane-ops)" if packed else "TOP/s (int32 lane-ops)",

@@ -341,6 +341,7 @@ struct EndCtx {
     int na, nb;               // lengths of the lane's two subjects
     int go, ge, ext;          // Go, Ge, min(Go, Ge)
     bool top;                 // pass 0: row 0 is the border
+    bool last;                // the last pass: it holds the query's last row
     __device__ int border(int k) const { return k <= 0 ? 0 : -(go + (k - 1) * ext); }
 };
 
@@ -407,7 +408,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
             }
             // the zero border of a first pass reads as zeros: raise it to the bias (F may stay below it)
             if constexpr (std::is_same<C, CellI16>::value) htop = C::mx(htop, bias);
-            const int col = 4 * c + u - b;                            // 0-based column of this step
+            const int col = 4 * c + u - (COOP ? b : 0);               // 0-based column of this step
             if constexpr (MODE != 0) {
                 if (first_lane && ec.top) {                           // row 0 of the matrix
                     const int h0 = MODE == 1 ? ec.border(col + 1) : 0;
@@ -417,7 +418,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
             }
             T F = ftop;
             if constexpr (MODE != 0) {
-                if (col >= 0) {                                       // before its first column a lane keeps the border
+                auto rows = [&]() {
                     T dg = diag;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -428,7 +429,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                         H[r] = h;
                         E[r] = T{max(E[r].x - ec.ge, h.x - ec.go), max(E[r].y - ec.ge, h.y - ec.go)};
                         F = T{max(F.x - ec.ge, h.x - ec.go), max(F.y - ec.ge, h.y - ec.go)};
-                        if (r == rcap) {
+                        if (ec.last && r == rcap) {
                             if (MODE == 1) {
                                 if (col == ec.na - 1) S.x = h.x;
                                 if (col == ec.nb - 1) S.y = h.y;
@@ -438,7 +439,11 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                             }
                         }
                     }
-                }
+                };
+                // a cooperating lane starts b steps late and keeps the border until its first column;
+                // once the wave's last lane has started (a wave-uniform test) no lane needs the guard
+                if (!COOP || 4 * c + u >= B - 1) rows();
+                else if (col >= 0) rows();
             } else if constexpr (std::is_same<C, CellI16>::value) {
                 if constexpr (PACKED) rows16_packed<R>(H, E, S, F, diag, cur, go, ge, bits<u2>(bias));
                 else rows16_pair<R>(H, E, S, F, diag, cur, cur + R / 2, go, ge, bits<u2>(bias));
@@ -625,6 +630,7 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
             io.wr_lane = (b == B - 1 && p + 1 < passes) ? lane_words : kNoAccess;
             ec.row0 = p * rows_pp + b * R;
             ec.top = p == 0;
+            ec.last = p == passes - 1;
             if (lgB == 0)
                 sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
             else
