@@ -362,6 +362,11 @@ def main():
             print(f"# m={m:5d}  sweep {ms:8.2f} ms  {m * total_res / ms / 1e6:7.0f} GCUPS", file=sys.stderr)
     elapsed = t1 - t0
     gcups = cells_step * args.steps / elapsed / 1e9
+    # cells of each timed launch (the plain form times one bulk launch per query, the batched form
+    # one per batch); if the library forgot the oldest launches, the newest ones are those kept
+    per_launch = [int(q.size) * total_res for q in queries] * args.steps if args.form == "plain" \
+        else [cells_step] * args.steps
+    timed_cells = sum(per_launch[-kt.size:]) if kt.size else 0
     kernel_s = float(kt.sum()) / 1e3
     launches = int(kt.size)
     # the local sweep computes in packed 16-bit lanes: two cell operations per VALU lane-op; the
@@ -370,7 +375,7 @@ def main():
     packed = args.mode == "local"
     peak_ops = perfmodel.int_valu_lane_ops_per_s() * (2 if packed else 1)
     ops_cell = CELL_OPS if packed else 7
-    achieved = ops_cell * cells_step * args.steps / kernel_s / 1e12 if kernel_s > 0 else None
+    achieved = ops_cell * timed_cells / kernel_s / 1e12 if kernel_s > 0 and 0 < kt.size <= len(per_launch) else None
     roof = {"bound": "alu", "achieved": round(achieved, 3) if achieved else None,
             "peak": round(peak_ops / 1e12, 3), "unit": "TOP/s (int16 lane-ops)" if packed else "TOP/s (int32 lane-ops)",
             "frac": round(achieved * 1e12 / peak_ops, 4) if achieved else None,
@@ -391,7 +396,7 @@ def main():
         "roofline": roof,
         "extra": {"pct_int32_cell_peak": round(100 * gcups / perfmodel.mi355x_peak_gcups(), 2),
                   "pct_packed16_cell_peak": round(100 * gcups / perfmodel.mi355x_peak_gcups(cells_per_lane_op=2), 2),
-                  "kernel_gcups": round(cells_step * args.steps / kernel_s / 1e9, 2) if kernel_s > 0 else None,
+                  "kernel_gcups": round(timed_cells / kernel_s / 1e9, 2) if kernel_s > 0 else None,
                   "rerun_pairs_last_call": st["rerun_pairs"], "waves": st["waves"],
                   "step_ms": {"mean": round(float(step_ms.mean()), 3), "min": round(float(step_ms.min()), 3),
                               "stdev": round(float(step_ms.std(ddof=1)), 3) if step_ms.size > 1 else 0.0},

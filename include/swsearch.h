@@ -299,7 +299,7 @@ sw_status sw_last_stats(sw_db* db, int64_t out[8]);
  * records a pair of HIP events on the caller's stream around its 16-bit sweep
  * launch (the dominant kernel).  sw_kernel_times synchronises the handle's
  * device, writes up to cap elapsed times in milliseconds (oldest first) to
- * ms_out, sets *count to the number written and forgets them.  At most 256
+ * ms_out, sets *count to the number written and forgets them.  At most 4096
  * launches are remembered; older ones are dropped.
  */
 sw_status sw_profile_kernels(sw_db* db, int32_t enable);

@@ -246,9 +246,9 @@ class Database:
 
     def kernel_times(self):
         """Elapsed ms of the sweep launches recorded since the last call (synchronises)."""
-        buf = np.zeros(256, dtype=np.float32)
+        buf = np.zeros(4096, dtype=np.float32)        # the library remembers at most 4096 launches
         cnt = ctypes.c_int32()
-        _check(load().sw_kernel_times(self.handle, _ptr(buf), 256, ctypes.byref(cnt)))
+        _check(load().sw_kernel_times(self.handle, _ptr(buf), buf.size, ctypes.byref(cnt)))
         return buf[: cnt.value].astype(np.float64)
 
     def matrix(self, subst) -> np.ndarray:

@@ -615,6 +615,23 @@ sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries
     return SW_OK;
 }
 
+// Timing events of the dominant launches (sw_profile_kernels): a ring of
+// kTimerSlots start/stop pairs; the oldest is forgotten when it is full.
+constexpr int kTimerSlots = 4096;
+
+int record_timer_start(sw_db* db, hipStream_t st) {
+    if (db->ev_used.size() >= (size_t)kTimerSlots) db->ev_used.erase(db->ev_used.begin());
+    const int ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % kTimerSlots;
+    while ((int)db->ev_pool.size() <= ev) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess) return -1;
+        if (hipEventCreate(&y) != hipSuccess) { hipEventDestroy(x); return -1; }
+        db->ev_pool.push_back({x, y});
+    }
+    if (hipEventRecord(db->ev_pool[ev].first, st) != hipSuccess) return -1;
+    return ev;
+}
+
 // The launch sequence of a search: profile (zeroes the counters), the side and
 // bulk 16-bit sweeps, the 32-bit recompute, top-k.  Allocates nothing and never
 // waits on the host, so it can be captured into a graph.
@@ -663,18 +680,7 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
         HIP_TRY(launch_sweep(true, plan.R_side, b, grid_side, db->side));
         HIP_TRY(hipEventRecord(db->ev_join, db->side));
     }
-    int ev = -1;
-    if (time_sweep && db->timing) {
-        if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
-        ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
-        while ((int)db->ev_pool.size() <= ev) {
-            hipEvent_t x, y;
-            HIP_TRY(hipEventCreate(&x));
-            HIP_TRY(hipEventCreate(&y));
-            db->ev_pool.push_back({x, y});
-        }
-        HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
-    }
+    const int ev = time_sweep && db->timing ? record_timer_start(db, st) : -1;
     if (plan.n_main > 0) {
         if (plan.qpack)
             HIP_TRY(launch_sweep_q2(plan.R_main, a, grid_main, st));
@@ -719,18 +725,6 @@ sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
     return SW_OK;
 }
 
-int record_timer_start(sw_db* db, hipStream_t st) {
-    if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
-    const int ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
-    while ((int)db->ev_pool.size() <= ev) {
-        hipEvent_t x, y;
-        if (hipEventCreate(&x) != hipSuccess) return -1;
-        if (hipEventCreate(&y) != hipSuccess) { hipEventDestroy(x); return -1; }
-        db->ev_pool.push_back({x, y});
-    }
-    if (hipEventRecord(db->ev_pool[ev].first, st) != hipSuccess) return -1;
-    return ev;
-}
 
 }  // namespace
 
@@ -1374,18 +1368,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     a.unit_list = 0;
     a.sat = kSat16;
     a.slen = db->slen_sorted.as<int32_t>();
-    int ev = -1;
-    if (db->timing) {
-        if (db->ev_used.size() >= 256) db->ev_used.erase(db->ev_used.begin());
-        ev = (int)((db->ev_used.empty() ? -1 : db->ev_used.back()) + 1) % 256;
-        while ((int)db->ev_pool.size() <= ev) {
-            hipEvent_t x, y;
-            HIP_TRY(hipEventCreate(&x));
-            HIP_TRY(hipEventCreate(&y));
-            db->ev_pool.push_back({x, y});
-        }
-        HIP_TRY(hipEventRecord(db->ev_pool[ev].first, st));
-    }
+    const int ev = db->timing ? record_timer_start(db, st) : -1;
     if (!mi.empty()) HIP_TRY(launch_sweep_mode(mode, a, std::max(1, std::min<int>(db->wg_mode, (int)mi.size())), st));
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
