@@ -34,7 +34,8 @@ hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
 hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st);
-hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu);
+hipError_t launch_sweep_mode16(int mode, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy_mode16(int mode, int* blocks_per_cu);
 hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
                         uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
                         int lds_max, hipStream_t st);
@@ -177,9 +178,7 @@ struct sw_db {
     DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
     DevBuf slen_sorted;               // subject length per sorted slot (end-to-end modes)
     DevBuf topk_ws;                   // candidates of the two-launch top-k of long score rows
-    DevBuf scratch_mode;              // boundary slots of the end-to-end sweeps
     int wg_mode = 0;                  // persistent workgroups of an end-to-end sweep
-    int64_t slot_cap_mode = 0;        // (column x pair) capacity of one of its wave slots
     Plan mode_plan;
     // launch geometry
     int cus = 0, wg16 = 0, wg32 = 0;  // scratch slots (workgroups) of the 16-bit sweeps; 32-bit grid
@@ -270,9 +269,11 @@ int64_t unit_cost(int m, int ncols, int lgB, int R) {
 // Overrides for sweeps other than the 16-bit ones: fixed R, their slot capacity and wave count.
 struct PlanLimits { int R; int64_t slot_cap; int64_t nwaves; };
 
+// Groups [g_lo, g_hi) only (g_hi < 0: to the end).
 void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
                 std::vector<WgItem>& side_out, const std::vector<int>* chunk = nullptr, int nchunks = 1,
-                const PlanLimits* lim = nullptr) {
+                const PlanLimits* lim = nullptr, int g_lo = 0, int g_hi = -1) {
+    if (g_hi < 0) g_hi = db->ngroups;
     const int64_t slot_cap = lim ? lim->slot_cap : db->slot_cap;
     const bool force_R = lim ? true : db->force_R != 0;
     // query qi covers groups chunk[qi], chunk[qi] + nchunks, ... (all groups when nchunks == 1)
@@ -284,7 +285,8 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
         int64_t total = 0;
         for (size_t qi = 0; qi < qlens.size(); ++qi)
             if (qlens[qi] > 0)
-                for (int g = first_group(qi); g < db->ngroups; g += nchunks) total += unit_cost(qlens[qi], db->ncols[g], 0, R_main);
+                for (int g = first_group(qi); g < db->ngroups; g += nchunks)
+                    if (g >= g_lo && g < g_hi) total += unit_cost(qlens[qi], db->ncols[g], 0, R_main);
         const double cap = db->unit_share * (double)total / (double)nwaves;
         R_side = R_main;
         int64_t sum = 0, biggest = 0, sbiggest = 0;
@@ -317,6 +319,7 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
                 cc = std::max(cc, cost);
             };
             for (int g = g_first; g < db->ngroups; g += nchunks) {
+                if (g < g_lo || g >= g_hi) continue;
                 const int nc = db->ncols[g];
                 int lgB = 0;
                 for (; lgB < 6; ++lgB) {
@@ -873,7 +876,7 @@ void sw_db_free(sw_db* db) {
     clear_caches(db);
     db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
-    db->slen_sorted.release(); db->scratch_mode.release(); db->mode_plan.items.release(); db->topk_ws.release();
+    db->slen_sorted.release(); db->mode_plan.items.release(); db->topk_ws.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
     db->counters.release(); db->rerun.release(); db->scores_tmp.release();
     db->hstage.release();
@@ -1328,31 +1331,48 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     if ((s = ensure_workspace(db)) != SW_OK) return s;
     if (db->wg_mode == 0) {
         int b1 = 0, b2 = 0;
-        HIP_TRY(sweep_occupancy_mode(SW_GLOBAL, &b1));
-        HIP_TRY(sweep_occupancy_mode(SW_SEMIGLOBAL, &b2));
-        const int b = std::min(std::min(b1, b2), 2);
-        if (b < 1) return fail(SW_E_HIP, "end-to-end sweep cannot be resident");
-        db->wg_mode = db->cus * b;
-        db->slot_cap_mode = std::max<int64_t>(16384, db->ncols_max);
-        HIP_TRY(db->scratch_mode.reserve((size_t)db->wg_mode * kWaves * db->slot_cap_mode * 16, &db->gen));
+        HIP_TRY(sweep_occupancy_mode16(SW_GLOBAL, &b1));
+        HIP_TRY(sweep_occupancy_mode16(SW_SEMIGLOBAL, &b2));
+        const int b = std::min(std::min(b1, b2), kMaxWgPerCu);
+        if (b < 1) return fail(SW_E_HIP, "16-bit end-to-end sweep cannot be resident");
+        db->wg_mode = std::min(db->cus * b, db->wg16);     // within the 16-bit boundary slots
     }
-    // plan: 32-bit cells at 8 rows per lane, slots of the mode workspace
-    const PlanLimits lim{8, db->slot_cap_mode, (int64_t)db->wg_mode * kWaves};
-    std::vector<WgItem> mi, si;
-    plan_units(db, std::vector<int>{qlen}, &db->mode_plan, mi, si, nullptr, 1, &lim);
+    // 16-bit cells hold values in [128 - bias, kModeTop - bias).  A query whose column-0 border (the gap
+    // run down its length) falls below that range runs wholly in 32-bit cells; in global mode so do the
+    // longest subjects, whose row-0 border does (a prefix of the length-sorted groups).
+    const int64_t lowest = 128 - (int64_t)kModeBias;
+    int g_split = 0;                              // groups [0, g_split) run in 32-bit cells
+    if (gap_run(qlen, gap_open, gap_extend) < lowest) g_split = db->ngroups;
+    else if (mode == SW_GLOBAL)
+        while (g_split < db->ngroups && gap_run(db->ncols[g_split], gap_open, gap_extend) < lowest) ++g_split;
+    std::vector<WgItem> mi, si, m32, s32;
+    if (g_split < db->ngroups) {
+        const PlanLimits lim{16, db->slot_cap, (int64_t)db->wg_mode * kWaves};
+        plan_units(db, std::vector<int>{qlen}, &db->mode_plan, mi, si, nullptr, 1, &lim, g_split, -1);
+    }
+    if (g_split > 0) {
+        // 32-bit units in the 32-bit boundary slots: one wave slot holds the widest subject's columns
+        const PlanLimits lim32{8, std::max<int64_t>(db->ncols_max, 4), (int64_t)db->wg32 * kWaves};
+        Plan tmp;
+        plan_units(db, std::vector<int>{qlen}, &tmp, m32, s32, nullptr, 1, &lim32, 0, g_split);
+    }
     HIP_TRY(hipStreamSynchronize(st));            // the plan buffer may still be read by an earlier launch
-    HIP_TRY(db->mode_plan.items.reserve(sizeof(WgItem) * std::max<size_t>(mi.size(), 1)));
-    if (!mi.empty()) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * mi.size(), hipMemcpyHostToDevice));
+    const size_t n_items = mi.size() + m32.size();
+    HIP_TRY(db->mode_plan.items.reserve(sizeof(WgItem) * std::max<size_t>(n_items, 1)));
+    mi.insert(mi.end(), m32.begin(), m32.end());
+    if (n_items) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * n_items, hipMemcpyHostToDevice));
+    const size_t n16 = n_items - m32.size();
     const int64_t qo[2] = {0, qlen};
     const StageLayout L = stage_layout(qo, 1);
-    if ((s = reserve_for(db, L, (int64_t)db->ngroups * kGroupPairs)) != SW_OK) return s;
+    const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
+    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
     int32_t* ctr = db->counters.as<int32_t>();
     HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
     SweepArgs a{};
     a.items = db->mode_plan.items.as<WgItem>();
-    a.n_items = (int32_t)mi.size();
+    a.n_items = (int32_t)n16;
     a.counter = ctr + 0;
     a.image = db->image.as<uint8_t>();
     a.groups = db->groups.as<GroupRec>();
@@ -1362,22 +1382,60 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     a.qd = S.qd;
     a.go = gap_open;
     a.ge = gap_extend;
-    a.scratch = db->scratch_mode.as<uint32_t>();
-    a.slot_words = db->slot_cap_mode * 4;
+    a.scratch = db->scratch16.as<uint32_t>();
+    a.slot_words = db->slot_cap * 2;
     a.scores = d_scores_out;
+    a.rerun = db->rerun.as<WgItem>();
+    a.rerun_count = ctr + 1;
+    a.rerun_cap = (int32_t)rerun_cap;
     a.unit_list = 0;
-    a.sat = kSat16;
+    // every value carries the middle of the 16-bit range; a pair whose H leaves [128, sat) is recomputed
+    a.bias = kModeBias;
+    a.sat = db->sat < kSat16 ? std::min<int32_t>(kModeBias + db->sat, kModeTop) : kModeTop;
     a.slen = db->slen_sorted.as<int32_t>();
+    if (!m32.empty()) {
+        // the longest subjects in 32-bit cells, concurrently on the side stream
+        SweepArgs b = a;
+        b.items = db->mode_plan.items.as<WgItem>() + n16;
+        b.n_items = (int32_t)m32.size();
+        b.counter = ctr + 3;
+        b.scratch = db->scratch32.as<uint32_t>();
+        b.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
+        b.rerun = nullptr;
+        b.rerun_count = nullptr;
+        b.rerun_cap = 0;
+        b.bias = 0;
+        HIP_TRY(hipEventRecord(db->ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(db->side, db->ev_fork, 0));
+        HIP_TRY(launch_sweep_mode(mode, b, std::max(1, std::min<int>(db->wg32, (int)m32.size())), db->side));
+        HIP_TRY(hipEventRecord(db->ev_join, db->side));
+    }
+    const int grid = std::max(1, std::min<int>(db->wg_mode, (int)n16));
     const int ev = db->timing ? record_timer_start(db, st) : -1;
-    if (!mi.empty()) HIP_TRY(launch_sweep_mode(mode, a, std::max(1, std::min<int>(db->wg_mode, (int)mi.size())), st));
+    if (n16 > 0) HIP_TRY(launch_sweep_mode16(mode, a, grid, st));
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
         db->ev_used.push_back(ev);
     }
-    db->last_items = (int)mi.size();
-    db->last_rows = 8;
-    db->last_side_items = 0;
-    db->last_side_rows = 0;
-    db->last_grid = std::max(1, std::min<int>(db->wg_mode, (int)mi.size()));
+    if (!m32.empty()) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));   // the recompute reuses the 32-bit slots
+    // exact 32-bit recompute of the pairs that left the range; the count is read on the device
+    SweepArgs r = a;
+    r.items = db->rerun.as<WgItem>();
+    r.n_items_dev = ctr + 1;
+    r.n_items = (int32_t)rerun_cap;
+    r.counter = ctr + 2;
+    r.scratch = db->scratch32.as<uint32_t>();
+    r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
+    r.rerun = nullptr;
+    r.rerun_count = nullptr;
+    r.rerun_cap = 0;
+    r.unit_list = 1;
+    r.bias = 0;
+    HIP_TRY(launch_sweep_mode(mode, r, db->wg32, st));
+    db->last_items = (int)n16;
+    db->last_rows = 16;
+    db->last_side_items = (int)m32.size();
+    db->last_side_rows = m32.empty() ? 0 : 8;
+    db->last_grid = grid;
     return SW_OK;
 }

@@ -9,8 +9,10 @@ namespace sw {
 constexpr int kMaxAlphabet = 24;  // residue codes 0..alphabet-1, alphabet <= 24 (20 amino acids + B, Z, X, *)
 constexpr int kNRes = kMaxAlphabet + 1;   // profile rows: padding (image code 0) and residues (codes 1..24)
 constexpr int kPadCode = 0;        // image byte of padding columns (residue codes are stored + 1)
-constexpr int16_t kPadScore = -32768;  // substitution score of padding: any biased 16-bit H plus it stays
-                                       // at or below -1025, a finite negative half float
+constexpr int16_t kPadScore = 0;       // substitution score of padding: never above a real score's effect
+                                       // (S is unchanged), and padded cells copy real values diagonally
+                                       // instead of decaying, so the 16-bit range checks of the end-to-end
+                                       // modes see only values of real cells
 constexpr int kGroupPairs = 64;    // subject pairs per group (one per lane of a wave)
 constexpr int kGroupSubjects = 2 * kGroupPairs;
 constexpr int kChunkCols = 4;      // columns per interleaved chunk (one dword per subject)
@@ -20,6 +22,10 @@ constexpr int kRowsMax = 16;       // most query rows per lane (R) of any sweep 
 constexpr int kSliceRows = 1024;   // largest rows-per-pass (B*R) kept in LDS: 64 lanes x 16 rows
 constexpr int kProfRowAlign = 1024;    // profile row stride is a multiple of this (covers every B*R)
 constexpr int16_t kSat16 = 0x7C00; // 16-bit scores at or above this are recomputed in 32 bits
+// End-to-end modes in 16-bit cells: every value carries kModeBias (the middle of
+// the exact range), and a pair whose H leaves [128, kModeTop) is recomputed in 32 bits.
+constexpr int32_t kModeBias = 0x3E00;
+constexpr int32_t kModeTop = 0x7C00 - 128;
 
 // Packed database image, one record per group of 128 length-sorted subjects.
 // Residues of group g live at image + base, as chunk rows of kChunkBytes bytes:
@@ -74,7 +80,8 @@ struct SweepArgs {
     int32_t rerun_cap;
     int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
     int32_t sat;                  // 16-bit scores >= sat (biased) are recomputed with 32-bit cells
-    int32_t bias;                 // 16-bit cells carry H, E, F + bias (>= minus the lowest substitution score)
+    int32_t bias;                 // 16-bit cells carry H, E, F + bias (>= minus the lowest substitution score;
+                                  // end-to-end modes: the middle of the 16-bit range)
     const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
     const int32_t* slen;          // end-to-end modes: subject length per sorted slot (0 for padding slots)
 };

@@ -34,8 +34,11 @@
 // floor c (E >= c keeps every H >= c, the local floor; F needs none), and one
 // more folds two rows' H into S.  Subtractions saturate at zero
 // (v_pk_sub_u16), so a value that drops below c only stands for one below
-// zero, which the floors make irrelevant.  Padding scores -32768, which keeps
-// its sums finite and negative.  So S < kSat16 (0x7C00) is exact (no H reached
+// zero, which the floors make irrelevant.  Padding rows and columns score 0:
+// a padded sum is a stored value plus zero, never one of the NaN patterns
+// -1023..-1, and padding cannot raise S above what the real cells reach
+// (a padded cell only repeats a real value along its diagonal, and local
+// cells start from the floor).  So S < kSat16 (0x7C00) is exact (no H reached
 // it, so no sum was clamped) and the score is S - c; S >= kSat16 sends the
 // pair to the 32-bit sweep.
 #include <hip/hip_runtime.h>
@@ -197,6 +200,16 @@ struct CellI32 {
 #define SW_BLKW(r, c, n, w) SWAW(r, n, w) SWD(r, c) SWF(r) SWE(r) SWH SWG(r) SWI
 #define SW_BLKWS(r, c, n, w, rp) SW_BLKW(r, c, n, w) SWM(rp, r)
 
+// End-to-end modes: no local floor (E' = max(es, hgo), one packed maximum),
+// and every two rows H folds into a running maximum (%[s]) and a running
+// minimum (%[lmin]) that tell whether all values stayed in the exact range.
+#define SWG0(r) "v_pk_max_i16 %[e" #r "], %[es], %[hgo]\n"
+#define SWN(a, b) "v_pk_minimum3_f16 %[lmin], %[lmin], %[h" #a "], %[h" #b "]\n"
+#define SW_MBLK(r, c, n, k2, sel2) SWA(r, n) SWD(r, c) SWF(r) SWE(r) SWH SWP(k2, sel2) SWG0(r) SWI
+#define SW_MBLKS(r, c, n, k2, sel2, rp) SW_MBLK(r, c, n, k2, sel2) SWM(rp, r) SWN(rp, r)
+#define SW_MBLKN(r, c, n) SWA(r, n) SWD(r, c) SWF(r) SWE(r) SWH SWG0(r) SWI
+#define SW_MLAST(r, c, rp) SWF(r) SWD(r, c) SWH SWE(r) SWM(rp, r) SWN(rp, r) SWG0(r) SWI
+
 #define SW_HE(i) [h##i] "+v"(H[i]), [e##i] "+v"(E[i])
 #define SW_AB(i) [a##i] "v"(pa[i]), [b##i] "v"(pb[i])
 #define SW_W(i) [w##i] "v"(w[i])
@@ -260,6 +273,25 @@ __device__ __forceinline__ void rows16_packed(s2* H, s2* E, s2& S, s2& F, s2 dia
             : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_OUTS
             : SW_INS, SW_W(0), SW_W(1), SW_W(2), SW_W(3));
     }
+}
+
+// End-to-end modes, subject-pair form, 16 rows: S is the running maximum of
+// H, lmin the running minimum (both for the range check).
+__device__ __forceinline__ void rows16_pair_mode(s2* H, s2* E, s2& S, s2& lmin, s2& F, s2 diag, const uint32_t* pa,
+                                                 const uint32_t* pb, u2 go, u2 ge) {
+    s2 d0, d1, hgo, es, fs, sm;
+    const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
+    asm(SW_PRO SW_MBLK(0, 0, 1, 1, s0) SW_MBLKS(1, 1, 0, 1, s1, 0) SW_MBLK(2, 0, 1, 2, s0)
+            SW_MBLKS(3, 1, 0, 2, s1, 2) SW_MBLK(4, 0, 1, 3, s0) SW_MBLKS(5, 1, 0, 3, s1, 4) SW_MBLK(6, 0, 1, 4, s0)
+                SW_MBLKS(7, 1, 0, 4, s1, 6) SW_MBLK(8, 0, 1, 5, s0) SW_MBLKS(9, 1, 0, 5, s1, 8)
+                    SW_MBLK(10, 0, 1, 6, s0) SW_MBLKS(11, 1, 0, 6, s1, 10) SW_MBLK(12, 0, 1, 7, s0)
+                        SW_MBLKS(13, 1, 0, 7, s1, 12) SW_MBLKN(14, 0, 1) SW_MLAST(15, 1, 14)
+        : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
+          SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), [s] "+v"(S), [lmin] "+v"(lmin),
+          [f] "+v"(F), [d0] "=&v"(d0), [d1] "=&v"(d1), [hgo] "=&v"(hgo), [es] "=&v"(es), [fs] "=&v"(fs),
+          [sm] "=&v"(sm)
+        : [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge), SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5),
+          SW_AB(6), SW_AB(7), [s0] "s"(s0), [s1] "s"(s1));
 }
 
 // ------------------------------------------------------------ one pass of one wave
@@ -342,7 +374,10 @@ struct EndCtx {
     int go, ge, ext;          // Go, Ge, min(Go, Ge)
     bool top;                 // pass 0: row 0 is the border
     bool last;                // the last pass: it holds the query's last row
+    int bias;                 // 16-bit cells: the bias every value carries
     __device__ int border(int k) const { return k <= 0 ? 0 : -(go + (k - 1) * ext); }
+    // a value as a biased 16-bit cell, clamped to [0, 0x7FFF] (a clamped value fails the range check)
+    __device__ short enc(int v) const { v += bias; return (short)(v < 0 ? 0 : v > 0x7FFF ? 0x7FFF : v); }
 };
 
 template <class C, int R, bool COOP, bool PACKED, int MODE = 0>
@@ -482,6 +517,123 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     }
 }
 
+// End-to-end modes in 16-bit cells (subject pairs, 16 rows per lane).  Values
+// carry the bias ec.bias (the middle of the 16-bit range), so that
+// H = max(hd, E, F) is one v_pk_maximum3_f16 as in the local sweep; there is
+// no floor, and a subtraction that saturates at 0 only stands for a value
+// below the range.  lmin and lmax fold every H: while all of a pair's H stay
+// in [kModeLo, a.sat) (and its borders are representable), every value is
+// exact; otherwise the pair is recomputed in 32-bit cells.  Padding scores 0,
+// so padded cells copy real values diagonally rather than leaving the range,
+// and the borders of padded rows and columns repeat the last real ones.
+constexpr int kModeLo = 128;       // lowest safe biased H: H + SM stays >= 0 for every int8 SM
+
+__device__ __forceinline__ short usub16(short v, int g) {
+    const int x = (int)(unsigned short)v - g;
+    return (short)(x < 0 ? 0 : x);
+}
+
+template <bool COOP, int MODE>
+__device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, int B, int b, const int16_t* lrow,
+                                                  u2 go, u2 ge, s2& S, s2& lmin, s2& lmax, const EndCtx& ec) {
+    constexpr int R = 16;
+    using C = CellI16;
+    using T = s2;
+    using RV = Res<false>::V;
+    constexpr int W = C::kWords;
+    const int nsteps = ncols + B - 1;
+    const int nloop = (nsteps + 3) >> 2;
+    const bool first_lane = (b == 0);
+
+    T H[R], E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const short hb = ec.enc(ec.border(min(ec.row0 + r + 1, ec.m)));   // H[i][0]; padded rows repeat row m's
+        H[r] = T{hb, hb};
+        const short e = usub16(hb, ec.go);                                   // E[i][1]
+        E[r] = T{e, e};
+    }
+    const short hb0 = ec.enc(ec.border(min(ec.row0, ec.m)));
+    T diag = T{hb0, hb0};          // H[row above][0]
+    T up_h = diag, up_f = C::zero();   // what lane b-1 hands over before its first column
+    const int rcap = ec.m - 1 - ec.row0;
+    const bool cap = ec.last && rcap >= 0 && rcap < R;     // this lane holds the query's last row
+
+    const int coff = COOP ? ((-b) >> 2) : 0;
+    const int csh = COOP ? ((-b) & 3) : 0;
+    auto res_at = [&](int c) { return Res<false>::load(io.img, io.img_lane + (uint32_t)(c * kChunkBytes)); };
+    auto resid = [&](RV lo, RV hi) { return COOP ? Res<false>::align(hi, lo, csh) : lo; };
+    RV c0 = res_at(coff), c1 = res_at(coff + 1), c2 = res_at(coff + 2);
+    uint4 bw[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) bw[i] = ld128(io.bnd, io.rd_lane + 16u * i);
+    RV rr = resid(c0, c1);
+    uint32_t cur[R];
+    fetch<R, false>(lrow, rr, 0, cur);
+    for (int c = 0; c < nloop; ++c) {
+        const RV c3 = res_at(coff + c + 3);
+        uint4 nw[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) nw[i] = ld128(io.bnd, io.rd_lane + (uint32_t)(c + 1) * io.cstride + 16u * i);
+        const RV rn = resid(c1, c2);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t nxt[R];
+            if (u < 3) fetch<R, false>(lrow, rr, u + 1, nxt);
+            else fetch<R, false>(lrow, rn, 0, nxt);
+            T htop, ftop;
+            C::col(bw, u, htop, ftop);
+            if (COOP) {
+                htop = C::sel(first_lane, htop, up_h);
+                ftop = C::sel(first_lane, ftop, up_f);
+            }
+            const int col = 4 * c + u - (COOP ? b : 0);
+            if (first_lane && ec.top) {
+                // row 0: the gap-run border (global; padded columns repeat the last real one) or 0
+                const short ta = ec.enc(MODE == 1 ? ec.border(min(col + 1, ec.na)) : 0);
+                const short tb = ec.enc(MODE == 1 ? ec.border(min(col + 1, ec.nb)) : 0);
+                htop = T{ta, tb};
+                ftop = T{usub16(ta, ec.go), usub16(tb, ec.go)};
+            }
+            T F = ftop;
+            // a cooperating lane starts b steps late and keeps the border until its first column (the
+            // asm block runs under the lane mask)
+            if (!COOP || col >= 0) rows16_pair_mode(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge);
+            if (cap) {
+                T hc = H[0];
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    if (r == rcap) hc = H[r];
+                if (col >= 0) {                     // a lane before its first column captures nothing
+                    if (MODE == 1) {
+                        if (col == ec.na - 1) S.x = hc.x;
+                        if (col == ec.nb - 1) S.y = hc.y;
+                    } else {
+                        if (col < ec.na) S.x = max(S.x, hc.x);
+                        if (col < ec.nb) S.y = max(S.y, hc.y);
+                    }
+                }
+            }
+            diag = htop;
+            const T hbot = H[R - 1];
+            const int j = 4 * c + u - (B - 1);
+            C::put(io.bnd, io.wr_lane + (uint32_t)((j >> 2) * (int)io.cstride + (j & 3) * 4 * W), hbot, F);
+            if (COOP) {
+                up_h = C::shift(hbot);
+                up_f = C::shift(F);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+        }
+        c0 = c1;
+        c1 = c2;
+        c2 = c3;
+        rr = rn;
+#pragma unroll
+        for (int i = 0; i < W; ++i) bw[i] = nw[i];
+    }
+}
+
 // Load rows [row0, row0 + B*R) of a query profile into LDS as [b][residue][R],
 // in 16-byte units (8-byte units when R = 4).
 template <int R>
@@ -584,6 +736,8 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         ub = a.bias;
     }
     T S = bias;
+    constexpr bool kMode16 = MODE != 0 && std::is_same<C, CellI16>::value;
+    T lmin = C::zero(), lmax = C::zero();       // 16-bit end-to-end modes: range of every H
     EndCtx ec{};
     if constexpr (MODE != 0) {
         ec.m = m;
@@ -595,9 +749,19 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         ec.nb = valid ? a.slen[slot0 + 1] : 0;
         // the lane holding the query's last row starts S at H[m][0] where that counts
         const bool cap = (m - 1 - (passes - 1) * rows_pp) / R == b;
-        constexpr int kNeg = -(1 << 30);
-        const int hm = ec.border(m);
-        S = T{cap && (MODE == 2 || ec.na == 0) ? hm : kNeg, cap && (MODE == 2 || ec.nb == 0) ? hm : kNeg};
+        if constexpr (kMode16) {
+            static_assert(R == 16, "16-bit end-to-end sweeps use 16 rows per lane");
+            ec.bias = a.bias;
+            const short hm = ec.enc(ec.border(m));
+            S = T{cap && (MODE == 2 || ec.na == 0) ? hm : (short)0, cap && (MODE == 2 || ec.nb == 0) ? hm : (short)0};
+            // the extreme borders (column 0 at the last row; row 0 at the last column, global) must fit too
+            const short ta = MODE == 1 ? ec.enc(ec.border(ec.na)) : hm, tb = MODE == 1 ? ec.enc(ec.border(ec.nb)) : hm;
+            lmin = T{min(hm, ta), min(hm, tb)};
+        } else {
+            constexpr int kNeg = -(1 << 30);
+            const int hm = ec.border(m);
+            S = T{cap && (MODE == 2 || ec.na == 0) ? hm : kNeg, cap && (MODE == 2 || ec.nb == 0) ? hm : kNeg};
+        }
     }
     // A unit with many lanes per matrix is a long subject: its passes are one
     // serial chain of steps that can outlast the rest of the search, so its
@@ -631,16 +795,30 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
             ec.row0 = p * rows_pp + b * R;
             ec.top = p == 0;
             ec.last = p == passes - 1;
-            if (lgB == 0)
-                sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
-            else
-                sweep_pass<C, R, true, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
+            if constexpr (kMode16) {
+                if (lgB == 0)
+                    sweep_pass_mode16<false, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
+                else
+                    sweep_pass_mode16<true, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
+            } else {
+                if (lgB == 0)
+                    sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
+                else
+                    sweep_pass<C, R, true, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // boundary stores visible to the next pass
     }
     if (chain) __builtin_amdgcn_s_setprio(0);
     if (!valid) return;
     for (int o = 1; o < B; o <<= 1) S = C::xmax(S, o);
+    int out_of_range = 0;                       // 16-bit end-to-end: some value left the exact range
+    if constexpr (kMode16) {
+        const bool ra = (unsigned short)lmin.x < kModeLo || (unsigned short)lmax.x >= (unsigned)a.sat;
+        const bool rb = (unsigned short)lmin.y < kModeLo || (unsigned short)lmax.y >= (unsigned)a.sat;
+        out_of_range = (ra || rb) ? 1 : 0;
+        for (int o = 1; o < B; o <<= 1) out_of_range |= __shfl_xor(out_of_range, o, 64);
+    }
     if (b != 0) return;
     if constexpr (PACKED) {
         const int o = a.perm[g * kGroupSubjects + su];
@@ -663,6 +841,7 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         if (o0 >= 0) out[o0] = C::lo(S) - ub;
         if (o1 >= 0) out[o1] = C::hi(S) - ub;
         if (MODE == 0 && a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
+        if (kMode16 && a.rerun != nullptr && out_of_range) append_rerun(a, g, qa, su);
     }
 }
 
@@ -967,6 +1146,27 @@ static const void* mode_kernel(int mode) {
     return nullptr;
 }
 
+static const void* mode16_kernel(int mode) {
+    if (mode == 1) return (const void*)k_sweep<CellI16, 16, 1>;
+    if (mode == 2) return (const void*)k_sweep<CellI16, 16, 2>;
+    return nullptr;
+}
+
+// End-to-end modes in 16-bit cells (16 rows per lane); out-of-range pairs go to the rerun list.
+hipError_t launch_sweep_mode16(int mode, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = mode16_kernel(mode);
+    if (!k) return hipErrorInvalidValue;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
+}
+
+hipError_t sweep_occupancy_mode16(int mode, int* blocks_per_cu) {
+    const void* k = mode16_kernel(mode);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
+}
+
 hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st) {
     const void* k = mode_kernel(mode);
     if (!k) return hipErrorInvalidValue;
@@ -975,11 +1175,6 @@ hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t
     return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
 }
 
-hipError_t sweep_occupancy_mode(int mode, int* blocks_per_cu) {
-    const void* k = mode_kernel(mode);
-    if (!k) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
-}
 
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {
     const void* k = sweep_kernel(i16, R);

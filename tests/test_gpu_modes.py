@@ -102,3 +102,56 @@ def test_mode_range_and_argument_errors(gpu, blosum):
     with pytest.raises(gpu.SwError):
         gpu.sw_search_mode(3, q, D.handle, db.offsets, db.n, blosum, 10, 2, out)
     D.close()
+
+
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+def test_mode_scores_beyond_the_16bit_range(gpu, blosum, mode):
+    """16-bit end-to-end cells hold values within about +-15,700 of the middle of
+    their range: a 22,000-point self alignment leaves it and goes to the 32-bit
+    recompute, exactly."""
+    W = 17
+    rng = np.random.default_rng(44)
+    subs = [np.full(2000, W, np.int8), np.concatenate([np.full(1000, W, np.int8), synth.background_residues(rng, 300)])]
+    subs += [synth.background_residues(rng, int(L)) for L in rng.integers(1, 600, 60)]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum([s.size for s in subs])
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    q = np.full(2000, W, np.int8)
+    _check(gpu, D, db, q, blosum, 10, 2, mode, f"{mode} W-run")
+    assert D.stats()["rerun_pairs"] >= 1
+    _check(gpu, D, db, synth.small_query(seed=45, m=300), blosum, 10, 2, mode, f"{mode} short query")
+    D.close()
+
+
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+@pytest.mark.parametrize("lanes", [0, 8])
+def test_mode_forced_recompute(gpu, blosum, mode, lanes):
+    """With the recompute threshold at 1 every pair with a positive H goes through
+    the 32-bit sweep as well; the scores do not change."""
+    db = _db(34, 150, 1, 500)
+    D = gpu.Database(db.residues, db.offsets, rerun_threshold=1, force_lanes=lanes)
+    for m in (5, 170):
+        _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, 10, 2, mode, f"{mode} forced m={m}")
+    assert D.stats()["rerun_pairs"] >= 10
+    D.close()
+
+
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+def test_modes_with_the_longest_group_in_32bit_cells(gpu, blosum, mode):
+    """Global mode: subjects whose row-0 border leaves the 16-bit range (a gap run
+    of more than ~7,800 residues at 10/2) form the first length-sorted group and
+    run in 32-bit cells beside the 16-bit launch of the other groups."""
+    rng = np.random.default_rng(46)
+    lens = [20000, 9000, 8000] + list(rng.integers(1, 900, 400))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    for m in (90, 700):
+        _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, 10, 2, mode, f"{mode} m={m}")
+        st = D.stats()
+        assert st["items"] > 0
+        assert (st["side_items"] > 0) == (mode == "global")
+    D.close()
