@@ -212,10 +212,15 @@ enum { SW_LOCAL = 0, SW_GLOBAL = 1, SW_SEMIGLOBAL = 2 };
  *   SW_GLOBAL      H[0][j] = g(j), S = H[m][n] (both sequences end to end);
  *   SW_SEMIGLOBAL  H[0][j] = 0, S = max over j of H[m][j] (the whole query
  *                  against any stretch of the subject).
- * Scores may be negative.  These modes run in exact 32-bit cells (about a
- * third of the local search's rate); SW_E_UNSUPPORTED if
- * Go + (qlen + longest subject) * max(Go, Ge) could leave +-2^29.  Other
- * arguments and errors as for sw_search.
+ * Scores may be negative.  Cells are 16-bit with a bias and a check that
+ * every H of a pair stayed in the exact range; pairs that left it are
+ * recomputed in 32-bit cells, and in SW_GLOBAL subjects whose row-0 gap run
+ * leaves the range run in 32-bit cells from the start, so every score is
+ * exact.  SW_E_UNSUPPORTED if Go + (qlen + longest subject) * max(Go, Ge)
+ * could leave +-2^29.  Other arguments and errors as for sw_search;
+ * sw_last_stats reports the 16-bit launch (out[0], out[2]) and, in out[4] and
+ * out[5], the launches beside it (long pairs of a short query at 4 or 8 rows
+ * per lane, and the 32-bit subjects).
  */
 sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
                          int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,

@@ -33,9 +33,9 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
 hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu);
 hipError_t launch_sweep_q2(int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
-hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st);
-hipError_t launch_sweep_mode16(int mode, const SweepArgs& a, int grid, hipStream_t st);
-hipError_t sweep_occupancy_mode16(int mode, int* blocks_per_cu);
+hipError_t launch_sweep_mode(int mode, int R, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t launch_sweep_mode16(int mode, int R, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_occupancy_mode16(int mode, int R, int* blocks_per_cu);
 hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
                         uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
                         int lds_max, hipStream_t st);
@@ -186,8 +186,9 @@ struct sw_db {
     int wgQ[17] = {0};                // persistent workgroups per query-pair instance, by R
     int64_t slot_cap = 0;             // (column x pair) capacity of one wave's boundary slot
     hipStream_t side = nullptr;       // second stream for the long pairs of short queries
+    hipStream_t side2 = nullptr;      // third stream (end-to-end modes: the 32-bit groups beside both 16-bit launches)
     hipStream_t cap = nullptr;        // stream the batched sequence is captured on
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     // workspace
     uint64_t gen = 1;                 // bumped on every workspace reallocation
     DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp;
@@ -213,7 +214,8 @@ struct sw_db {
 
 namespace {
 
-constexpr int kCounters = 4;   // [0] bulk sweep counter, [1] rerun count, [2] rerun counter, [3] side sweep counter
+// [0] bulk sweep counter, [1] rerun count, [2] rerun counter, [3] side sweep counter, [4] second side sweep counter
+constexpr int kCounters = 5;
 constexpr int kRerunGrid = 64;
 constexpr int kRerunRows = 8;  // rows per lane of the 32-bit recompute
 constexpr int kMaxWgPerCu = 4; // persistent workgroups per CU (bounds the scratch slots)
@@ -266,8 +268,9 @@ int64_t unit_cost(int m, int ncols, int lgB, int R) {
 // are pairs that a single wave sweeps column by column; for a single short
 // query a smaller R makes them cheaper (most of a 64 x 16-row pass would be
 // padding) and they go to the side list.  Items are ordered longest first.
-// Overrides for sweeps other than the 16-bit ones: fixed R, their slot capacity and wave count.
-struct PlanLimits { int R; int64_t slot_cap; int64_t nwaves; };
+// Overrides for sweeps other than the 16-bit ones: fixed R, their slot capacity and wave count, and
+// whether the long pairs of a single short query may still go to the side list at a smaller R.
+struct PlanLimits { int R; int64_t slot_cap; int64_t nwaves; bool side = false; };
 
 // Groups [g_lo, g_hi) only (g_hi < 0: to the end).
 void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std::vector<WgItem>& main_out,
@@ -294,7 +297,7 @@ void plan_units(const sw_db* db, const std::vector<int>& qlens, Plan* plan, std:
             const int m = qlens[qi];
             if (m <= 0) continue;
             int r_long = R_main;
-            if (qlens.size() == 1 && !force_R)
+            if (qlens.size() == 1 && (!force_R || (lim && lim->side)))
                 for (int R : kRowChoices)
                     if (unit_cost(m, db->ncols_max, 6, R) < unit_cost(m, db->ncols_max, 6, r_long)) r_long = R;
             const int g_first = first_group(qi);
@@ -544,9 +547,11 @@ sw_status ensure_workspace(sw_db* db) {
         HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4, &db->gen));
         HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t), &db->gen));
         HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&db->side2, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&db->cap, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&db->ev_join2, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
     }
     return SW_OK;
@@ -882,9 +887,11 @@ void sw_db_free(sw_db* db) {
     db->hstage.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (db->side) hipStreamDestroy(db->side);
+    if (db->side2) hipStreamDestroy(db->side2);
     if (db->cap) hipStreamDestroy(db->cap);
     if (db->ev_fork) hipEventDestroy(db->ev_fork);
     if (db->ev_join) hipEventDestroy(db->ev_join);
+    if (db->ev_join2) hipEventDestroy(db->ev_join2);
     delete db;
 }
 
@@ -1111,7 +1118,7 @@ sw_status sw_kernel_times(sw_db* db, float* ms_out, int32_t cap, int32_t* count)
 sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
     if (!db || !out) return fail(SW_E_INVALID, "NULL argument");
     DeviceGuard dg(db->device);
-    int32_t c[kCounters] = {0, 0, 0, 0};
+    int32_t c[kCounters] = {};
     if (db->counters.p) {
         HIP_TRY(hipDeviceSynchronize());
         HIP_TRY(hipMemcpy(c, db->counters.p, sizeof c, hipMemcpyDeviceToHost));
@@ -1331,37 +1338,49 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     if ((s = ensure_workspace(db)) != SW_OK) return s;
     if (db->wg_mode == 0) {
         int b1 = 0, b2 = 0;
-        HIP_TRY(sweep_occupancy_mode16(SW_GLOBAL, &b1));
-        HIP_TRY(sweep_occupancy_mode16(SW_SEMIGLOBAL, &b2));
+        HIP_TRY(sweep_occupancy_mode16(SW_GLOBAL, 16, &b1));
+        HIP_TRY(sweep_occupancy_mode16(SW_SEMIGLOBAL, 16, &b2));
         const int b = std::min(std::min(b1, b2), kMaxWgPerCu);
         if (b < 1) return fail(SW_E_HIP, "16-bit end-to-end sweep cannot be resident");
         db->wg_mode = std::min(db->cus * b, db->wg16);     // within the 16-bit boundary slots
     }
-    // 16-bit cells hold values in [128 - bias, kModeTop - bias).  A query whose column-0 border (the gap
-    // run down its length) falls below that range runs wholly in 32-bit cells; in global mode so do the
-    // longest subjects, whose row-0 border does (a prefix of the length-sorted groups).
-    const int64_t lowest = 128 - (int64_t)kModeBias;
+    // 16-bit cells hold values in [128 - bias, kModeTop - bias).  Semi-global H never falls below the
+    // gap run down the query, -(Go + (m - 1) Ge), so its bias is just large enough for that (at most the
+    // middle of the range), which leaves the most room above for high scores; global H can fall further
+    // (gap runs along both sequences) and keeps the middle.
+    int32_t bias = kModeBias;
+    if (mode == SW_SEMIGLOBAL)
+        bias = (int32_t)std::min<int64_t>(kModeBias, 128 + (int64_t)gap_open + (int64_t)(qlen - 1) * gap_extend);
+    // A query whose column-0 border (the gap run down its length) falls below the range runs wholly in
+    // 32-bit cells; in global mode so do the longest subjects, whose row-0 border does (a prefix of the
+    // length-sorted groups).
+    const int64_t lowest = 128 - (int64_t)bias;
     int g_split = 0;                              // groups [0, g_split) run in 32-bit cells
     if (gap_run(qlen, gap_open, gap_extend) < lowest) g_split = db->ngroups;
     else if (mode == SW_GLOBAL)
         while (g_split < db->ngroups && gap_run(db->ncols[g_split], gap_open, gap_extend) < lowest) ++g_split;
+    // 16-bit plan at 16 rows per lane; the long pairs of a short query go to a side list at 4 or 8 rows
     std::vector<WgItem> mi, si, m32, s32;
     if (g_split < db->ngroups) {
-        const PlanLimits lim{16, db->slot_cap, (int64_t)db->wg_mode * kWaves};
+        PlanLimits lim{16, db->slot_cap, (int64_t)db->wg_mode * kWaves};
+        lim.side = true;
         plan_units(db, std::vector<int>{qlen}, &db->mode_plan, mi, si, nullptr, 1, &lim, g_split, -1);
     }
+    // (4 rows per lane measured no faster for the 32-bit chain of a short query, and slower for longer ones)
+    constexpr int R32 = 8;
     if (g_split > 0) {
         // 32-bit units in the 32-bit boundary slots: one wave slot holds the widest subject's columns
-        const PlanLimits lim32{8, std::max<int64_t>(db->ncols_max, 4), (int64_t)db->wg32 * kWaves};
+        const PlanLimits lim32{R32, std::max<int64_t>(db->ncols_max, 4), (int64_t)db->wg32 * kWaves};
         Plan tmp;
         plan_units(db, std::vector<int>{qlen}, &tmp, m32, s32, nullptr, 1, &lim32, 0, g_split);
     }
     HIP_TRY(hipStreamSynchronize(st));            // the plan buffer may still be read by an earlier launch
-    const size_t n_items = mi.size() + m32.size();
+    // device item list: [16-bit main..., 16-bit side..., 32-bit...]
+    const size_t n16 = mi.size(), n16s = si.size(), n_items = n16 + n16s + m32.size();
     HIP_TRY(db->mode_plan.items.reserve(sizeof(WgItem) * std::max<size_t>(n_items, 1)));
+    mi.insert(mi.end(), si.begin(), si.end());
     mi.insert(mi.end(), m32.begin(), m32.end());
     if (n_items) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * n_items, hipMemcpyHostToDevice));
-    const size_t n16 = n_items - m32.size();
     const int64_t qo[2] = {0, qlen};
     const StageLayout L = stage_layout(qo, 1);
     const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
@@ -1384,40 +1403,59 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     a.ge = gap_extend;
     a.scratch = db->scratch16.as<uint32_t>();
     a.slot_words = db->slot_cap * 2;
+    a.slot_base = 0;
     a.scores = d_scores_out;
     a.rerun = db->rerun.as<WgItem>();
     a.rerun_count = ctr + 1;
     a.rerun_cap = (int32_t)rerun_cap;
     a.unit_list = 0;
-    // every value carries the middle of the 16-bit range; a pair whose H leaves [128, sat) is recomputed
-    a.bias = kModeBias;
-    a.sat = db->sat < kSat16 ? std::min<int32_t>(kModeBias + db->sat, kModeTop) : kModeTop;
+    // every value carries the bias; a pair whose H leaves [128, sat) is recomputed
+    a.bias = bias;
+    a.sat = db->sat < kSat16 ? std::min<int32_t>(bias + db->sat, kModeTop) : kModeTop;
     a.slen = db->slen_sorted.as<int32_t>();
-    if (!m32.empty()) {
-        // the longest subjects in 32-bit cells, concurrently on the side stream
+    // the 16-bit side launch takes the first slots; the 16-bit bulk launch fills the rest
+    const int grid_side = n16s ? std::min<int>((int)n16s, std::max(1, db->wg_mode / 8)) : 0;
+    const int grid = std::max(1, std::min<int>(db->wg_mode - grid_side, std::max<int>((int)n16, 1)));
+    if (n16s || !m32.empty()) {
+        HIP_TRY(hipEventRecord(db->ev_fork, st));
+        if (n16s) HIP_TRY(hipStreamWaitEvent(db->side, db->ev_fork, 0));
+        if (!m32.empty()) HIP_TRY(hipStreamWaitEvent(db->side2, db->ev_fork, 0));
+    }
+    if (n16s) {
+        // long pairs of a short query at fewer rows per lane, concurrently on the side stream
         SweepArgs b = a;
         b.items = db->mode_plan.items.as<WgItem>() + n16;
-        b.n_items = (int32_t)m32.size();
+        b.n_items = (int32_t)n16s;
         b.counter = ctr + 3;
+        b.slot_base = grid;
+        HIP_TRY(launch_sweep_mode16(mode, db->mode_plan.R_side, b, grid_side, db->side));
+        HIP_TRY(hipEventRecord(db->ev_join, db->side));
+    }
+    if (!m32.empty()) {
+        // the longest subjects in 32-bit cells, concurrently on the second side stream
+        SweepArgs b = a;
+        b.items = db->mode_plan.items.as<WgItem>() + n16 + n16s;
+        b.n_items = (int32_t)m32.size();
+        b.counter = ctr + 4;
         b.scratch = db->scratch32.as<uint32_t>();
         b.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
         b.rerun = nullptr;
         b.rerun_count = nullptr;
         b.rerun_cap = 0;
         b.bias = 0;
-        HIP_TRY(hipEventRecord(db->ev_fork, st));
-        HIP_TRY(hipStreamWaitEvent(db->side, db->ev_fork, 0));
-        HIP_TRY(launch_sweep_mode(mode, b, std::max(1, std::min<int>(db->wg32, (int)m32.size())), db->side));
-        HIP_TRY(hipEventRecord(db->ev_join, db->side));
+        HIP_TRY(launch_sweep_mode(mode, R32, b, std::max(1, std::min<int>(db->wg32, (int)m32.size())), db->side2));
+        HIP_TRY(hipEventRecord(db->ev_join2, db->side2));
     }
-    const int grid = std::max(1, std::min<int>(db->wg_mode, (int)n16));
     const int ev = db->timing ? record_timer_start(db, st) : -1;
-    if (n16 > 0) HIP_TRY(launch_sweep_mode16(mode, a, grid, st));
+    if (n16 > 0) HIP_TRY(launch_sweep_mode16(mode, 16, a, grid, st));
+    // the recompute reads the side launches' rerun entries and reuses the 32-bit slots; the timed
+    // region of the sweep ends when all three launches have
+    if (n16s) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));
+    if (!m32.empty()) HIP_TRY(hipStreamWaitEvent(st, db->ev_join2, 0));
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
         db->ev_used.push_back(ev);
     }
-    if (!m32.empty()) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));   // the recompute reuses the 32-bit slots
     // exact 32-bit recompute of the pairs that left the range; the count is read on the device
     SweepArgs r = a;
     r.items = db->rerun.as<WgItem>();
@@ -1431,11 +1469,11 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     r.rerun_cap = 0;
     r.unit_list = 1;
     r.bias = 0;
-    HIP_TRY(launch_sweep_mode(mode, r, db->wg32, st));
+    HIP_TRY(launch_sweep_mode(mode, kRerunRows, r, db->wg32, st));
     db->last_items = (int)n16;
     db->last_rows = 16;
-    db->last_side_items = (int)m32.size();
-    db->last_side_rows = m32.empty() ? 0 : 8;
-    db->last_grid = grid;
+    db->last_side_items = (int)(n16s + m32.size());
+    db->last_side_rows = n16s ? db->mode_plan.R_side : m32.empty() ? 0 : R32;
+    db->last_grid = grid + grid_side;
     return SW_OK;
 }

@@ -275,23 +275,37 @@ __device__ __forceinline__ void rows16_packed(s2* H, s2* E, s2& S, s2& F, s2 dia
     }
 }
 
-// End-to-end modes, subject-pair form, 16 rows: S is the running maximum of
-// H, lmin the running minimum (both for the range check).
+// End-to-end modes, subject-pair form, R = 16, 8 or 4 rows: S is the running
+// maximum of H, lmin the running minimum (both for the range check).
+#define SW_MOUTS [s] "+v"(S), [lmin] "+v"(lmin), [f] "+v"(F), [d0] "=&v"(d0), [d1] "=&v"(d1), [hgo] "=&v"(hgo), \
+                 [es] "=&v"(es), [fs] "=&v"(fs), [sm] "=&v"(sm)
+#define SW_MINS [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge), [s0] "s"(s0), [s1] "s"(s1)
+template <int R>
 __device__ __forceinline__ void rows16_pair_mode(s2* H, s2* E, s2& S, s2& lmin, s2& F, s2 diag, const uint32_t* pa,
                                                  const uint32_t* pb, u2 go, u2 ge) {
     s2 d0, d1, hgo, es, fs, sm;
     const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
-    asm(SW_PRO SW_MBLK(0, 0, 1, 1, s0) SW_MBLKS(1, 1, 0, 1, s1, 0) SW_MBLK(2, 0, 1, 2, s0)
-            SW_MBLKS(3, 1, 0, 2, s1, 2) SW_MBLK(4, 0, 1, 3, s0) SW_MBLKS(5, 1, 0, 3, s1, 4) SW_MBLK(6, 0, 1, 4, s0)
-                SW_MBLKS(7, 1, 0, 4, s1, 6) SW_MBLK(8, 0, 1, 5, s0) SW_MBLKS(9, 1, 0, 5, s1, 8)
-                    SW_MBLK(10, 0, 1, 6, s0) SW_MBLKS(11, 1, 0, 6, s1, 10) SW_MBLK(12, 0, 1, 7, s0)
-                        SW_MBLKS(13, 1, 0, 7, s1, 12) SW_MBLKN(14, 0, 1) SW_MLAST(15, 1, 14)
-        : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
-          SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), [s] "+v"(S), [lmin] "+v"(lmin),
-          [f] "+v"(F), [d0] "=&v"(d0), [d1] "=&v"(d1), [hgo] "=&v"(hgo), [es] "=&v"(es), [fs] "=&v"(fs),
-          [sm] "=&v"(sm)
-        : [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge), SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5),
-          SW_AB(6), SW_AB(7), [s0] "s"(s0), [s1] "s"(s1));
+    if constexpr (R == 16) {
+        asm(SW_PRO SW_MBLK(0, 0, 1, 1, s0) SW_MBLKS(1, 1, 0, 1, s1, 0) SW_MBLK(2, 0, 1, 2, s0)
+                SW_MBLKS(3, 1, 0, 2, s1, 2) SW_MBLK(4, 0, 1, 3, s0) SW_MBLKS(5, 1, 0, 3, s1, 4) SW_MBLK(6, 0, 1, 4, s0)
+                    SW_MBLKS(7, 1, 0, 4, s1, 6) SW_MBLK(8, 0, 1, 5, s0) SW_MBLKS(9, 1, 0, 5, s1, 8)
+                        SW_MBLK(10, 0, 1, 6, s0) SW_MBLKS(11, 1, 0, 6, s1, 10) SW_MBLK(12, 0, 1, 7, s0)
+                            SW_MBLKS(13, 1, 0, 7, s1, 12) SW_MBLKN(14, 0, 1) SW_MLAST(15, 1, 14)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
+              SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_MOUTS
+            : SW_MINS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5), SW_AB(6), SW_AB(7));
+    } else if constexpr (R == 8) {
+        asm(SW_PRO SW_MBLK(0, 0, 1, 1, s0) SW_MBLKS(1, 1, 0, 1, s1, 0) SW_MBLK(2, 0, 1, 2, s0)
+                SW_MBLKS(3, 1, 0, 2, s1, 2) SW_MBLK(4, 0, 1, 3, s0) SW_MBLKS(5, 1, 0, 3, s1, 4) SW_MBLKN(6, 0, 1)
+                    SW_MLAST(7, 1, 6)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_MOUTS
+            : SW_MINS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3));
+    } else {
+        static_assert(R == 4, "rows per lane must be 4, 8 or 16");
+        asm(SW_PRO SW_MBLK(0, 0, 1, 1, s0) SW_MBLKS(1, 1, 0, 1, s1, 0) SW_MBLKN(2, 0, 1) SW_MLAST(3, 1, 2)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_MOUTS
+            : SW_MINS, SW_AB(0), SW_AB(1));
+    }
 }
 
 // ------------------------------------------------------------ one pass of one wave
@@ -424,6 +438,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     RV rr = resid(c0, c1);
     uint32_t cur[R];
     fetch<R, PACKED>(lrow, rr, 0, cur);
+#pragma unroll 2
     for (int c = 0; c < nloop; ++c) {
         const RV c3 = res_at(coff + c + 3);
         uint4 nw[W];
@@ -517,7 +532,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     }
 }
 
-// End-to-end modes in 16-bit cells (subject pairs, 16 rows per lane).  Values
+// End-to-end modes in 16-bit cells (subject pairs, R rows per lane).  Values
 // carry the bias ec.bias (the middle of the 16-bit range), so that
 // H = max(hd, E, F) is one v_pk_maximum3_f16 as in the local sweep; there is
 // no floor, and a subtraction that saturates at 0 only stands for a value
@@ -533,10 +548,9 @@ __device__ __forceinline__ short usub16(short v, int g) {
     return (short)(x < 0 ? 0 : x);
 }
 
-template <bool COOP, int MODE>
+template <int R, bool COOP, int MODE>
 __device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, int B, int b, const int16_t* lrow,
                                                   u2 go, u2 ge, s2& S, s2& lmin, s2& lmax, const EndCtx& ec) {
-    constexpr int R = 16;
     using C = CellI16;
     using T = s2;
     using RV = Res<false>::V;
@@ -598,7 +612,7 @@ __device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, i
             T F = ftop;
             // a cooperating lane starts b steps late and keeps the border until its first column (the
             // asm block runs under the lane mask)
-            if (!COOP || col >= 0) rows16_pair_mode(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge);
+            if (!COOP || col >= 0) rows16_pair_mode<R>(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge);
             if (cap) {
                 T hc = H[0];
 #pragma unroll
@@ -750,7 +764,6 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         // the lane holding the query's last row starts S at H[m][0] where that counts
         const bool cap = (m - 1 - (passes - 1) * rows_pp) / R == b;
         if constexpr (kMode16) {
-            static_assert(R == 16, "16-bit end-to-end sweeps use 16 rows per lane");
             ec.bias = a.bias;
             const short hm = ec.enc(ec.border(m));
             S = T{cap && (MODE == 2 || ec.na == 0) ? hm : (short)0, cap && (MODE == 2 || ec.nb == 0) ? hm : (short)0};
@@ -797,9 +810,9 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
             ec.last = p == passes - 1;
             if constexpr (kMode16) {
                 if (lgB == 0)
-                    sweep_pass_mode16<false, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
+                    sweep_pass_mode16<R, false, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
                 else
-                    sweep_pass_mode16<true, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
+                    sweep_pass_mode16<R, true, MODE>(io, ncols, B, b, lrow, go, ge, S, lmin, lmax, ec);
             } else {
                 if (lgB == 0)
                     sweep_pass<C, R, false, PACKED, MODE>(io, ncols, B, b, lrow, go, ge, S, bias, ec);
@@ -1140,35 +1153,43 @@ hipError_t launch_sweep(bool i16, int R, const SweepArgs& a, int grid, hipStream
 }
 
 // Global (mode 1) and semi-global (mode 2) sweeps: 32-bit cells, R = 8.
-static const void* mode_kernel(int mode) {
+static const void* mode_kernel(int mode, int R) {
+    if (R != 8) return nullptr;
     if (mode == 1) return (const void*)k_sweep<CellI32, 8, 1>;
     if (mode == 2) return (const void*)k_sweep<CellI32, 8, 2>;
     return nullptr;
 }
 
-static const void* mode16_kernel(int mode) {
-    if (mode == 1) return (const void*)k_sweep<CellI16, 16, 1>;
-    if (mode == 2) return (const void*)k_sweep<CellI16, 16, 2>;
+static const void* mode16_kernel(int mode, int R) {
+    if (mode == 1)
+        return R == 16 ? (const void*)k_sweep<CellI16, 16, 1>
+             : R == 8  ? (const void*)k_sweep<CellI16, 8, 1>
+             : R == 4  ? (const void*)k_sweep<CellI16, 4, 1> : nullptr;
+    if (mode == 2)
+        return R == 16 ? (const void*)k_sweep<CellI16, 16, 2>
+             : R == 8  ? (const void*)k_sweep<CellI16, 8, 2>
+             : R == 4  ? (const void*)k_sweep<CellI16, 4, 2> : nullptr;
     return nullptr;
 }
 
-// End-to-end modes in 16-bit cells (16 rows per lane); out-of-range pairs go to the rerun list.
-hipError_t launch_sweep_mode16(int mode, const SweepArgs& a, int grid, hipStream_t st) {
-    const void* k = mode16_kernel(mode);
+// End-to-end modes in 16-bit cells (R = 16, 8 or 4 rows per lane); out-of-range pairs go to the rerun list.
+hipError_t launch_sweep_mode16(int mode, int R, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = mode16_kernel(mode, R);
     if (!k) return hipErrorInvalidValue;
     SweepArgs copy = a;
     void* args[] = {&copy};
     return hipLaunchKernel(k, dim3(grid), dim3(64 * kWaves), args, 0, st);
 }
 
-hipError_t sweep_occupancy_mode16(int mode, int* blocks_per_cu) {
-    const void* k = mode16_kernel(mode);
+hipError_t sweep_occupancy_mode16(int mode, int R, int* blocks_per_cu) {
+    const void* k = mode16_kernel(mode, R);
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * kWaves, 0);
 }
 
-hipError_t launch_sweep_mode(int mode, const SweepArgs& a, int grid, hipStream_t st) {
-    const void* k = mode_kernel(mode);
+// End-to-end modes in 32-bit cells (8 rows per lane).
+hipError_t launch_sweep_mode(int mode, int R, const SweepArgs& a, int grid, hipStream_t st) {
+    const void* k = mode_kernel(mode, R);
     if (!k) return hipErrorInvalidValue;
     SweepArgs copy = a;
     void* args[] = {&copy};

@@ -106,20 +106,26 @@ def test_mode_range_and_argument_errors(gpu, blosum):
 
 @pytest.mark.parametrize("mode", ["global", "semiglobal"])
 def test_mode_scores_beyond_the_16bit_range(gpu, blosum, mode):
-    """16-bit end-to-end cells hold values within about +-15,700 of the middle of
-    their range: a 22,000-point self alignment leaves it and goes to the 32-bit
-    recompute, exactly."""
+    """Global 16-bit cells hold values within about +-15,700 of the middle of
+    their range; semi-global cells start just above the lowest value the query
+    allows (-(Go + (m - 1) Ge)) and reach higher.  A 33,000-point self alignment
+    leaves either range, a 22,000-point one only the global range; both go to the
+    32-bit recompute, exactly."""
     W = 17
     rng = np.random.default_rng(44)
-    subs = [np.full(2000, W, np.int8), np.concatenate([np.full(1000, W, np.int8), synth.background_residues(rng, 300)])]
+    subs = [np.full(3000, W, np.int8), np.concatenate([np.full(1000, W, np.int8), synth.background_residues(rng, 300)])]
     subs += [synth.background_residues(rng, int(L)) for L in rng.integers(1, 600, 60)]
     offs = np.zeros(len(subs) + 1, np.int64)
     offs[1:] = np.cumsum([s.size for s in subs])
     db = synth.Database(np.concatenate(subs), offs)
     D = gpu.Database(db.residues, db.offsets)
-    q = np.full(2000, W, np.int8)
-    _check(gpu, D, db, q, blosum, 10, 2, mode, f"{mode} W-run")
+    _check(gpu, D, db, np.full(3000, W, np.int8), blosum, 10, 2, mode, f"{mode} W-run 3000")
     assert D.stats()["rerun_pairs"] >= 1
+    _check(gpu, D, db, np.full(2000, W, np.int8), blosum, 10, 2, mode, f"{mode} W-run 2000")
+    if mode == "global":
+        assert D.stats()["rerun_pairs"] >= 1
+    else:
+        assert D.stats()["rerun_pairs"] == 0
     _check(gpu, D, db, synth.small_query(seed=45, m=300), blosum, 10, 2, mode, f"{mode} short query")
     D.close()
 
@@ -149,9 +155,32 @@ def test_modes_with_the_longest_group_in_32bit_cells(gpu, blosum, mode):
     offs[1:] = np.cumsum(lens)
     db = synth.Database(np.concatenate(subs), offs)
     D = gpu.Database(db.residues, db.offsets)
-    for m in (90, 700):
+    for m in (90, 700, 900):
         _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, 10, 2, mode, f"{mode} m={m}")
         st = D.stats()
-        assert st["items"] > 0
-        assert (st["side_items"] > 0) == (mode == "global")
+        assert st["items"] + st["side_items"] > 0
+        if mode == "global":
+            assert st["side_items"] > 0
+    D.close()
+
+
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+def test_modes_short_queries_with_long_pairs_beside(gpu, blosum, mode):
+    """A short query against a few long subjects: the long pairs run at 4 or 8
+    rows per lane on a side stream beside the 16-row launch (a 64-lane pass of
+    16 rows would be mostly padding); the scores do not change."""
+    rng = np.random.default_rng(47)
+    lens = [6000, 5000, 4000, 3500] + list(rng.integers(1, 400, 600))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    rows = set()
+    for m in (1, 30, 100, 300, 600):
+        _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, 10, 2, mode, f"{mode} m={m}")
+        st = D.stats()
+        if st["side_items"] > 0:
+            rows.add(st["side_rows_per_lane"])
+    assert rows and rows <= {4, 8}, rows
     D.close()
