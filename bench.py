@@ -274,7 +274,7 @@ def main():
                          "(one request at a time, least remaining work first at every chunk boundary)")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--mode", default="local", choices=["local", "global", "semiglobal"],
-                    help="plain form: alignment mode (global and semi-global run in 32-bit cells)")
+                    help="plain form: alignment mode (global and semi-global run in biased 16-bit cells, exact)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched-compare", action="store_true",
