@@ -80,7 +80,7 @@ def measured_traffic(args):
     return d.get("hbm_bytes_per_launch_avg")
 
 
-def cpu_baseline(queries, db, sm, seconds: float):
+def cpu_baseline(queries, db, sm, seconds: float, mode: str = "local"):
     """The oracle, as it stands, on the host cores: the queries in order, each
     against consecutive blocks of subjects, until about ``seconds`` of work."""
     import oracle
@@ -94,7 +94,7 @@ def cpu_baseline(queries, db, sm, seconds: float):
             done = 0
             while done < db.n and time.perf_counter() - t0 < limit:
                 idx = np.arange(done, min(db.n, done + blk), dtype=np.int64)
-                oracle.scores(q, db.residues, db.offsets, sm, 10, 2, idx=idx, threads=nthreads)
+                oracle.scores(q, db.residues, db.offsets, sm, 10, 2, idx=idx, threads=nthreads, mode=mode)
                 cells += int(q.size) * int(lengths[idx].sum())
                 done += idx.size
             if done:
@@ -212,6 +212,9 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     print(json.dumps(res), flush=True)
 
 
+ALIGN_CELL_OPS = 9
+
+
 def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
     """Alignment form: search each query, then align the top 10 of every query
     in one sw_align_batch call per step; one sw_align call per query is timed
@@ -239,6 +242,21 @@ def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
     el1 = time.perf_counter() - t1
     same = all(D.align(q, t, sm, 10, 2) == a for q, t, a in zip(queries[:3], tops[:3], al[:3]))
     n_al = len(queries) * 10
+    # The fill sweeps Eq. 1-3 in int32 lanes: 9 operations per cell (diagonal add, three-input maximum
+    # and the floor for H, H - Go shared by E and F, two extension subtractions, two maxima, the running
+    # maximum); the direction byte it also records is not counted.  One workgroup holds one pair, so a
+    # call lasts as long as its longest pair on one CU: the whole-chip fraction is small by construction,
+    # and the longest pair's own rate is given against one CU.
+    call_s = el / args.steps
+    longest = max(int(q.size) * int(lens[k]) for q, t in zip(queries, tops) for k in t)
+    peak_chip = perfmodel.int_valu_lane_ops_per_s()
+    peak_cu = peak_chip / perfmodel.MI355X_CUS
+    achieved = ALIGN_CELL_OPS * cells / call_s
+    roof = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(peak_chip / 1e12, 3),
+            "unit": "TOP/s (int32 lane-ops)", "frac": round(achieved / peak_chip, 4), "traffic": None,
+            "kernel": "k_align_fill + k_align_trace (one call)", "ops_per_cell": ALIGN_CELL_OPS,
+            "longest_pair": {"cells": longest, "gcups_on_its_cu": round(longest / call_s / 1e9, 3),
+                             "frac_of_one_cu": round(ALIGN_CELL_OPS * longest / call_s / peak_cu, 4)}}
     res = {
         "metric": "GCUPS of the traceback (top-10 alignments per query)", "value": round(cells * args.steps / el / 1e9, 2),
         "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -251,9 +269,35 @@ def align_bench(args, sw, D, queries, db, sm, total_res, perfmodel):
                   "one_call_per_query": {"gcups": round(cells / el1 / 1e9, 2), "ms": round(el1 * 1e3, 3)},
                   "batch_equals_per_query": same,
                   "last_alignment": {k: al[-1][-1][k] for k in ("score", "q_begin", "q_end", "s_begin", "s_end")}},
+        "roofline": roof,
     }
     D.close()
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_align_baseline(queries, tops, db, sm, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def cpu_align_baseline(queries, tops, db, sm, seconds: float):
+    """The oracle's alignment, as it stands, on the host cores (one pair per
+    thread; the C call runs outside the interpreter lock): the same pairs in
+    query order until about ``seconds`` of work."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    threads = host_cores()
+    pairs = [(q, int(k)) for q, t in zip(queries, tops) for k in t]
+    cells, done, t0 = 0, 0, time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        while done < len(pairs) and time.perf_counter() - t0 < seconds:
+            batch = pairs[done:done + threads]
+            subj = [db.residues[db.offsets[k]:db.offsets[k + 1]] for _, k in batch]
+            list(pool.map(lambda a: oracle.align(a[0], a[1], sm, 10, 2), [(q, d) for (q, _), d in zip(batch, subj)]))
+            cells += sum(int(q.size) * int(d.size) for (q, _), d in zip(batch, subj))
+            done += len(batch)
+    dt = time.perf_counter() - t0
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"the first {done} of the {len(pairs)} (query, subject) pairs in query order: "
+                      f"{cells:.3e} cells in {dt:.1f} s"}
 
 
 def main():
@@ -429,9 +473,9 @@ def main():
         res["extra"]["batched_same_queries"] = {"gcups": round(bg, 2), "gain_vs_plain": round(bg / gcups, 3),
                                                 "ms_per_step": round((tb1 - tb0) / args.steps * 1e3, 3),
                                                 "knobs": tb["knobs"], "scores_equal_plain": same}
-    if not args.no_cpu_baseline and args.mode == "local":
+    if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(queries, db, sm, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(queries, db, sm, args.cpu_seconds, mode=args.mode)
     D.close()
     print(json.dumps(res), flush=True)
 

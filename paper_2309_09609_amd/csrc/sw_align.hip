@@ -40,6 +40,8 @@
 
 #include <stdint.h>
 
+#include <climits>
+
 #include <algorithm>
 
 #include "sw_internal.h"
@@ -74,9 +76,18 @@ __device__ __forceinline__ align_rsrc align_buffer(const void* base, uint32_t by
 
 // Residues arrive 4 columns per dword two chunks ahead and the boundary row
 // one iteration ahead, so no step waits for memory.  Dynamic LDS: the query
-// profile of each wave's band, prof[d][row] with the rows of lane b at bytes
-// 4b .. 4b + 3 of each residue row (W * A * 256 bytes), built from a copy of
-// the substitution matrix in LDS.
+// profile of each wave's band, prof[c][row] for image byte c (0 = padding,
+// 1..A = residue c - 1) with the rows of lane b at bytes 4b .. 4b + 3 of each
+// row (W * (A + 1) * 256 bytes), built from a copy of the substitution matrix
+// in LDS.  Padding scores -128.
+// Every lane computes every step, also before its first column and past the
+// last: there the diagonal term is H + (-128) from a zero border, so H stays
+// 0 before the first column, and E may drift below 0 -- such E (and F) never
+// lie on an alignment's path, which only follows positive values.  Cells past
+// the last column feed no real cell (those depend only on cells to their left
+// and above); they may start from stale boundary words of a padding column
+// and are never taken as the end cell.  Only the direction stores past the
+// band's steps and the bottom-row stores are guarded.
 // A pair with fewer bands than the workgroup has waves leaves the other waves
 // idle (they still take part in every barrier).
 __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair* pairs, const int8_t* subst, int A,
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     const int b = threadIdx.x & 63;
     const int8_t* query = P.query;
     const int m = P.m;
-    int8_t* prof = align_lds + wave * (A * kAlignPass);
+    int8_t* prof = align_lds + wave * ((A + 1) * kAlignPass);
     for (int e = threadIdx.x; e < A * A; e += blockDim.x) sm[e] = subst[e];
     __syncthreads();
     const int n = P.n;
@@ -132,16 +143,24 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
         if (p >= 0 && c == 0) {
             row0 = p * kAlignPass + b * kAlignRows;
 #pragma unroll
-            for (int r = 0; r < kAlignRows; ++r) { valid[r] = row0 + r < m; H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
+            // rows past the query never become the best (their running maximum starts above every score)
+            for (int r = 0; r < kAlignRows; ++r) {
+                valid[r] = row0 + r < m;
+                H[r] = 0;
+                E[r] = 0;
+                bs[r] = valid[r] ? 0 : INT_MAX;
+                bj[r] = 0;
+            }
             int qa[kAlignRows];                 // matrix row offset of each query row, -1 past the query
 #pragma unroll
             for (int r = 0; r < kAlignRows; ++r) qa[r] = valid[r] ? query[row0 + r] * A : -1;
+            *reinterpret_cast<uint32_t*>(prof + 4 * b) = 0x80808080u;          // padding: -128 on every row
             for (int d = 0; d < A; ++d) {
                 uint32_t v = 0;
 #pragma unroll
                 for (int r = 0; r < kAlignRows; ++r)
                     if (qa[r] >= 0) v |= (uint32_t)(uint8_t)sm[qa[r] + d] << (8 * r);
-                *reinterpret_cast<uint32_t*>(prof + d * kAlignPass + 4 * b) = v;
+                *reinterpret_cast<uint32_t*>(prof + (d + 1) * kAlignPass + 4 * b) = v;
             }
             diag_top = 0;
             up_h = 0;
@@ -167,41 +186,39 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
                 for (int u = 0; u < 4; ++u) {
                     const int t = 4 * it + u;
                     const int j = t - b + 1;    // 1-based column of this lane
-                    const bool active = j >= 1 && j <= n;
                     const int htop = b == 0 ? th[u] : up_h;
                     const int ftop = b == 0 ? tf[u] : up_f;
-                    int hbot = 0, fbot = 0;
-                    if (active) {
-                        const int d = (int)((rr >> (8 * u)) & 0xffu) - 1;
-                        const uint32_t sv = *reinterpret_cast<const uint32_t*>(prof + d * kAlignPass + 4 * b);
-                        int dg = diag_top, hu = htop, fu = ftop;
-                        uint32_t bits = 0;
+                    const int d = (int)((rr >> (8 * u)) & 0xffu);
+                    const uint32_t sv = *reinterpret_cast<const uint32_t*>(prof + d * kAlignPass + 4 * b);
+                    int dg = diag_top, hu = htop, fu = ftop;
+                    uint32_t bits = 0;
+                    const bool real = j <= n;   // columns past the subject may read stale boundary words
 #pragma unroll
-                        for (int r = 0; r < kAlignRows; ++r) {
-                            const int hl = H[r];                         // H[i][j-1]
-                            const int eo = hl - go, ee = E[r] - ge;
-                            const int e = max(eo, ee);                   // Eq. 2
-                            const int fo = hu - go, fe = fu - ge;
-                            const int f = max(fo, fe);                   // Eq. 3
-                            const int hd = dg + (int)(int8_t)(sv >> (8 * r));
-                            const int h = max(max(hd, e), max(f, 0));    // Eq. 1
-                            const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
-                            bits |= (src | (e == eo ? 4u : 0u) | (f == fo ? 8u : 0u)) << (8 * r);
-                            if (valid[r] && h > bs[r]) { bs[r] = h; bj[r] = j; }
-                            dg = hl;
-                            H[r] = h;
-                            E[r] = e;
-                            hu = h;
-                            fu = f;
-                        }
-                        dir[((int64_t)p * nsteps + t) * 64 + b] = bits;
-                        hbot = hu;
-                        fbot = fu;
-                        if (b == 63 && p + 1 < passes) { bh[j - 1] = hbot; bf[j - 1] = fbot; }
+                    for (int r = 0; r < kAlignRows; ++r) {
+                        const int hl = H[r];                         // H[i][j-1]
+                        const int eo = hl - go, ee = E[r] - ge;
+                        const int e = max(eo, ee);                   // Eq. 2
+                        const int fo = hu - go, fe = fu - ge;
+                        const int f = max(fo, fe);                   // Eq. 3
+                        const int hd = dg + (int)(int8_t)(sv >> (8 * r));
+                        const int h = max(max(hd, e), max(f, 0));    // Eq. 1
+                        const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
+                        bits |= (src | (eo >= ee ? 4u : 0u) | (fo >= fe ? 8u : 0u)) << (8 * r);
+                        if (real && h > bs[r]) { bs[r] = h; bj[r] = j; }
+                        dg = hl;
+                        H[r] = h;
+                        E[r] = e;
+                        hu = h;
+                        fu = f;
                     }
+                    if (t < nsteps) dir[((int64_t)p * nsteps + t) * 64 + b] = bits;   // t is the same in every lane
+                    // the last lane hands the band's bottom row to the next band (columns 1..n4 only)
+                    const uint32_t bo = (b == 63 && p + 1 < passes) ? (uint32_t)(j - 1) * 4u : 0x80000000u;
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)hu, bhr, bo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)fu, bfr, bo, 0, 0);
                     diag_top = htop;
-                    up_h = (int)align_shr1((uint32_t)hbot);
-                    up_f = (int)align_shr1((uint32_t)fbot);
+                    up_h = (int)align_shr1((uint32_t)hu);
+                    up_f = (int)align_shr1((uint32_t)fu);
                 }
                 lo = hi;
                 hi = nx;
@@ -214,7 +231,11 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
                 int sc = 0, ci = 0, cj = 0;
 #pragma unroll
                 for (int r = 0; r < kAlignRows; ++r)
-                    if (bs[r] > 0 && end_before(bs[r], row0 + r + 1, bj[r], sc, ci, cj)) { sc = bs[r]; ci = row0 + r + 1; cj = bj[r]; }
+                    if (valid[r] && bs[r] > 0 && end_before(bs[r], row0 + r + 1, bj[r], sc, ci, cj)) {
+                        sc = bs[r];
+                        ci = row0 + r + 1;
+                        cj = bj[r];
+                    }
                 for (int o = 1; o < 64; o <<= 1) {
                     const int s2 = __shfl_xor(sc, o, 64), i2 = __shfl_xor(ci, o, 64), j2 = __shfl_xor(cj, o, 64);
                     if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
@@ -364,7 +385,7 @@ hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t*
                         uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
                         int lds_max, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    const size_t lds = (size_t)W * A * kAlignPass;
+    const size_t lds = (size_t)W * (A + 1) * kAlignPass;
     if (W < 1 || W > kAlignWaves || lds + kFillStaticLds > (size_t)lds_max) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, subst, A, go, ge, dirs, bnd, best);
     hipError_t e = hipGetLastError();
@@ -374,10 +395,10 @@ hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t*
 }
 
 // Waves per pair: one per band of 256 query rows, up to 16, with the bands'
-// profiles (A x 256 bytes each) and the kernel's own LDS within lds_max.
+// profiles ((A + 1) x 256 bytes each) and the kernel's own LDS within lds_max.
 int align_waves(int m, int A, int lds_max) {
     const int passes = (m + kAlignPass - 1) / kAlignPass;
-    const int fit = (lds_max - kFillStaticLds) / (A * kAlignPass);
+    const int fit = (lds_max - kFillStaticLds) / ((A + 1) * kAlignPass);
     return std::max(1, std::min(std::min(passes, kAlignWaves), fit));
 }
 
