@@ -11,12 +11,12 @@
 // 4 consecutive rows and at step t updates column j = t - b + 1 (1-based), so
 // the 64 lanes form an anti-diagonal wavefront and the bottom row of lane b
 // reaches lane b+1 through a DPP shift.  Band k goes to wave k mod W, and the
-// bands run as a pipeline: band k processes its 128-step stages k*L, k*L + 1,
-// ... with L >= 2 stages of lag behind band k-1, whose bottom row (H and F per
-// column, in a per-pair row buffer) it reads; a workgroup barrier ends every
-// stage.  Lag 2 covers the 64 steps a column needs to cross a band plus one
-// step of read-ahead; L >= (stages per band) / W keeps a wave from being
-// needed by two bands at once.  The 4 direction bytes a lane produces per
+// bands run as a pipeline of 128-step stages: band k starts 2 stages after
+// band k-1, whose bottom row (H and F per column, in a per-pair row buffer) it
+// reads, and every W-th band waits max(0, nch - 2W) stages more (nch = stages
+// per band) so that its wave has finished its previous band; a workgroup
+// barrier ends every stage.  Lag 2 covers the 64 steps a column needs to
+// cross a band plus one step of read-ahead.  The 4 direction bytes a lane produces per
 // step form one dword, and the 64 lanes write 256 consecutive bytes per
 // step: byte (band p, step t, lane b, row r) at ((p * (n + 63) + t) * 64 + b)
 // * 4 + r.
@@ -116,8 +116,11 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     const int nsteps = n + 63;
     const int nloop = (nsteps + 3) >> 2;
     const int nch = (nloop + kAlignStage - 1) / kAlignStage;     // stages per band
-    const int L = max(2, (nch + W - 1) / W);                      // lag between consecutive bands
-    const int nstages = (passes - 1) * L + nch;
+    // band k starts at stage 2k + (k / W) * D: two stages after band k-1, and every W-th band D stages
+    // later still, so that its wave has finished the band before (a wave's bands start max(2W, nch) apart)
+    const int D = max(0, nch - 2 * W);
+    const int period = 2 * W + D;
+    const int nstages = 2 * (passes - 1) + ((passes - 1) / W) * D + nch;
     const int coff = (-b) >> 2, csh = (-b) & 3;  // lane b works on 0-based columns 4c - b .. 4c - b + 3 in iteration c
     auto chunk = [&](int c) { return __builtin_amdgcn_raw_buffer_load_b32(img, (uint32_t)(c * kChunkBytes), 0, 0); };
     int best_s = 0, best_i = 0, best_j = 0;     // wave-uniform after each band
@@ -133,11 +136,12 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
 #pragma unroll
     for (int r = 0; r < kAlignRows; ++r) { valid[r] = false; H[r] = 0; E[r] = 0; bs[r] = 0; bj[r] = 0; }
     for (int s = 0; s < nstages; ++s) {
-        // the band of this wave in stage s, if any: bands wave, wave + W, ... start every W * L stages
+        // the band of this wave in stage s, if any: bands wave, wave + W, ... start at 2 wave + i period
         int p = -1, c = 0;
-        if (wave < W && s >= wave * L) {
-            const int kk = wave + (s - wave * L) / (W * L) * W;
-            const int cc = s - kk * L;
+        if (wave < W && s >= 2 * wave) {
+            const int i = (s - 2 * wave) / period;
+            const int kk = wave + i * W;
+            const int cc = s - (2 * wave + i * period);
             if (kk < passes && cc < nch) { p = kk; c = cc; }
         }
         if (p >= 0 && c == 0) {
