@@ -516,6 +516,13 @@ sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
 
 sw_status ensure_workspace(sw_db* db) {
     if (db->wg16 == 0) {
+        // a failure part way leaves wg16 at 0, so the next call sets up again (streams and events are
+        // created once; buffers only grow)
+        struct Undo {
+            sw_db* d;
+            bool done = false;
+            ~Undo() { if (!done) d->wg16 = 0; }
+        } undo{db};
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, db->device));
         db->cus = prop.multiProcessorCount;
@@ -546,13 +553,14 @@ sw_status ensure_workspace(sw_db* db) {
         HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4, &db->gen));
         HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4, &db->gen));
         HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t), &db->gen));
-        HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
-        HIP_TRY(hipStreamCreateWithFlags(&db->side2, hipStreamNonBlocking));
-        HIP_TRY(hipStreamCreateWithFlags(&db->cap, hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&db->ev_join2, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
+        if (!db->side) HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
+        if (!db->side2) HIP_TRY(hipStreamCreateWithFlags(&db->side2, hipStreamNonBlocking));
+        if (!db->cap) HIP_TRY(hipStreamCreateWithFlags(&db->cap, hipStreamNonBlocking));
+        if (!db->ev_fork) HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
+        if (!db->ev_join) HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
+        if (!db->ev_join2) HIP_TRY(hipEventCreateWithFlags(&db->ev_join2, hipEventDisableTiming));
+        if (!db->hstage.done) HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
+        undo.done = true;
     }
     return SW_OK;
 }
