@@ -438,7 +438,6 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     RV rr = resid(c0, c1);
     uint32_t cur[R];
     fetch<R, PACKED>(lrow, rr, 0, cur);
-#pragma unroll 2
     for (int c = 0; c < nloop; ++c) {
         const RV c3 = res_at(coff + c + 3);
         uint4 nw[W];
