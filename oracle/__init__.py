@@ -101,6 +101,16 @@ def pair_mode(q, d, sm, go: int, ge: int, mode: str) -> int:
     return int(v)
 
 
+def default_threads() -> int:
+    """Threads for a call that names none: the cores this process may run on,
+    at most 16 (a GPU host's share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | None = None,
            mode: str = "local") -> np.ndarray:
     """int64 scores of query ``q`` against subjects ``idx`` (default: all) of a
@@ -118,7 +128,7 @@ def scores(q, residues, offsets, sm, go: int, ge: int, idx=None, threads: int | 
     out = np.zeros(count, dtype=np.int64)
     if count == 0:
         return out
-    threads = threads or os.cpu_count() or 1
+    threads = threads or default_threads()
     rc = _load().sw_oracle_scores(q.ctypes.data, q.size, residues.ctypes.data, offsets.ctypes.data,
                                   idx_ptr, count, sm.ctypes.data, sm.shape[0], int(go), int(ge), MODES[mode],
                                   int(threads),

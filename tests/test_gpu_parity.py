@@ -435,6 +435,23 @@ def test_full_size_workload2_sampled(gpu, blosum):
     D.close()
 
 
+def test_full_size_workload2_every_score(gpu, blosum):
+    """570k-subject database, the shortest query (m = 144, 3.0e10 cells): every
+    one of the 570,000 scores, local, global and semi-global, in the launch
+    configuration the benchmark times."""
+    import torch
+    db = synth.sp570k()
+    q = synth.workload2_queries()[0]
+    D = gpu.Database(db.residues, db.offsets)
+    for mode in ("local", "global", "semiglobal"):
+        say(f"workload2 full size, every score: m={q.size} mode={mode}")
+        out = D.search(q, blosum, 10, 2, mode=mode)
+        torch.cuda.synchronize()
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2, mode=mode)
+        assert_equal_scores(out.cpu().numpy(), want, f"workload2 query 0 {mode}")
+    D.close()
+
+
 def test_extended_alphabet(gpu):
     """24-letter alphabet (B, Z, X, * after the 20 residues) with the full BLOSUM62."""
     import torch
