@@ -1227,9 +1227,12 @@ hipError_t launch_topk(const int32_t* scores, int64_t n, int64_t row_stride, int
 }
 
 // Pieces for the two-launch top-k of rows x n scores (1 = one launch).
+// Pieces of about 4,096 scores: one workgroup per piece keeps the first launch
+// spread over many CUs (a 570,000-score row takes 140), and the merge sorts
+// pieces x k candidates.
 int topk_pieces(int64_t n, int rows, int k) {
-    if (n < (int64_t)4 * kTopkThreads * 32 || rows >= 128) return 1;
-    int64_t p = (n + 32767) / 32768;
+    if (n < (int64_t)4 * kTopkThreads * 4 || rows >= 128) return 1;
+    int64_t p = (n + 4095) / 4096;
     p = std::min<int64_t>(p, std::max(1, 256 / std::max(rows, 1)));
     return (int)std::max<int64_t>(p, 1);
 }

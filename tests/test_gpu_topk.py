@@ -9,7 +9,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("n,k,spread", [(200_000, 10, 50), (1_000_003, 1, 7), (3_000_000, 1024, 300),
-                                        (10_000_000, 10, 2000), (150_000, 1024, 3), (131_071, 5, 100)])
+                                        (10_000_000, 10, 2000), (150_000, 1024, 3), (131_071, 5, 100),
+                                        (16_383, 5, 100), (16_384, 7, 30), (570_000, 10, 40)])
 def test_long_vectors(gpu, n, k, spread):
     import torch
     rng = np.random.default_rng(n + k)
