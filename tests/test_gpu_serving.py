@@ -41,7 +41,7 @@ def test_server_results_alone_and_in_mix(gpu, blosum, lane_pack):
     D = gpu.Database(db.residues, db.offsets, lane_pack=lane_pack)
     rng = np.random.default_rng(1)
     qs = [synth.small_query(seed=100 + i, m=int(m)) for i, m in enumerate(rng.integers(30, 700, 12))]
-    arrivals = np.sort(rng.uniform(0, 0.05, len(qs)))
+    arrivals = np.sort(rng.uniform(0, 0.002, len(qs)))   # close together: they share iterations
     eng = GpuEngine(D, blosum, 10, 2, k=10)
     mix = Server(eng, nchunks=4).run(qs, arrivals)
     assert mix.max_active > 1
