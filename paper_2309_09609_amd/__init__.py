@@ -333,15 +333,15 @@ def sw_align(query, handle, subjects, subst, gap_open, gap_extend, longest, stre
     sm = _square(subst)
     stride = int(q.size + longest + 1)
     out = (Alignment * max(subs.size, 1))()
-    ops = ctypes.create_string_buffer(max(subs.size, 1) * stride)
+    ops = np.empty(max(subs.size, 1) * stride, dtype=np.uint8)     # the library writes what is read back
     _check(load().sw_align(_ptr(q), int(q.size), handle, _ptr(subs), int(subs.size), _ptr(sm), int(gap_open),
-                           int(gap_extend), ctypes.cast(out, ctypes.c_void_p), ops, stride, _stream(stream)))
+                           int(gap_extend), ctypes.cast(out, ctypes.c_void_p), _ptr(ops), stride, _stream(stream)))
     res = []
-    raw = ops.raw
     for k in range(subs.size):
         a = out[k]
         res.append({"score": a.score, "q_begin": a.q_begin, "q_end": a.q_end, "subject": a.subject,
-                    "s_begin": a.s_begin, "s_end": a.s_end, "ops": raw[k * stride: k * stride + a.n_ops].decode()})
+                    "s_begin": a.s_begin, "s_end": a.s_end,
+                    "ops": ops[k * stride: k * stride + a.n_ops].tobytes().decode()})
     return res
 
 
@@ -360,18 +360,18 @@ def sw_align_batch(queries, handle, subjects, subst, gap_open, gap_extend, longe
     npairs = int(so[-1])
     stride = int(max([q.size for q in qs] or [0]) + longest + 1)
     out = (Alignment * max(npairs, 1))()
-    ops = ctypes.create_string_buffer(max(npairs, 1) * stride)
+    ops = np.empty(max(npairs, 1) * stride, dtype=np.uint8)        # the library writes what is read back
     _check(load().sw_align_batch(_ptr(cat_q), _ptr(qo), len(qs), handle, _ptr(cat_s), _ptr(so), _ptr(sm),
-                                 int(gap_open), int(gap_extend), ctypes.cast(out, ctypes.c_void_p), ops, stride,
+                                 int(gap_open), int(gap_extend), ctypes.cast(out, ctypes.c_void_p), _ptr(ops), stride,
                                  _stream(stream)))
-    raw = ops.raw
     res = []
     for q in range(len(qs)):
         row = []
         for k in range(int(so[q]), int(so[q + 1])):
             a = out[k]
             row.append({"score": a.score, "q_begin": a.q_begin, "q_end": a.q_end, "subject": a.subject,
-                        "s_begin": a.s_begin, "s_end": a.s_end, "ops": raw[k * stride: k * stride + a.n_ops].decode()})
+                        "s_begin": a.s_begin, "s_end": a.s_end,
+                        "ops": ops[k * stride: k * stride + a.n_ops].tobytes().decode()})
         res.append(row)
     return res
 
