@@ -89,7 +89,14 @@ typedef struct {
                                  ARNDCQEGHILKMFPSTWYV); up to 24 (e.g. plus B, Z, X, *).  Substitution
                                  matrices passed with this database are int8[alphabet * alphabet].
                                  Fixed at packing; sw_db_tune ignores it. */
-    int32_t reserved;
+    int32_t rerun_cap;        /* test hook: 0 = default; > 0 = at most this many flagged (query, subject
+                                 pair) entries in the recompute's list.  Pairs flagged beyond the list are
+                                 kept as one bit each and recomputed all the same, so scores never
+                                 depend on it; it exists to exercise that path. */
+    int32_t poison;           /* test hook: 1 = every flagged pair's 16-bit scores are written as
+                                 -1,000,000,007 before the recompute overwrites them, so a pair the
+                                 recompute missed would show; 0 = off. */
+    int32_t reserved;         /* 0 */
 } sw_pack_opts;
 
 /*
@@ -109,10 +116,10 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
                      const sw_pack_opts* opts, sw_stream stream, sw_db** out);
 
 /*
- * sw_db_tune - change the tuning knobs of a packed database (the force_lanes,
- * rerun_threshold, rows_per_lane and unit_share fields of opts; max_qlen is
- * ignored).  Synchronises the handle's device and drops cached plans and graphs.
- * Results are bit-identical for every setting; only speed changes.
+ * sw_db_tune - change the tuning knobs and test hooks of a packed database
+ * (every field of opts but max_qlen and alphabet).  Synchronises the handle's
+ * device and drops cached plans and graphs.  Results are bit-identical for
+ * every setting; only speed changes.
  */
 sw_status sw_db_tune(sw_db* db, const sw_pack_opts* opts);
 
@@ -288,13 +295,16 @@ const char* sw_status_str(sw_status s);
 const char* sw_last_error(void);
 
 /*
- * Execution statistics of the most recent sw_search / sw_search_batch on the
- * handle (read after the stream has completed):
- *   out[0] = work items of the bulk 16-bit launch,  out[1] = subject pairs
- *   recomputed with 32-bit cells,  out[2] = rows per lane (R) of the bulk launch,
- *   out[3] = persistent waves launched,  out[4] = work items of the side launch
- *   (long pairs of a short query),  out[5] = rows per lane of the side launch,
- *   out[6], out[7] = 0 (reserved).
+ * Execution statistics of the most recent search on the handle (read after the
+ * stream has completed):
+ *   out[0] = work items of the bulk 16-bit launch,  out[1] = (query, subject
+ *   pair) entries flagged for the 32-bit recompute (saturated or, in the
+ *   end-to-end modes, out of the exact range),  out[2] = rows per lane (R) of
+ *   the bulk launch,  out[3] = persistent waves launched,  out[4] = work items
+ *   of the side launch (long pairs of a short query),  out[5] = rows per lane
+ *   of the side launch,  out[6] = pairs the 32-bit recompute computed (equals
+ *   out[1] after every search),  out[7] = flagged pairs beyond the recompute
+ *   list's capacity (recomputed from their flag bits).
  * This call synchronises the handle's device.
  */
 sw_status sw_last_stats(sw_db* db, int64_t out[8]);

@@ -131,20 +131,20 @@ class PackOpts(ctypes.Structure):
     _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
                 ("rerun_threshold", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
                 ("unit_share", ctypes.c_int32), ("lane_pack", ctypes.c_int32), ("alphabet", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("rerun_cap", ctypes.c_int32), ("poison", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
-               unit_share=0, lane_pack=0, alphabet=0) -> ctypes.c_void_p:
+               unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0) -> ctypes.c_void_p:
     """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
-    ``alphabet`` is the residue alphabet size (0 = 20); ``force_lanes``, ``rerun_threshold`` and
-    ``rows_per_lane`` are tuning/test hooks (see sw_pack_opts)."""
+    ``alphabet`` is the residue alphabet size (0 = 20); ``force_lanes``, ``rerun_threshold``,
+    ``rows_per_lane``, ``rerun_cap`` and ``poison`` are tuning/test hooks (see sw_pack_opts)."""
     lib = load()
     offs = _host_i64(h_offsets)
     n = offs.size - 1
     h = ctypes.c_void_p()
     opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack),
-                    int(alphabet))
+                    int(alphabet), int(rerun_cap), int(poison))
     _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
                           _stream(stream), ctypes.byref(h)))
     return h
@@ -194,7 +194,7 @@ class Database:
     """A packed, device-resident protein database."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
-                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0):
+                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0):
         import torch
         self.offsets = _host_i64(offsets)
         self.n = self.offsets.size - 1
@@ -209,7 +209,7 @@ class Database:
         self.device = d_res.device
         self.alphabet = int(alphabet) if alphabet else 20
         self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
-                                 unit_share, lane_pack, alphabet)
+                                 unit_share, lane_pack, alphabet, rerun_cap, poison)
         del d_res
 
     def close(self):
@@ -232,12 +232,14 @@ class Database:
         out = np.zeros(8, dtype=np.int64)
         _check(load().sw_last_stats(self.handle, _ptr(out)))
         return {"items": int(out[0]), "rerun_pairs": int(out[1]), "rows_per_lane": int(out[2]),
-                "waves": int(out[3]), "side_items": int(out[4]), "side_rows_per_lane": int(out[5])}
+                "waves": int(out[3]), "side_items": int(out[4]), "side_rows_per_lane": int(out[5]),
+                "recomputed": int(out[6]), "rerun_overflow": int(out[7])}
 
-    def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0, lane_pack=0):
+    def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0, lane_pack=0, rerun_cap=0,
+             poison=0):
         """Change the handle's tuning knobs (results are identical for every setting)."""
         opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share),
-                        int(lane_pack))
+                        int(lane_pack), 0, int(rerun_cap), int(poison))
         _check(load().sw_db_tune(self.handle, ctypes.byref(opts)))
 
     def profile_kernels(self, enable=True):

@@ -43,7 +43,8 @@ int align_waves(int m, int A, int lds_max);
 int64_t align_dir_bytes(int m, int64_t n);
 int64_t align_bnd_words(int64_t n);
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
-                          int32_t* counters, int ncounters, int max_mp, hipStream_t st);
+                          int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words, int max_mp,
+                          hipStream_t st);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err, hipStream_t st);
@@ -191,7 +192,7 @@ struct sw_db {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     // workspace
     uint64_t gen = 1;                 // bumped on every workspace reallocation
-    DevBuf scratch16, scratch32, prof, stage, counters, rerun, scores_tmp;
+    DevBuf scratch16, scratch32, prof, stage, counters, rerun, rerun_bits, scores_tmp;
     HostPinned hstage;
     std::map<int, Plan> plans;        // plain searches: query length -> plan
     Plan batch_plan, multi_plan;
@@ -202,10 +203,13 @@ struct sw_db {
     int force_R = 0;                  // fixed rows per lane (4, 8, 16)
     double unit_share = 0.25;         // largest unit / one wave's share of a search
     int32_t sat = kSat16;             // rerun threshold
+    int64_t rerun_cap_hook = 0;       // test hook: list capacity of the recompute (0 = default)
+    int poison = 0;                   // test hook: flagged pairs' 16-bit scores read kPoison
     int lane_pack = 1;                // 1: subject pairs per lane; 2: query pairs per lane (several queries)
     int alphabet = 20;                // residue codes 0..alphabet-1; matrices are alphabet x alphabet
     // statistics and timing
     int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
+    int64_t last_cap = 0;             // list capacity of the last search's recompute
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_used;         // indices into ev_pool, in launch order
@@ -214,8 +218,11 @@ struct sw_db {
 
 namespace {
 
-// [0] bulk sweep counter, [1] rerun count, [2] rerun counter, [3] side sweep counter, [4] second side sweep counter
-constexpr int kCounters = 5;
+// [0] bulk sweep counter, [1] flagged pairs, [2] recompute work counter, [3] side sweep counter,
+// [4] second side sweep counter, [5] pairs recomputed
+constexpr int kCounters = 6;
+// Most entries of the recompute list; flagged pairs beyond it are found through their bits.
+constexpr int64_t kRerunListMax = (int64_t)1 << 20;
 constexpr int kRerunGrid = 64;
 constexpr int kRerunRows = 8;  // rows per lane of the 32-bit recompute
 constexpr int kMaxWgPerCu = 4; // persistent workgroups per CU (bounds the scratch slots)
@@ -239,11 +246,15 @@ sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
     if (rpl != 0 && rpl != 4 && rpl != 8 && rpl != 16) return fail(SW_E_INVALID, "rows_per_lane must be 0, 4, 8 or 16");
     if (opts->lane_pack < 0 || opts->lane_pack > 2) return fail(SW_E_INVALID, "lane_pack must be 0, 1 or 2");
     if (opts->unit_share < 0 || opts->unit_share > 100000) return fail(SW_E_INVALID, "unit_share must be in 0..100000");
+    if (opts->rerun_cap < 0) return fail(SW_E_INVALID, "rerun_cap must be >= 0");
+    if (opts->poison != 0 && opts->poison != 1) return fail(SW_E_INVALID, "poison must be 0 or 1");
     db->force_lgB = fl ? __builtin_ctz(fl) : -1;
     db->force_R = rpl;
     db->unit_share = opts->unit_share > 0 ? opts->unit_share / 1000.0 : 0.25;
     db->sat = opts->rerun_threshold > 0 ? std::min<int32_t>(opts->rerun_threshold, kSat16) : kSat16;
     db->lane_pack = opts->lane_pack == 2 ? 2 : 1;
+    db->rerun_cap_hook = opts->rerun_cap;
+    db->poison = opts->poison;
     return SW_OK;
 }
 
@@ -583,13 +594,57 @@ StageLayout stage_layout(const int64_t* h_qoffsets, int nq) {
     return L;
 }
 
+// Capacity of the recompute list for nq queries: a flagged (query, subject
+// pair) is appended once, so nq x pairs entries can never overflow; the list
+// stops at kRerunListMax (or the test hook's capacity) and the pairs past it
+// go through their flag bits.
+int64_t rerun_capacity(const sw_db* db, int nq) {
+    int64_t cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * std::max(nq, 1), kRerunListMax);
+    if (db->rerun_cap_hook > 0) cap = std::min<int64_t>(cap, db->rerun_cap_hook);
+    return std::max<int64_t>(cap, 1);
+}
+
+int64_t rerun_words(const sw_db* db, int nq) { return (int64_t)std::max(nq, 1) * db->ngroups * 2; }
+
 // Every device buffer a launch sequence for this input needs (may reallocate).
-sw_status reserve_for(sw_db* db, const StageLayout& L, int64_t rerun_cap) {
+sw_status reserve_for(sw_db* db, const StageLayout& L, int nq) {
     HIP_TRY(db->hstage.reserve(L.total));
     HIP_TRY(db->stage.reserve(L.total, &db->gen));
     HIP_TRY(db->prof.reserve(L.prof_elems * sizeof(int16_t), &db->gen));
-    HIP_TRY(db->rerun.reserve((size_t)rerun_cap * sizeof(WgItem), &db->gen));
+    HIP_TRY(db->rerun.reserve((size_t)rerun_capacity(db, nq) * sizeof(WgItem), &db->gen));
+    HIP_TRY(db->rerun_bits.reserve((size_t)rerun_words(db, nq) * sizeof(uint32_t), &db->gen));
     return SW_OK;
+}
+
+// The recompute fields of a 16-bit sweep's arguments (flagged pairs are listed, then set as bits).
+void set_rerun_args(sw_db* db, SweepArgs& a, int nq, int32_t* ctr) {
+    a.rerun = db->rerun.as<WgItem>();
+    a.rerun_count = ctr + 1;
+    a.rerun_cap = (int32_t)rerun_capacity(db, nq);
+    a.rerun_bits = db->rerun_bits.as<uint32_t>();
+    a.rerun_groups = db->ngroups;
+    a.rerun_words = rerun_words(db, nq);
+    a.recomputed = ctr + 5;
+    a.poison = db->poison;
+    db->last_cap = a.rerun_cap;
+}
+
+// Arguments of the 32-bit recompute that follows sweep arguments a: every listed pair, then (when the
+// list overflowed) every pair whose flag bit is set; one unit per workgroup in the 32-bit slots.
+SweepArgs recompute_args(const sw_db* db, const SweepArgs& a, int32_t* ctr) {
+    SweepArgs r = a;
+    r.items = db->rerun.as<WgItem>();
+    r.n_items_dev = ctr + 1;
+    r.n_items = a.rerun_cap;
+    r.counter = ctr + 2;
+    r.scratch = db->scratch32.as<uint32_t>();
+    r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
+    r.slot_base = 0;
+    r.rerun = nullptr;              // reads rerun_bits, appends nothing
+    r.rerun_count = nullptr;
+    r.unit_list = 1;
+    r.poison = 0;
+    return r;
 }
 
 sw_status reserve_topk(sw_db* db, int rows, int k) {
@@ -652,10 +707,10 @@ int record_timer_start(sw_db* db, hipStream_t st) {
 // bulk 16-bit sweeps, the 32-bit recompute, top-k.  Allocates nothing and never
 // waits on the host, so it can be captured into a graph.
 sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int32_t ge, int32_t* d_scores,
-                  int64_t n, int64_t rerun_cap, int k, int32_t* top_s, int64_t* top_i, hipStream_t st,
-                  bool time_sweep) {
+                  int64_t n, int k, int32_t* top_s, int64_t* top_i, hipStream_t st, bool time_sweep) {
     int32_t* ctr = db->counters.as<int32_t>();
-    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters,
+                           db->rerun_bits.as<uint32_t>(), rerun_words(db, S.nq), S.max_mp, st));
     const WgItem* d_items = plan.items.as<WgItem>();
     SweepArgs a{};
     a.items = d_items;
@@ -674,9 +729,7 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
     a.slot_words = db->slot_cap * 2;
     a.slot_base = 0;
     a.scores = d_scores;
-    a.rerun = db->rerun.as<WgItem>();
-    a.rerun_count = ctr + 1;
-    a.rerun_cap = (int32_t)rerun_cap;
+    set_rerun_args(db, a, S.nq, ctr);
     a.unit_list = 0;
     a.bias = S.bias;
     a.sat = std::min<int32_t>(db->sat + S.bias, kSat16);
@@ -709,18 +762,7 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
         db->ev_used.push_back(ev);
     }
     // exact 32-bit recompute of saturated pairs; the count is read on the device
-    SweepArgs r = a;
-    r.items = db->rerun.as<WgItem>();
-    r.n_items_dev = ctr + 1;
-    r.n_items = (int32_t)rerun_cap;
-    r.counter = ctr + 2;
-    r.scratch = db->scratch32.as<uint32_t>();
-    r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
-    r.slot_base = 0;
-    r.rerun = nullptr;
-    r.rerun_count = nullptr;
-    r.rerun_cap = 0;
-    r.unit_list = 1;
+    const SweepArgs r = recompute_args(db, a, ctr);
     HIP_TRY(launch_sweep(false, kRerunRows, r, db->wg32, st));
     if (k > 0)
         HIP_TRY(launch_topk_ws(d_scores, n, n, S.nq, k, top_s, top_i,
@@ -891,7 +933,7 @@ void sw_db_free(sw_db* db) {
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
     db->slen_sorted.release(); db->mode_plan.items.release(); db->topk_ws.release();
     db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
-    db->counters.release(); db->rerun.release(); db->scores_tmp.release();
+    db->counters.release(); db->rerun.release(); db->rerun_bits.release(); db->scores_tmp.release();
     db->hstage.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (db->side) hipStreamDestroy(db->side);
@@ -910,7 +952,7 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
     if (device_bytes)
         *device_bytes = (int64_t)(db->image.bytes + db->groups.bytes + db->perm.bytes + db->pair_cols.bytes +
                                   db->scratch16.bytes + db->scratch32.bytes + db->prof.bytes + db->stage.bytes +
-                                  db->rerun.bytes + db->scores_tmp.bytes);
+                                  db->rerun.bytes + db->rerun_bits.bytes + db->scores_tmp.bytes);
     return SW_OK;
 }
 
@@ -936,11 +978,10 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
     if ((s = get_plan(db, qlen, &plan)) != SW_OK) return s;
     const int64_t qo[2] = {0, qlen};
     const StageLayout L = stage_layout(qo, 1);
-    const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
-    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    if ((s = reserve_for(db, L, 1)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
-    return enqueue(db, S, *plan, gap_open, gap_extend, d_scores_out, n, rerun_cap, 0, nullptr, nullptr, st, true);
+    return enqueue(db, S, *plan, gap_open, gap_extend, d_scores_out, n, 0, nullptr, nullptr, st, true);
 }
 
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
@@ -1016,8 +1057,7 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
         db->batch_qlens = qlens;
     }
     const StageLayout L = stage_layout(h_qoffsets, nq);
-    const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
-    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    if ((s = reserve_for(db, L, nq)) != SW_OK) return s;
     if ((s = reserve_topk(db, nq, k)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
@@ -1030,8 +1070,8 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
         // default stream, which cannot be captured); launched on the caller's
         G.clear();
         HIP_TRY(hipStreamBeginCapture(db->cap, hipStreamCaptureModeThreadLocal));
-        s = enqueue(db, S, db->batch_plan, gap_open, gap_extend, scores, n, rerun_cap, k, d_top_scores, d_top_index,
-                    db->cap, false);
+        s = enqueue(db, S, db->batch_plan, gap_open, gap_extend, scores, n, k, d_top_scores, d_top_index, db->cap,
+                    false);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(db->cap, &graph);
         if (s != SW_OK) { if (graph) hipGraphDestroy(graph); return s; }
@@ -1092,12 +1132,11 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
     HIP_TRY(hipStreamSynchronize(st));              // the previous call may still read the plan buffer
     if ((s = build_plan(db, qlens, &db->multi_plan, &chunk, nchunks)) != SW_OK) return s;
     const StageLayout L = stage_layout(h_qoffsets, nq);
-    const int64_t rerun_cap = std::min<int64_t>((int64_t)db->ngroups * kGroupPairs * nq, (int64_t)1 << 22);
-    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    if ((s = reserve_for(db, L, nq)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, 0, st, &S, h_d_scores)) != SW_OK) return s;
     if (db->multi_plan.n_main + db->multi_plan.n_side == 0) return SW_OK;
-    return enqueue(db, S, db->multi_plan, gap_open, gap_extend, nullptr, db->n, rerun_cap, 0, nullptr, nullptr, st, true);
+    return enqueue(db, S, db->multi_plan, gap_open, gap_extend, nullptr, db->n, 0, nullptr, nullptr, st, true);
 }
 
 sw_status sw_profile_kernels(sw_db* db, int32_t enable) {
@@ -1137,8 +1176,8 @@ sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
     out[3] = (int64_t)db->last_grid * kWaves;
     out[4] = db->last_side_items;
     out[5] = db->last_side_rows;
-    out[6] = 0;
-    out[7] = 0;
+    out[6] = c[5];
+    out[7] = std::max<int64_t>(0, (int64_t)c[1] - db->last_cap);
     return SW_OK;
 }
 
@@ -1391,12 +1430,12 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     if (n_items) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * n_items, hipMemcpyHostToDevice));
     const int64_t qo[2] = {0, qlen};
     const StageLayout L = stage_layout(qo, 1);
-    const int64_t rerun_cap = (int64_t)db->ngroups * kGroupPairs;
-    if ((s = reserve_for(db, L, rerun_cap)) != SW_OK) return s;
+    if ((s = reserve_for(db, L, 1)) != SW_OK) return s;
     Staged S;
     if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
     int32_t* ctr = db->counters.as<int32_t>();
-    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters, S.max_mp, st));
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters,
+                           db->rerun_bits.as<uint32_t>(), rerun_words(db, 1), S.max_mp, st));
     SweepArgs a{};
     a.items = db->mode_plan.items.as<WgItem>();
     a.n_items = (int32_t)n16;
@@ -1413,9 +1452,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     a.slot_words = db->slot_cap * 2;
     a.slot_base = 0;
     a.scores = d_scores_out;
-    a.rerun = db->rerun.as<WgItem>();
-    a.rerun_count = ctr + 1;
-    a.rerun_cap = (int32_t)rerun_cap;
+    set_rerun_args(db, a, 1, ctr);
     a.unit_list = 0;
     // every value carries the bias; a pair whose H leaves [128, sat) is recomputed
     a.bias = bias;
@@ -1450,6 +1487,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         b.rerun = nullptr;
         b.rerun_count = nullptr;
         b.rerun_cap = 0;
+        b.poison = 0;
         b.bias = 0;
         HIP_TRY(launch_sweep_mode(mode, R32, b, std::max(1, std::min<int>(db->wg32, (int)m32.size())), db->side2));
         HIP_TRY(hipEventRecord(db->ev_join2, db->side2));
@@ -1465,17 +1503,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         db->ev_used.push_back(ev);
     }
     // exact 32-bit recompute of the pairs that left the range; the count is read on the device
-    SweepArgs r = a;
-    r.items = db->rerun.as<WgItem>();
-    r.n_items_dev = ctr + 1;
-    r.n_items = (int32_t)rerun_cap;
-    r.counter = ctr + 2;
-    r.scratch = db->scratch32.as<uint32_t>();
-    r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
-    r.rerun = nullptr;
-    r.rerun_count = nullptr;
-    r.rerun_cap = 0;
-    r.unit_list = 1;
+    SweepArgs r = recompute_args(db, a, ctr);
     r.bias = 0;
     HIP_TRY(launch_sweep_mode(mode, kRerunRows, r, db->wg32, st));
     db->last_items = (int)n16;

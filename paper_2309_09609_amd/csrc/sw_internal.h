@@ -26,6 +26,8 @@ constexpr int16_t kSat16 = 0x7C00; // 16-bit scores at or above this are recompu
 // the exact range), and a pair whose H leaves [128, kModeTop) is recomputed in 32 bits.
 constexpr int32_t kModeBias = 0x3E00;
 constexpr int32_t kModeTop = 0x7C00 - 128;
+// Test hook: what a flagged pair's 16-bit scores read until its 32-bit recompute overwrites them.
+constexpr int32_t kPoison = -0x3B9ACA07;
 
 // Packed database image, one record per group of 128 length-sorted subjects.
 // Residues of group g live at image + base, as chunk rows of kChunkBytes bytes:
@@ -76,8 +78,13 @@ struct SweepArgs {
     int32_t slot_base;            // first workgroup slot of this launch (launches share the scratch)
     int32_t* scores;
     WgItem* rerun;                // 16-bit sweep: pairs that saturated are appended here
-    int32_t* rerun_count;
-    int32_t rerun_cap;
+    int32_t* rerun_count;         // flagged (query, pair) count: appends attempted, listed or not
+    int32_t rerun_cap;            // entries of rerun[]; a flagged pair beyond it sets its bit in rerun_bits
+    uint32_t* rerun_bits;         // one bit per (query, group, pair): [q][group][2 words], zero before a search
+    int32_t rerun_groups;         // groups per query row of rerun_bits (the database's group count)
+    int64_t rerun_words;          // words of rerun_bits (queries x groups x 2)
+    int32_t* recomputed;          // 32-bit recompute: pairs recomputed (listed and from rerun_bits)
+    int32_t poison;               // test hook: a flagged pair's 16-bit scores are written as kPoison
     int32_t unit_list;            // 1: items[] holds one unit per workgroup (rerun list), 0: workgroup items
     int32_t sat;                  // 16-bit scores >= sat (biased) are recomputed with 32-bit cells
     int32_t bias;                 // 16-bit cells carry H, E, F + bias (>= minus the lowest substitution score;

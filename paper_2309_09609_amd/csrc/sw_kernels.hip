@@ -697,9 +697,13 @@ __device__ __forceinline__ void load_slice_q2(uint32_t* dst, const int16_t* pa, 
     }
 }
 
+// A flagged (query, subject pair) goes to the list while it has room and to
+// its bit in rerun_bits after that, so that none is lost however many
+// saturate; the recompute reads both.
 __device__ __forceinline__ void append_rerun(const SweepArgs& a, int g, int q, int pair) {
     const int idx = atomicAdd(a.rerun_count, 1);
     if (idx < a.rerun_cap) a.rerun[idx] = WgItem{g, q, (int16_t)pair, 6, 1, 1};
+    else atomicOr(a.rerun_bits + ((int64_t)q * a.rerun_groups + g) * 2 + (pair >> 5), 1u << (pair & 31));
 }
 
 // One unit of a wave: lane groups [k*P, (k+1)*P) of group g, all passes.
@@ -831,44 +835,61 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         out_of_range = (ra || rb) ? 1 : 0;
         for (int o = 1; o < B; o <<= 1) out_of_range |= __shfl_xor(out_of_range, o, 64);
     }
-    if (b != 0) return;
     if constexpr (PACKED) {
+        // The recompute takes subject pairs: subjects su and su ^ 1 (lane groups s and s ^ 1, B lanes
+        // apart, in the same unit since P >= 2) share one flag per query, and only the even one appends it.
+        int fa = a.rerun != nullptr && C::lo(S) >= a.sat;
+        int fb = a.rerun != nullptr && qb >= 0 && C::hi(S) >= a.sat;
+        fa |= __shfl_xor(fa, B, 64);
+        fb |= __shfl_xor(fb, B, 64);
+        if (b != 0) return;
         const int o = a.perm[g * kGroupSubjects + su];
         if (o >= 0) {
             int32_t* outa = Qa.out ? Qa.out : a.scores + Qa.out_off;
-            outa[o] = C::lo(S) - ub;
+            outa[o] = a.poison && fa ? kPoison : C::lo(S) - ub;
             if (qb >= 0) {
                 int32_t* outb = Qb.out ? Qb.out : a.scores + Qb.out_off;
-                outb[o] = C::hi(S) - ub;
+                outb[o] = a.poison && fb ? kPoison : C::hi(S) - ub;
             }
         }
-        if (a.rerun != nullptr) {
-            if (C::lo(S) >= a.sat) append_rerun(a, g, qa, su >> 1);
-            if (qb >= 0 && C::hi(S) >= a.sat) append_rerun(a, g, qb, su >> 1);
+        if ((su & 1) == 0) {
+            if (fa) append_rerun(a, g, qa, su >> 1);
+            if (fb) append_rerun(a, g, qb, su >> 1);
         }
     } else {
+        if (b != 0) return;
+        bool flag = false;                      // the pair must be recomputed with 32-bit cells
+        if (a.rerun != nullptr) flag = kMode16 ? out_of_range != 0 : (C::lo(S) >= a.sat || C::hi(S) >= a.sat);
+        const bool poisoned = flag && a.poison;
         const int slot0 = g * kGroupSubjects + 2 * su;
         const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
         int32_t* out = Qa.out ? Qa.out : a.scores + Qa.out_off;
-        if (o0 >= 0) out[o0] = C::lo(S) - ub;
-        if (o1 >= 0) out[o1] = C::hi(S) - ub;
-        if (MODE == 0 && a.rerun != nullptr && (C::lo(S) >= a.sat || C::hi(S) >= a.sat)) append_rerun(a, g, qa, su);
-        if (kMode16 && a.rerun != nullptr && out_of_range) append_rerun(a, g, qa, su);
+        if (o0 >= 0) out[o0] = poisoned ? kPoison : C::lo(S) - ub;
+        if (o1 >= 0) out[o1] = poisoned ? kPoison : C::hi(S) - ub;
+        if (flag) append_rerun(a, g, qa, su);
     }
 }
+
+// Recompute items past the list: blocks of kBitsBlock words of the flag bits.
+constexpr int kBitsBlock = 64;
 
 template <class C, int R, int MODE = 0>
 __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
     // one shared slice of up to 64*R rows, or four per-wave slices of up to 16*R rows
     __shared__ __attribute__((aligned(16))) int16_t lds[kNRes * 64 * R];
     __shared__ int s_item;
+    __shared__ uint32_t s_bits[kBitsBlock];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: buffer resources stay scalar
     const int lane = threadIdx.x & 63;
     uint32_t* slot = a.scratch + ((int64_t)(a.slot_base + blockIdx.x) * kWaves + wave) * a.slot_words;
-    int n_items = a.n_items;
+    int n_items = a.n_items, n_list = a.n_items;
     if (a.n_items_dev) {
-        const int c = min(*a.n_items_dev, a.n_items);
-        n_items = c;
+        // recompute: the flagged pairs are the list's first min(count, capacity) entries, then (when the
+        // list overflowed) every set bit of rerun_bits, read kBitsBlock words per item
+        const int c = *a.n_items_dev;
+        n_list = min(c, a.n_items);
+        n_items = n_list;
+        if (c > a.n_items) n_items += (int)((a.rerun_words + kBitsBlock - 1) / kBitsBlock);
     }
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
@@ -876,11 +897,52 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep(SweepArgs a) {
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it >= n_items) break;
+        if constexpr (std::is_same<C, CellI32>::value) {
+            if (a.unit_list) {
+                // 32-bit recompute, one unit per workgroup computed by wave 0 with the whole LDS slice: a
+                // listed pair, or every pair whose flag bit is set in a block of kBitsBlock words (all
+                // threads read the same words from LDS, so the workgroup runs the same units and barriers)
+                const bool listed = it < n_list;
+                WgItem I{};
+                int64_t w0 = 0;
+                if (listed) I = a.items[it];
+                else {
+                    w0 = (int64_t)(it - n_list) * kBitsBlock;
+                    if (threadIdx.x < kBitsBlock) {
+                        const int64_t w = w0 + threadIdx.x;
+                        s_bits[threadIdx.x] = w < a.rerun_words ? a.rerun_bits[w] : 0u;
+                    }
+                    __syncthreads();
+                }
+                int done = 0, wi = 0;
+                uint32_t v = 0;
+                for (;;) {
+                    int g, k, q;
+                    if (listed) {
+                        if (done) break;
+                        g = I.g0;
+                        k = I.k0;
+                        q = I.q;
+                    } else {
+                        while (v == 0 && wi < kBitsBlock) v = s_bits[wi++];
+                        if (v == 0) break;
+                        const int bit = __builtin_ctz(v);
+                        v &= v - 1;
+                        const int64_t w = w0 + wi - 1;
+                        q = (int)(w / (2 * (int64_t)a.rerun_groups));
+                        const int rem = (int)(w - (int64_t)q * 2 * a.rerun_groups);
+                        g = rem >> 1;
+                        k = ((rem & 1) << 5) + bit;
+                    }
+                    run_unit<C, R, false, MODE>(a, g, k, 6, q, wave == 0, true, lds, wave, lane, slot);
+                    ++done;
+                }
+                if (threadIdx.x == 0 && done) atomicAdd(a.recomputed, done);
+                continue;
+            }
+        }
         const WgItem I = a.items[it];
-        if (a.unit_list) {
-            // one unit per workgroup, computed by wave 0 with the whole LDS slice
-            run_unit<C, R, false, MODE>(a, I.g0, I.k0, I.lgB, I.q, wave == 0, true, lds, wave, lane, slot);
-        } else {
+        {
             const int B = 1 << I.lgB;
             int k = I.k0 + wave;
             const int g = I.g0 + (k >> I.lgB) * I.gstep;
@@ -926,10 +988,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
 // matrix (in a kMaxAlphabet^2-byte region) followed by the query codes.
 // Thread 0 also zeroes the launch counters (they are consumed by later kernels
 // on the same stream).
+// The blocks of query 0 also clear the recompute's flag bits.
 __global__ void k_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff,
-                          int16_t* prof, int32_t* counters, int ncounters) {
+                          int16_t* prof, int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words) {
     const int q = blockIdx.y;
     if (q == 0 && blockIdx.x == 0 && threadIdx.x < ncounters) counters[threadIdx.x] = 0;
+    if (q == 0)
+        for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nbits_words; w += (int64_t)gridDim.x * blockDim.x)
+            bits[w] = 0;
     if (q >= nq) return;
     const QDesc Q = qd[q];
     const int8_t* sm = stage;
@@ -1203,10 +1269,12 @@ hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {
 }
 
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
-                          int32_t* counters, int ncounters, int max_mp, hipStream_t st) {
-    const int bx = (int)std::min<int64_t>(((int64_t)kNRes * max_mp + 255) / 256, 1024);
+                          int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words, int max_mp,
+                          hipStream_t st) {
+    const int64_t work = std::max<int64_t>((int64_t)kNRes * max_mp, nbits_words);
+    const int bx = (int)std::min<int64_t>((work + 255) / 256, 1024);
     hipLaunchKernelGGL(k_profile, dim3(bx, std::max(nq, 1)), dim3(256), 0, st, stage, A, qd, nq, qoff, prof,
-                       counters, ncounters);
+                       counters, ncounters, bits, nbits_words);
     return hipGetLastError();
 }
 

@@ -63,5 +63,25 @@ def test_alignment_record_layout():
     assert sw.Alignment.subject.offset == 16 and sw.Alignment.n_ops.offset == 40
 
 
-def test_pack_opts_layout():
-    assert ctypes.sizeof(sw.PackOpts) == 32
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a C program compiled with gcc."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "swsearch.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct,mirror", [("sw_pack_opts", "PackOpts"), ("sw_alignment", "Alignment")])
+def test_struct_mirrors_match_the_header(tmp_path, struct, mirror):
+    cls = getattr(sw, mirror)
+    fields = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(struct, fields, tmp_path)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs
