@@ -35,12 +35,35 @@ CELL_OPS = 7.5
 MODE_CELL_OPS = 8.0
 
 
+# Oracle threads at most: a GPU host's CPU share for one GPU (the box runs other GPUs' work too).
+HOST_THREAD_CAP = 16
+
+
 def host_cores() -> int:
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    return max(1, min(n, HOST_THREAD_CAP))
+
+
+def host_report() -> dict:
+    """What the host offers (nproc, the CPUs this process may use, the CPU model) and the thread cap."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model, "thread_cap": HOST_THREAD_CAP,
+            "threads_used": host_cores(),
+            "cap_reason": "the oracle uses at most one GPU's share of the host (16 threads)"}
 
 
 def workload(name: str):
@@ -109,7 +132,7 @@ def cpu_baseline(queries, db, sm, seconds: float, mode: str = "local"):
     desc = ", ".join(f"query {qi} (m={m}) vs {done} subjects" for qi, m, done in parts)
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
             "sample": f"{desc}: {cells:.3e} cells in {dt:.1f} s",
-            "single_thread_gcups": round(cells1 / dt1 / 1e9, 4)}
+            "single_thread_gcups": round(cells1 / dt1 / 1e9, 4), "host": host_report()}
 
 
 def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
@@ -316,7 +339,7 @@ def cpu_align_baseline(queries, tops, db, sm, seconds: float):
     dt = time.perf_counter() - t0
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
             "sample": f"the first {done} of the {len(pairs)} (query, subject) pairs in query order: "
-                      f"{cells:.3e} cells in {dt:.1f} s"}
+                      f"{cells:.3e} cells in {dt:.1f} s", "host": host_report()}
 
 
 def main():

@@ -134,8 +134,11 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
  *   h_query    : host int8[qlen], residue codes (validated on the host).
  *   qlen       : >= 0; qlen == 0 gives all-zero scores.
  *   db         : packed database.
- *   h_offsets  : the offsets the database was packed with (checked against
- *                the handle: same n and same first and last offset), or NULL.
+ *   h_offsets  : the offsets the database was packed with, or NULL.  When
+ *                given they are checked against the handle (same n, same
+ *                first and last offset and the same 64-bit hash of all n + 1
+ *                values, an O(n) pass on the host): SW_E_INVALID otherwise.
+ *                NULL skips the check (the caller vouches for them).
  *   n          : number of subjects; must equal the handle's.
  *   h_subst    : host int8[A*A] substitution matrix.
  *   gap_open, gap_extend : Go, Ge >= 0.

@@ -267,11 +267,11 @@ class Database:
         subst = self.matrix(subst)
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        # the handle was packed from self.offsets: no need for the library's O(n) offsets check per call
         if mode == "local":
-            sw_search(query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out, stream)
+            sw_search(query, self.handle, None, self.n, subst, gap_open, gap_extend, out, stream)
         else:
-            sw_search_mode(MODES[mode], query, self.handle, self.offsets, self.n, subst, gap_open, gap_extend, out,
-                           stream)
+            sw_search_mode(MODES[mode], query, self.handle, None, self.n, subst, gap_open, gap_extend, out, stream)
         return out[: self.n]
 
     def align(self, query, subjects, subst, gap_open=10, gap_extend=2, stream=None):

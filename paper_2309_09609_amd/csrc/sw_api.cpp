@@ -160,6 +160,19 @@ struct GraphEntry {
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// 64-bit hash of offsets[0..n]: every value through the splitmix64 finaliser, combined with its
+// position, so a changed, moved or swapped boundary changes it.
+uint64_t offsets_hash(const int64_t* offsets, int64_t n) {
+    uint64_t h = 0x243F6A8885A308D3ull ^ (uint64_t)n;
+    for (int64_t k = 0; k <= n; ++k) {
+        uint64_t x = (uint64_t)offsets[k] + 0x9E3779B97F4A7C15ull * (uint64_t)(k + 1);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        h = (h ^ (x ^ (x >> 31))) * 0x100000001B3ull;
+    }
+    return h;
+}
+
 }  // namespace
 
 struct sw_db {
@@ -167,6 +180,7 @@ struct sw_db {
     int64_t n = 0;
     int64_t total_res = 0;
     int64_t off_first = 0, off_last = 0;
+    uint64_t off_hash = 0;            // offsets_hash of the offsets the image was packed with
     int ngroups = 0;
     std::vector<int32_t> ncols;       // per group
     std::vector<int32_t> pcols;       // per pair: longest subject of the pair, rounded up to 4
@@ -778,7 +792,8 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
 sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
     if (!db) return fail(SW_E_INVALID, "db is NULL");
     if (n != db->n) return fail(SW_E_INVALID, "n = %lld but the database holds %lld subjects", (long long)n, (long long)db->n);
-    if (h_offsets && n > 0 && (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last))
+    if (h_offsets && n > 0 &&
+        (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last || offsets_hash(h_offsets, n) != db->off_hash))
         return fail(SW_E_INVALID, "offsets do not match the packed database");
     return SW_OK;
 }
@@ -833,6 +848,7 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
     db->n = n;
     db->off_first = n > 0 ? h_offsets[0] : 0;
     db->off_last = n > 0 ? h_offsets[n] : 0;
+    db->off_hash = n > 0 ? offsets_hash(h_offsets, n) : 0;
     db->total_res = db->off_last - db->off_first;
 
     std::vector<int32_t> order(n);

@@ -27,6 +27,8 @@ def test_cpu_baseline_reports_the_oracle_rate():
     assert out["kind"] == "oracle" and out["unit"] == "GCUPS"
     assert out["value"] > 0 and out["single_thread_gcups"] > 0 and out["cores"] >= 1
     assert "query 0 (m=144)" in out["sample"]
+    host = out["host"]
+    assert host["nproc"] >= 1 and host["threads_used"] == out["cores"] <= host["thread_cap"]
     json.dumps(out)
 
 

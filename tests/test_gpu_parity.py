@@ -413,6 +413,27 @@ def test_invalid_residues_are_rejected(gpu, blosum):
     assert e.value.status == -2
 
 
+def test_offsets_must_match_the_packed_database(gpu, blosum):
+    """Offsets passed to a search are checked against the packed ones in full:
+    same endpoints but a moved interior boundary is rejected."""
+    import torch
+    qs, db = synth.workload1()
+    D = gpu.Database(db.residues, db.offsets)
+    out = torch.empty(db.n, dtype=torch.int32, device="cuda")
+    gpu.sw_search(qs[0], D.handle, db.offsets, db.n, blosum, 10, 2, out)     # the packed offsets: accepted
+    torch.cuda.synchronize()
+    assert_equal_scores(out.cpu().numpy(), oracle.scores(qs[0], db.residues, db.offsets, blosum, 10, 2), "offsets")
+    moved = db.offsets.copy()
+    moved[7] += 1
+    for bad in (moved, db.offsets[::-1].copy()):
+        with pytest.raises(gpu.SwError) as e:
+            gpu.sw_search(qs[0], D.handle, bad, db.n, blosum, 10, 2, out)
+        assert e.value.status == -1
+    with pytest.raises(gpu.SwError):
+        gpu.sw_search_mode(1, qs[0], D.handle, moved, db.n, blosum, 10, 2, out)
+    D.close()
+
+
 def test_full_size_workload2_sampled(gpu, blosum):
     """570k-subject database: every score of the sample (every 1000th subject,
     planted homologs, overflow sentinels, all subjects longer than 3,000) for the
