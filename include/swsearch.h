@@ -174,6 +174,20 @@ sw_status sw_topk_ws(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_t
                      void* d_workspace, int64_t ws_bytes, sw_stream stream);
 
 /*
+ * sw_topk_noalloc - sw_topk_ws without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops).
+ * The piece workspace is a fixed 4 MiB device array inside the library, one
+ * copy per device, held until the process ends; the call itself makes no
+ * hipMalloc, hipFree or other allocation.  Same arguments and results as
+ * sw_topk (k in 1..1024, any n), on the current device.  Calls that overlap
+ * on one device share its array and race: keep them on one stream or order
+ * them with events.  A workspace need beyond the array would be SW_E_SIZE; a
+ * row needs at most 256 pieces x k x 12 bytes + 256, so none does.
+ */
+sw_status sw_topk_noalloc(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores,
+                          int64_t* d_top_index, sw_stream stream);
+
+/*
  * sw_search_batch - scores of nq queries against every subject in one
  * persistent launch sequence (the "batched" form), plus each query's top k.
  *   h_queries  : host int8, the queries concatenated.

@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
-           "sw_search_multi", "sw_align", "sw_align_batch", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws",
+           "sw_search_multi", "sw_align", "sw_align_batch", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws", "sw_topk_noalloc",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
 _lib = None
@@ -67,6 +67,8 @@ def load():
     lib.sw_topk_ws_bytes.argtypes = [I64, I32, P]
     lib.sw_topk_ws.restype = I32
     lib.sw_topk_ws.argtypes = [P, I64, I32, P, P, P, I64, P]
+    lib.sw_topk_noalloc.restype = I32
+    lib.sw_topk_noalloc.argtypes = [P, I64, I32, P, P, P]
     lib.sw_search_mode.restype = I32
     lib.sw_search_mode.argtypes = [I32, P, I32, P, P, I64, P, I32, I32, P, P]
     lib.sw_align.restype = I32
@@ -163,6 +165,23 @@ def sw_topk(d_scores, n, k, d_top_scores, d_top_index, stream=None):
     _check(load().sw_topk(ctypes.c_void_p(d_scores.data_ptr()), int(n), int(k),
                           ctypes.c_void_p(d_top_scores.data_ptr()), ctypes.c_void_p(d_top_index.data_ptr()),
                           _stream(stream)))
+
+
+def sw_topk_ws(d_scores, n, k, d_top_scores, d_top_index, d_workspace, ws_bytes, stream=None):
+    _check(load().sw_topk_ws(_ptr(d_scores), int(n), int(k), _ptr(d_top_scores), _ptr(d_top_index),
+                             None if d_workspace is None else _ptr(d_workspace), int(ws_bytes), _stream(stream)))
+
+
+def sw_topk_ws_bytes(n, k) -> int:
+    need = ctypes.c_int64()
+    _check(load().sw_topk_ws_bytes(int(n), int(k), ctypes.byref(need)))
+    return need.value
+
+
+def sw_topk_noalloc(d_scores, n, k, d_top_scores, d_top_index, stream=None):
+    """Top k of one score vector with no allocation (the library's fixed device array)."""
+    _check(load().sw_topk_noalloc(_ptr(d_scores), int(n), int(k), _ptr(d_top_scores), _ptr(d_top_index),
+                                  _stream(stream)))
 
 
 def sw_search_batch(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, k, d_scores=None,

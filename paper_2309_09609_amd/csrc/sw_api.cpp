@@ -801,6 +801,19 @@ sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
 
 }  // namespace
 
+namespace sw {
+// Records an error for sw_last_error() from other files of the library and returns s.
+sw_status report(sw_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+}  // namespace sw
+
 // ====================================================================== C ABI
 extern "C" {
 
