@@ -33,7 +33,11 @@
  *    is what is computed for any Go, Ge >= 0).  Negative values: SW_E_INVALID.
  *  - "d_" pointers are device memory of the device that was current when the
  *    database was packed; "h_" pointers are host memory.  The caller owns every
- *    pointer it passes; the library owns the memory behind an sw_db handle.
+ *    pointer it passes.  The library allocates device memory behind an sw_db
+ *    handle only for calls that are not given it: a caller can own all of it
+ *    by packing with sw_db_pack_into and searching with sw_search_ws and
+ *    sw_search_batch_ws (sizes from sw_db_pack_bytes and
+ *    sw_batch_workspace_bytes); the handle then holds host memory only.
  *  - All work is enqueued on the given HIP stream and the call returns without
  *    waiting for it, except where stated.  Outputs are valid once the stream
  *    has completed.  Host input arrays may be reused as soon as a call returns.
@@ -116,6 +120,22 @@ sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t
                      const sw_pack_opts* opts, sw_stream stream, sw_db** out);
 
 /*
+ * sw_db_pack_bytes - device bytes of the packed image of a database with these
+ * offsets (the same for any options): the interleaved residues plus about
+ * 20 bytes per subject of tables, of which 8 per subject are used while
+ * packing only.
+ *
+ * sw_db_pack_into - sw_db_pack into a caller-owned device buffer d_db of
+ * db_bytes >= sw_db_pack_bytes (SW_E_SIZE otherwise), 256-byte aligned
+ * (SW_E_INVALID otherwise).  The handle keeps host-side tables only and never
+ * frees d_db, which must outlive the handle.
+ */
+sw_status sw_db_pack_bytes(const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts, int64_t* bytes);
+sw_status sw_db_pack_into(const int8_t* d_residues, const int64_t* h_offsets, int64_t n,
+                          const sw_pack_opts* opts, void* d_db, int64_t db_bytes, sw_stream stream,
+                          sw_db** out);
+
+/*
  * sw_db_tune - change the tuning knobs and test hooks of a packed database
  * (every field of opts but max_qlen and alphabet).  Synchronises the handle's
  * device and drops cached plans and graphs.  Results are bit-identical for
@@ -126,7 +146,8 @@ sw_status sw_db_tune(sw_db* db, const sw_pack_opts* opts);
 /* Releases the handle and its device memory (after synchronising its device). */
 void sw_db_free(sw_db* db);
 
-/* Number of subjects, total residues and device bytes held by the handle. */
+/* Number of subjects, total residues and device bytes the handle itself allocated (0 for a
+   handle packed with sw_db_pack_into and searched only through the _ws calls). */
 sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* device_bytes);
 
 /*
@@ -148,6 +169,19 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
 sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
                     int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
                     int32_t* d_scores_out, sw_stream stream);
+
+/*
+ * sw_search_ws - sw_search on a caller-owned device workspace d_workspace of
+ * ws_bytes >= sw_batch_workspace_bytes(db, {0, qlen}, 1, 0, 0) bytes,
+ * 256-byte aligned.  Allocates no device memory.  The workspace holds the
+ * boundary rows between passes, the query profile, the staged query and work
+ * items, the recompute list and counters; it must stay untouched until the
+ * stream has completed the search (and until sw_last_stats, which reads the
+ * counters from it).  Results are identical to sw_search.
+ */
+sw_status sw_search_ws(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets, int64_t n,
+                       const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out,
+                       void* d_workspace, int64_t ws_bytes, sw_stream stream);
 
 /*
  * sw_topk - the k best subjects of one score vector (Sec. II-B: alignments are
@@ -204,6 +238,27 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
                           sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
                           int32_t k, int32_t* d_scores, int32_t* d_top_scores, int64_t* d_top_index,
                           sw_stream stream);
+
+/*
+ * sw_batch_workspace_bytes - device bytes of the workspace of one search of
+ * the nq queries with offsets h_qoffsets (lengths matter, contents do not):
+ * sw_search_batch_ws with top k (0..1024), or sw_search_ws when nq == 1 and
+ * k == 0.  scores_in_ws != 0 adds room for the nq score rows, needed when the
+ * batched call is given d_scores == NULL.  Plans the batch (the plan is kept
+ * for the next call with the same lengths).
+ *
+ * sw_search_batch_ws - sw_search_batch on a caller-owned workspace of
+ * ws_bytes >= that size (SW_E_SIZE otherwise), 256-byte aligned.  Allocates
+ * no device memory; the captured graph of a batch shape is tied to the
+ * workspace address (another address captures again).  The workspace must
+ * stay untouched until the stream has completed the call.
+ */
+sw_status sw_batch_workspace_bytes(sw_db* db, const int64_t* h_qoffsets, int32_t nq, int32_t k,
+                                   int32_t scores_in_ws, int64_t* bytes);
+sw_status sw_search_batch_ws(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                             const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t k,
+                             int32_t* d_scores, int32_t* d_top_scores, int64_t* d_top_index,
+                             void* d_workspace, int64_t ws_bytes, sw_stream stream);
 
 /*
  * sw_search_multi - one launch sequence in which each query scores one chunk of

@@ -25,7 +25,8 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
           -5: "SW_E_UNSUPPORTED", -6: "SW_E_SIZE"}
 
 # Every entry point declared in include/swsearch.h.
-EXPORTS = ("sw_db_pack", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
+EXPORTS = ("sw_db_pack", "sw_db_pack_bytes", "sw_db_pack_into", "sw_search_ws", "sw_batch_workspace_bytes",
+           "sw_search_batch_ws", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
            "sw_search_multi", "sw_align", "sw_align_batch", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws", "sw_topk_noalloc",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
@@ -49,6 +50,16 @@ def load():
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.sw_db_pack.restype = I32
     lib.sw_db_pack.argtypes = [P, P, I64, P, P, ctypes.POINTER(P)]
+    lib.sw_db_pack_bytes.restype = I32
+    lib.sw_db_pack_bytes.argtypes = [P, I64, P, P]
+    lib.sw_db_pack_into.restype = I32
+    lib.sw_db_pack_into.argtypes = [P, P, I64, P, P, I64, P, ctypes.POINTER(P)]
+    lib.sw_search_ws.restype = I32
+    lib.sw_search_ws.argtypes = [P, I32, P, P, I64, P, I32, I32, P, P, I64, P]
+    lib.sw_batch_workspace_bytes.restype = I32
+    lib.sw_batch_workspace_bytes.argtypes = [P, P, I32, I32, I32, P]
+    lib.sw_search_batch_ws.restype = I32
+    lib.sw_search_batch_ws.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P, I64, P]
     lib.sw_db_tune.restype = I32
     lib.sw_db_tune.argtypes = [P, P]
     lib.sw_db_free.restype = None
@@ -152,6 +163,58 @@ def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshol
     return h
 
 
+def sw_db_pack_bytes(h_offsets) -> int:
+    """Device bytes of the packed image of a database with these offsets."""
+    offs = _host_i64(h_offsets)
+    out = ctypes.c_int64()
+    _check(load().sw_db_pack_bytes(_ptr(offs), offs.size - 1, None, ctypes.byref(out)))
+    return out.value
+
+
+def sw_db_pack_into(d_residues, h_offsets, d_db, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
+                    unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0) -> ctypes.c_void_p:
+    """``sw_db_pack`` into ``d_db``, a caller-owned uint8 tensor of at least ``sw_db_pack_bytes`` bytes."""
+    offs = _host_i64(h_offsets)
+    h = ctypes.c_void_p()
+    opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack),
+                    int(alphabet), int(rerun_cap), int(poison))
+    _check(load().sw_db_pack_into(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), offs.size - 1,
+                                  ctypes.byref(opts), _ptr(d_db), d_db.numel() * d_db.element_size(), _stream(stream),
+                                  ctypes.byref(h)))
+    return h
+
+
+def sw_batch_workspace_bytes(handle, h_qoffsets, k=0, scores_in_ws=False) -> int:
+    """Device bytes of the workspace of ``sw_search_ws`` (one query, k = 0) or ``sw_search_batch_ws``."""
+    qo = _host_i64(h_qoffsets)
+    out = ctypes.c_int64()
+    _check(load().sw_batch_workspace_bytes(handle, _ptr(qo), qo.size - 1, int(k), 1 if scores_in_ws else 0,
+                                           ctypes.byref(out)))
+    return out.value
+
+
+def sw_search_ws(query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, d_ws, stream=None):
+    lib = load()
+    q = _host_i8(query)
+    sm = _square(subst)
+    offs = None if h_offsets is None else _host_i64(h_offsets)
+    _check(lib.sw_search_ws(_ptr(q), q.size, handle, None if offs is None else _ptr(offs), int(n), _ptr(sm),
+                            int(gap_open), int(gap_extend), ctypes.c_void_p(d_scores_out.data_ptr()), _ptr(d_ws),
+                            d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+def sw_search_batch_ws(h_queries, h_qoffsets, handle, subst, gap_open, gap_extend, k, d_scores, d_top_scores,
+                       d_top_index, d_ws, stream=None):
+    lib = load()
+    q = _host_i8(h_queries)
+    qo = _host_i64(h_qoffsets)
+    sm = _square(subst)
+    P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    _check(lib.sw_search_batch_ws(_ptr(q), _ptr(qo), qo.size - 1, handle, _ptr(sm), int(gap_open), int(gap_extend),
+                                  int(k), P(d_scores), P(d_top_scores), P(d_top_index), _ptr(d_ws),
+                                  d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
 def sw_search(query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, stream=None):
     lib = load()
     q = _host_i8(query)
@@ -210,11 +273,22 @@ def sw_search_multi(h_queries, h_qoffsets, chunks, nchunks, handle, subst, gap_o
 
 # --------------------------------------------------------------------------- convenience layer
 class Database:
-    """A packed, device-resident protein database."""
+    """A packed, device-resident protein database.
+
+    ``memory="library"``: the handle allocates its image and search workspace.
+    ``memory="torch"``: torch allocates both (the image through
+    ``sw_db_pack_into``, workspaces for ``sw_search_ws`` / ``sw_search_batch_ws``);
+    the handle then holds no device memory of its own (global and semi-global
+    searches and alignments still use the handle's)."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
-                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0):
+                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, memory="library"):
         import torch
+        if memory not in ("library", "torch"):
+            raise ValueError("memory must be 'library' or 'torch'")
+        self.memory = memory
+        self.image = None
+        self.ws = None
         self.offsets = _host_i64(offsets)
         self.n = self.offsets.size - 1
         if isinstance(residues, torch.Tensor) and residues.is_cuda:
@@ -227,14 +301,33 @@ class Database:
             d_res = torch.zeros(1, dtype=torch.int8, device=device)
         self.device = d_res.device
         self.alphabet = int(alphabet) if alphabet else 20
-        self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
-                                 unit_share, lane_pack, alphabet, rerun_cap, poison)
+        if memory == "torch":
+            self.image = torch.empty(sw_db_pack_bytes(self.offsets), dtype=torch.uint8, device=d_res.device)
+            self.handle = sw_db_pack_into(d_res, self.offsets, self.image, stream, force_lanes, rerun_threshold,
+                                          rows_per_lane, unit_share, lane_pack, alphabet, rerun_cap, poison)
+        else:
+            self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
+                                     unit_share, lane_pack, alphabet, rerun_cap, poison)
         del d_res
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
-            load().sw_db_free(self.handle)
+            load().sw_db_free(self.handle)          # synchronises the device: the buffers below are idle
             self.handle = None
+        self.image = None
+        self.ws = None
+
+    def workspace(self, qoffsets, k=0, scores_in_ws=False, stream=None):
+        """A torch workspace of at least the size one search of these query lengths needs (grown, never
+        shrunk; kept for the next call)."""
+        import torch
+        need = sw_batch_workspace_bytes(self.handle, qoffsets, k, scores_in_ws)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = None
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if stream is not None:
+            self.ws.record_stream(stream)
+        return self.ws
 
     def __del__(self):
         try:
@@ -287,7 +380,11 @@ class Database:
         if out is None:
             out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
         # the handle was packed from self.offsets: no need for the library's O(n) offsets check per call
-        if mode == "local":
+        if mode == "local" and self.memory == "torch":
+            q = _host_i8(query)
+            ws = self.workspace(np.array([0, q.size], np.int64), stream=stream)
+            sw_search_ws(q, self.handle, None, self.n, subst, gap_open, gap_extend, out, ws, stream)
+        elif mode == "local":
             sw_search(query, self.handle, None, self.n, subst, gap_open, gap_extend, out, stream)
         else:
             sw_search_mode(MODES[mode], query, self.handle, None, self.n, subst, gap_open, gap_extend, out, stream)
@@ -329,7 +426,11 @@ class Database:
         if k > 0:
             ts = torch.empty((nq, k), dtype=torch.int32, device=self.device)
             ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
-        sw_search_batch(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, stream)
+        if self.memory == "torch":
+            ws = self.workspace(qo, k, scores is None, stream)
+            sw_search_batch_ws(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, ws, stream)
+        else:
+            sw_search_batch(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, stream)
         return scores, ts, ti
 
 

@@ -120,13 +120,18 @@ struct HostPinned {
 };
 
 // Work items of one search: the bulk at R_main rows per lane and, on a side
-// stream, the long pairs of a short query at a smaller R_side.
+// stream, the long pairs of a short query at a smaller R_side.  Searches on
+// the handle's own workspace read the items from device copies made once;
+// searches on a caller's workspace upload them with the queries.
 struct Plan {
-    DevBuf items;                 // [main items..., side items...]
+    std::vector<WgItem> h_items;  // [main items..., side items...]
+    std::vector<int2> h_pairs;    // query pairs (query a, query b or -1) when qpack
     int32_t n_main = 0, n_side = 0;
     int R_main = 16, R_side = 16;
     bool qpack = false;           // items index query pairs (two queries per lane)
-    DevBuf qpairs;                // int2 per pair: (query a, query b or -1)
+    DevBuf items, qpairs;         // device copies (handle workspace only)
+    bool on_device = false;
+    void release() { items.release(); qpairs.release(); on_device = false; }
 };
 
 // Device pointers of the staged queries (descriptors, offsets, matrix + residues).
@@ -147,6 +152,7 @@ struct GraphEntry {
     const void* top_i = nullptr;
     hipStream_t stream = nullptr;
     uint64_t gen = 0;
+    const void* ws = nullptr;         // workspace base the sequence was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void clear() {
@@ -185,14 +191,20 @@ struct sw_db {
     std::vector<int32_t> ncols;       // per group
     std::vector<int32_t> pcols;       // per pair: longest subject of the pair, rounded up to 4
     int32_t ncols_max = 0;
-    DevBuf image, groups, perm, pair_cols;
+    // The packed image: one device allocation, the handle's own (image_own) or the caller's
+    // (sw_db_pack_into), laid out by DbLayout.
+    DevBuf image_own;
+    bool caller_image = false;
+    uint8_t* d_image = nullptr;       // interleaved residues
+    GroupRec* d_groups = nullptr;
+    int32_t* d_perm = nullptr;        // sorted slot -> original subject index, -1 for padding slots
+    int32_t* d_pair_cols = nullptr;   // per pair: longest subject of the pair, rounded up to 4
+    int32_t* d_slen = nullptr;        // subject length per sorted slot (end-to-end modes), 0 for padding
     int64_t image_bytes = 0;
     // per original subject: length and sorted slot; per group: byte offset in the image (alignments)
     std::vector<int32_t> lens, slot_of;
     std::vector<int64_t> gbase;
     DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
-    DevBuf slen_sorted;               // subject length per sorted slot (end-to-end modes)
-    DevBuf topk_ws;                   // candidates of the two-launch top-k of long score rows
     int wg_mode = 0;                  // persistent workgroups of an end-to-end sweep
     Plan mode_plan;
     // launch geometry
@@ -204,9 +216,9 @@ struct sw_db {
     hipStream_t side2 = nullptr;      // third stream (end-to-end modes: the 32-bit groups beside both 16-bit launches)
     hipStream_t cap = nullptr;        // stream the batched sequence is captured on
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
-    // workspace
+    // workspace of searches without a caller workspace (laid out by WsLayout)
     uint64_t gen = 1;                 // bumped on every workspace reallocation
-    DevBuf scratch16, scratch32, prof, stage, counters, rerun, rerun_bits, scores_tmp;
+    DevBuf ws_own;
     HostPinned hstage;
     std::map<int, Plan> plans;        // plain searches: query length -> plan
     Plan batch_plan, multi_plan;
@@ -224,6 +236,7 @@ struct sw_db {
     // statistics and timing
     int last_items = 0, last_rows = 16, last_grid = 0, last_side_items = 0, last_side_rows = 0;
     int64_t last_cap = 0;             // list capacity of the last search's recompute
+    const int32_t* last_counters = nullptr;   // device counters of the last search (its workspace)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_used;         // indices into ev_pool, in launch order
@@ -497,12 +510,24 @@ sw_status build_plan(sw_db* db, const std::vector<int>& qlens, Plan* p, const st
     p->n_main = (int32_t)mi.size();
     p->n_side = (int32_t)si.size();
     mi.insert(mi.end(), si.begin(), si.end());
-    HIP_TRY(p->items.reserve(std::max<size_t>(mi.size(), 1) * sizeof(WgItem), &db->gen));
-    if (!mi.empty()) HIP_TRY(hipMemcpy(p->items.p, mi.data(), mi.size() * sizeof(WgItem), hipMemcpyHostToDevice));
+    p->h_items.swap(mi);
+    p->h_pairs.swap(pairs);
+    p->on_device = false;
+    return SW_OK;
+}
+
+// Device copies of a plan's items and query pairs (searches on the handle's own workspace).
+sw_status upload_plan(sw_db* db, Plan* p) {
+    if (p->on_device) return SW_OK;
+    HIP_TRY(p->items.reserve(std::max<size_t>(p->h_items.size(), 1) * sizeof(WgItem), &db->gen));
+    if (!p->h_items.empty())
+        HIP_TRY(hipMemcpy(p->items.p, p->h_items.data(), p->h_items.size() * sizeof(WgItem), hipMemcpyHostToDevice));
     if (p->qpack) {
-        HIP_TRY(p->qpairs.reserve(std::max<size_t>(pairs.size(), 1) * sizeof(int2), &db->gen));
-        if (!pairs.empty()) HIP_TRY(hipMemcpy(p->qpairs.p, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
+        HIP_TRY(p->qpairs.reserve(std::max<size_t>(p->h_pairs.size(), 1) * sizeof(int2), &db->gen));
+        if (!p->h_pairs.empty())
+            HIP_TRY(hipMemcpy(p->qpairs.p, p->h_pairs.data(), p->h_pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
+    p->on_device = true;
     return SW_OK;
 }
 
@@ -510,24 +535,24 @@ sw_status get_plan(sw_db* db, int m, Plan** out) {
     auto it = db->plans.find(m);
     if (it != db->plans.end()) { *out = &it->second; return SW_OK; }
     if (db->plans.size() >= 64) {
-        for (auto& kv : db->plans) kv.second.items.release();
+        for (auto& kv : db->plans) kv.second.release();
         db->plans.clear();
     }
     Plan& p = db->plans[m];
     sw_status s = build_plan(db, std::vector<int>{m}, &p);
-    if (s != SW_OK) { p.items.release(); db->plans.erase(m); return s; }
+    if (s != SW_OK) { p.release(); db->plans.erase(m); return s; }
     *out = &p;
     return SW_OK;
 }
 
 void clear_caches(sw_db* db) {
-    for (auto& kv : db->plans) kv.second.items.release();
+    for (auto& kv : db->plans) kv.second.release();
     db->plans.clear();
-    db->batch_plan.items.release();
-    db->batch_plan.qpairs.release();
+    db->batch_plan.release();
+    db->batch_plan.h_items.clear();
     db->batch_plan.n_main = db->batch_plan.n_side = 0;
-    db->multi_plan.items.release();
-    db->multi_plan.qpairs.release();
+    db->multi_plan.release();
+    db->multi_plan.h_items.clear();
     db->multi_plan.n_main = db->multi_plan.n_side = 0;
     db->batch_qlens.clear();
     db->graph.clear();
@@ -539,10 +564,12 @@ sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
     return SW_OK;
 }
 
-sw_status ensure_workspace(sw_db* db) {
+// Launch geometry (occupancy of every sweep instance, boundary-slot sizes), streams and events.
+// Allocates no device memory.
+sw_status ensure_geometry(sw_db* db) {
     if (db->wg16 == 0) {
         // a failure part way leaves wg16 at 0, so the next call sets up again (streams and events are
-        // created once; buffers only grow)
+        // created once)
         struct Undo {
             sw_db* d;
             bool done = false;
@@ -573,11 +600,6 @@ sw_status ensure_workspace(sw_db* db) {
         // a unit's boundary row is (columns x subjects-or-pairs per wave); the widest
         // query-pair unit is 2 subjects of the longest subject's width
         db->slot_cap = std::max<int64_t>(65536, 2 * (int64_t)db->ncols_max);
-        const int64_t nw16 = (int64_t)db->wg16 * kWaves;
-        const int64_t nw32 = (int64_t)db->wg32 * kWaves;
-        HIP_TRY(db->scratch16.reserve((size_t)nw16 * db->slot_cap * 2 * 4, &db->gen));
-        HIP_TRY(db->scratch32.reserve((size_t)nw32 * std::max<int64_t>(db->ncols_max, 4) * 4 * 4, &db->gen));
-        HIP_TRY(db->counters.reserve(kCounters * sizeof(int32_t), &db->gen));
         if (!db->side) HIP_TRY(hipStreamCreateWithFlags(&db->side, hipStreamNonBlocking));
         if (!db->side2) HIP_TRY(hipStreamCreateWithFlags(&db->side2, hipStreamNonBlocking));
         if (!db->cap) HIP_TRY(hipStreamCreateWithFlags(&db->cap, hipStreamNonBlocking));
@@ -590,14 +612,18 @@ sw_status ensure_workspace(sw_db* db) {
     return SW_OK;
 }
 
-// Layout of the staging buffer: [QDesc x nq][qoff x nq][subst, kMaxAlphabet^2 bytes][queries].
-struct StageLayout { size_t off_qoff, off_sm, total; int64_t prof_elems; int max_mp; };
+// Layout of the staging buffer: [QDesc x nq][qoff x nq][subst, kMaxAlphabet^2 bytes][queries]
+// [plan items][query pairs]; the plan parts only when the plan travels with the queries (a caller's
+// workspace).
+struct StageLayout { size_t off_qoff, off_sm, off_items, off_pairs, total; int64_t prof_elems; int max_mp; };
 
-StageLayout stage_layout(const int64_t* h_qoffsets, int nq) {
+StageLayout stage_layout(const int64_t* h_qoffsets, int nq, const Plan* with_plan = nullptr) {
     StageLayout L{};
     L.off_qoff = round_up(sizeof(QDesc) * nq, 64);
     L.off_sm = L.off_qoff + round_up(sizeof(int64_t) * nq, 64);
-    L.total = L.off_sm + kMaxAlphabet * kMaxAlphabet + (h_qoffsets[nq] - h_qoffsets[0]);
+    L.off_items = round_up(L.off_sm + kMaxAlphabet * kMaxAlphabet + (h_qoffsets[nq] - h_qoffsets[0]), 64);
+    L.off_pairs = round_up(L.off_items + (with_plan ? with_plan->h_items.size() * sizeof(WgItem) : 0), 64);
+    L.total = L.off_pairs + (with_plan && with_plan->qpack ? with_plan->h_pairs.size() * sizeof(int2) : 0);
     L.max_mp = kProfRowAlign;
     for (int q = 0; q < nq; ++q) {
         const int m = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
@@ -620,24 +646,109 @@ int64_t rerun_capacity(const sw_db* db, int nq) {
 
 int64_t rerun_words(const sw_db* db, int nq) { return (int64_t)std::max(nq, 1) * db->ngroups * 2; }
 
-// Every device buffer a launch sequence for this input needs (may reallocate).
-sw_status reserve_for(sw_db* db, const StageLayout& L, int nq) {
-    HIP_TRY(db->hstage.reserve(L.total));
-    HIP_TRY(db->stage.reserve(L.total, &db->gen));
-    HIP_TRY(db->prof.reserve(L.prof_elems * sizeof(int16_t), &db->gen));
-    HIP_TRY(db->rerun.reserve((size_t)rerun_capacity(db, nq) * sizeof(WgItem), &db->gen));
-    HIP_TRY(db->rerun_bits.reserve((size_t)rerun_words(db, nq) * sizeof(uint32_t), &db->gen));
+// The device workspace of a launch sequence, one region laid out in this order:
+// 16-bit boundary slots, 32-bit slots, counters, profiles, staging, recompute
+// list, flag bits, top-k pieces, score rows (a batch that keeps only its top k).
+struct WsLayout {
+    StageLayout st;
+    int64_t scratch16 = 0, scratch32 = 0, counters = 0, prof = 0, stage = 0, rerun = 0, bits = 0, topk = 0,
+            scores = 0, total = 0;
+    int64_t rerun_cap = 0, bits_words = 0;
+};
+
+WsLayout ws_layout(const sw_db* db, const int64_t* h_qoffsets, int nq, int k, bool with_scores,
+                   const Plan* with_plan) {
+    WsLayout L;
+    L.st = stage_layout(h_qoffsets, nq, with_plan);
+    L.rerun_cap = rerun_capacity(db, nq);
+    L.bits_words = rerun_words(db, nq);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { const int64_t at = o; o = round_up(o + std::max<int64_t>(bytes, 1), 256); return at; };
+    L.scratch16 = take((int64_t)db->wg16 * kWaves * db->slot_cap * 2 * 4);
+    L.scratch32 = take((int64_t)db->wg32 * kWaves * std::max<int64_t>(db->ncols_max, 4) * 4 * 4);
+    L.counters = take(kCounters * sizeof(int32_t));
+    L.prof = take(L.st.prof_elems * (int64_t)sizeof(int16_t));
+    L.stage = take((int64_t)L.st.total);
+    L.rerun = take(L.rerun_cap * (int64_t)sizeof(WgItem));
+    L.bits = take(L.bits_words * (int64_t)sizeof(uint32_t));
+    L.topk = take(k > 0 ? topk_ws_bytes(db->n, nq, k) : 0);
+    L.scores = take(with_scores ? (int64_t)nq * std::max<int64_t>(db->n, 1) * (int64_t)sizeof(int32_t) : 0);
+    L.total = o;
+    return L;
+}
+
+// Device pointers of a workspace (the handle's own or a caller's) carved by a layout, and where the
+// plan's items live.
+struct Work {
+    WsLayout L;
+    uint32_t* scratch16 = nullptr;
+    uint32_t* scratch32 = nullptr;
+    int32_t* counters = nullptr;
+    int16_t* prof = nullptr;
+    char* stage = nullptr;
+    WgItem* rerun = nullptr;
+    uint32_t* bits = nullptr;
+    void* topk = nullptr;
+    int32_t* scores = nullptr;
+    const WgItem* items = nullptr;
+    const int2* qpairs = nullptr;
+};
+
+Work carve(void* base, const WsLayout& L) {
+    char* b = static_cast<char*>(base);
+    Work W;
+    W.L = L;
+    W.scratch16 = reinterpret_cast<uint32_t*>(b + L.scratch16);
+    W.scratch32 = reinterpret_cast<uint32_t*>(b + L.scratch32);
+    W.counters = reinterpret_cast<int32_t*>(b + L.counters);
+    W.prof = reinterpret_cast<int16_t*>(b + L.prof);
+    W.stage = b + L.stage;
+    W.rerun = reinterpret_cast<WgItem*>(b + L.rerun);
+    W.bits = reinterpret_cast<uint32_t*>(b + L.bits);
+    W.topk = b + L.topk;
+    W.scores = reinterpret_cast<int32_t*>(b + L.scores);
+    return W;
+}
+
+// The workspace of a launch sequence: the caller's (d_ws, checked against the layout) or the
+// handle's own (grown as needed); plan items from the plan's device copy or, with a caller's
+// workspace, from the staging area they are uploaded to.
+sw_status get_work(sw_db* db, const int64_t* h_qoffsets, int nq, int k, bool with_scores, Plan* plan, void* d_ws,
+                   int64_t ws_bytes, Work* out) {
+    const bool caller = d_ws != nullptr;
+    const WsLayout L = ws_layout(db, h_qoffsets, nq, k, with_scores, caller ? plan : nullptr);
+    if (caller) {
+        if (ws_bytes < L.total)
+            return fail(SW_E_SIZE, "workspace of %lld bytes < %lld needed", (long long)ws_bytes, (long long)L.total);
+        if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(SW_E_INVALID, "workspace not 256-byte aligned");
+        *out = carve(d_ws, L);
+    } else {
+        HIP_TRY(db->ws_own.reserve((size_t)L.total, &db->gen));
+        *out = carve(db->ws_own.p, L);
+    }
+    HIP_TRY(db->hstage.reserve(L.st.total));
+    if (plan) {
+        if (caller) {
+            out->items = reinterpret_cast<const WgItem*>(out->stage + L.st.off_items);
+            out->qpairs = plan->qpack ? reinterpret_cast<const int2*>(out->stage + L.st.off_pairs) : nullptr;
+        } else {
+            sw_status s = upload_plan(db, plan);
+            if (s != SW_OK) return s;
+            out->items = plan->items.as<WgItem>();
+            out->qpairs = plan->qpack ? plan->qpairs.as<int2>() : nullptr;
+        }
+    }
     return SW_OK;
 }
 
 // The recompute fields of a 16-bit sweep's arguments (flagged pairs are listed, then set as bits).
-void set_rerun_args(sw_db* db, SweepArgs& a, int nq, int32_t* ctr) {
-    a.rerun = db->rerun.as<WgItem>();
+void set_rerun_args(sw_db* db, SweepArgs& a, const Work& W, int32_t* ctr) {
+    a.rerun = W.rerun;
     a.rerun_count = ctr + 1;
-    a.rerun_cap = (int32_t)rerun_capacity(db, nq);
-    a.rerun_bits = db->rerun_bits.as<uint32_t>();
+    a.rerun_cap = (int32_t)W.L.rerun_cap;
+    a.rerun_bits = W.bits;
     a.rerun_groups = db->ngroups;
-    a.rerun_words = rerun_words(db, nq);
+    a.rerun_words = W.L.bits_words;
     a.recomputed = ctr + 5;
     a.poison = db->poison;
     db->last_cap = a.rerun_cap;
@@ -645,13 +756,13 @@ void set_rerun_args(sw_db* db, SweepArgs& a, int nq, int32_t* ctr) {
 
 // Arguments of the 32-bit recompute that follows sweep arguments a: every listed pair, then (when the
 // list overflowed) every pair whose flag bit is set; one unit per workgroup in the 32-bit slots.
-SweepArgs recompute_args(const sw_db* db, const SweepArgs& a, int32_t* ctr) {
+SweepArgs recompute_args(const sw_db* db, const SweepArgs& a, const Work& W, int32_t* ctr) {
     SweepArgs r = a;
-    r.items = db->rerun.as<WgItem>();
+    r.items = W.rerun;
     r.n_items_dev = ctr + 1;
     r.n_items = a.rerun_cap;
     r.counter = ctr + 2;
-    r.scratch = db->scratch32.as<uint32_t>();
+    r.scratch = W.scratch32;
     r.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
     r.slot_base = 0;
     r.rerun = nullptr;              // reads rerun_bits, appends nothing
@@ -661,16 +772,30 @@ SweepArgs recompute_args(const sw_db* db, const SweepArgs& a, int32_t* ctr) {
     return r;
 }
 
-sw_status reserve_topk(sw_db* db, int rows, int k) {
-    const int64_t b = k > 0 ? topk_ws_bytes(db->n, rows, k) : 0;
-    if (b > 0) HIP_TRY(db->topk_ws.reserve((size_t)b, &db->gen));
-    return SW_OK;
+// Sweep arguments shared by every launch of a search: image, profile, queries, gaps, 16-bit slots.
+SweepArgs sweep_args(const sw_db* db, const Staged& S, const Work& W, int32_t go, int32_t ge, int32_t* scores) {
+    SweepArgs a{};
+    a.image = db->d_image;
+    a.groups = db->d_groups;
+    a.perm = db->d_perm;
+    a.pair_cols = db->d_pair_cols;
+    a.slen = db->d_slen;
+    a.prof = W.prof;
+    a.qd = S.qd;
+    a.go = go;
+    a.ge = ge;
+    a.scratch = W.scratch16;
+    a.slot_words = db->slot_cap * 2;
+    a.slot_base = 0;
+    a.scores = scores;
+    return a;
 }
 
 // Copies the queries (host) into the staging buffer on the device.  No launch.
-sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
+sw_status stage_queries(sw_db* db, const Work& W, const int8_t* h_queries, const int64_t* h_qoffsets, int nq,
                         const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out,
-                        int32_t* const* per_query_out = nullptr) {
+                        int32_t* const* per_query_out = nullptr, const Plan* with_plan = nullptr) {
+    const StageLayout& L = W.L.st;
     char* h = static_cast<char*>(db->hstage.p);
     int64_t prof_off = 0;
     QDesc* qd = reinterpret_cast<QDesc*>(h);
@@ -688,10 +813,16 @@ sw_status stage_queries(sw_db* db, const StageLayout& L, const int8_t* h_queries
     out->bias = -lowest;
     const int64_t qbytes = h_qoffsets[nq] - h_qoffsets[0];
     if (qbytes) memcpy(h + L.off_sm + kMaxAlphabet * kMaxAlphabet, h_queries + h_qoffsets[0], qbytes);
-    HIP_TRY(hipMemcpyAsync(db->stage.p, h, L.total, hipMemcpyHostToDevice, st));
+    if (with_plan) {
+        if (!with_plan->h_items.empty())
+            memcpy(h + L.off_items, with_plan->h_items.data(), with_plan->h_items.size() * sizeof(WgItem));
+        if (with_plan->qpack && !with_plan->h_pairs.empty())
+            memcpy(h + L.off_pairs, with_plan->h_pairs.data(), with_plan->h_pairs.size() * sizeof(int2));
+    }
+    HIP_TRY(hipMemcpyAsync(W.stage, h, L.total, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(db->hstage.done, st));
     db->hstage.pending = true;
-    char* d = db->stage.as<char>();
+    const char* d = W.stage;
     out->qd = reinterpret_cast<const QDesc*>(d);
     out->qoff = reinterpret_cast<const int64_t*>(d + L.off_qoff);
     out->sm_q = reinterpret_cast<const int8_t*>(d + L.off_sm);
@@ -720,41 +851,29 @@ int record_timer_start(sw_db* db, hipStream_t st) {
 // The launch sequence of a search: profile (zeroes the counters), the side and
 // bulk 16-bit sweeps, the 32-bit recompute, top-k.  Allocates nothing and never
 // waits on the host, so it can be captured into a graph.
-sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int32_t ge, int32_t* d_scores,
-                  int64_t n, int k, int32_t* top_s, int64_t* top_i, hipStream_t st, bool time_sweep) {
-    int32_t* ctr = db->counters.as<int32_t>();
-    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters,
-                           db->rerun_bits.as<uint32_t>(), rerun_words(db, S.nq), S.max_mp, st));
-    const WgItem* d_items = plan.items.as<WgItem>();
-    SweepArgs a{};
-    a.items = d_items;
+sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, const Work& W, int32_t go, int32_t ge,
+                  int32_t* d_scores, int64_t n, int k, int32_t* top_s, int64_t* top_i, hipStream_t st,
+                  bool time_sweep) {
+    int32_t* ctr = W.counters;
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, W.prof, ctr, kCounters, W.bits, W.L.bits_words,
+                           S.max_mp, st));
+    SweepArgs a = sweep_args(db, S, W, go, ge, d_scores);
+    a.items = W.items;
     a.n_items_dev = nullptr;
     a.n_items = plan.n_main;
     a.counter = ctr + 0;
-    a.image = db->image.as<uint8_t>();
-    a.groups = db->groups.as<GroupRec>();
-    a.perm = db->perm.as<int32_t>();
-    a.pair_cols = db->pair_cols.as<int32_t>();
-    a.prof = db->prof.as<int16_t>();
-    a.qd = S.qd;
-    a.go = go;
-    a.ge = ge;
-    a.scratch = db->scratch16.as<uint32_t>();
-    a.slot_words = db->slot_cap * 2;
-    a.slot_base = 0;
-    a.scores = d_scores;
-    set_rerun_args(db, a, S.nq, ctr);
+    set_rerun_args(db, a, W, ctr);
     a.unit_list = 0;
     a.bias = S.bias;
     a.sat = std::min<int32_t>(db->sat + S.bias, kSat16);
-    a.qpairs = plan.qpack ? plan.qpairs.as<int2>() : nullptr;
+    a.qpairs = plan.qpack ? W.qpairs : nullptr;
     // the side launch takes the first slots; the bulk launch fills the rest of the GPU
     const int wg_main = plan.qpack ? db->wgQ[plan.R_main] : db->wgR[plan.R_main];
     const int grid_side = std::min(plan.n_side, std::max(1, wg_main / 8));
     const int grid_main = std::max(1, std::min(wg_main - grid_side, std::max(plan.n_main, 1)));
     if (plan.n_side > 0) {
         SweepArgs b = a;
-        b.items = d_items + plan.n_main;
+        b.items = W.items + plan.n_main;
         b.n_items = plan.n_side;
         b.counter = ctr + 3;
         b.slot_base = grid_main;
@@ -776,16 +895,17 @@ sw_status enqueue(sw_db* db, const Staged& S, const Plan& plan, int32_t go, int3
         db->ev_used.push_back(ev);
     }
     // exact 32-bit recompute of saturated pairs; the count is read on the device
-    const SweepArgs r = recompute_args(db, a, ctr);
+    const SweepArgs r = recompute_args(db, a, W, ctr);
     HIP_TRY(launch_sweep(false, kRerunRows, r, db->wg32, st));
     if (k > 0)
-        HIP_TRY(launch_topk_ws(d_scores, n, n, S.nq, k, top_s, top_i,
-                               topk_ws_bytes(n, S.nq, k) > 0 ? db->topk_ws.p : nullptr, st));
+        HIP_TRY(launch_topk_ws(d_scores, n, n, S.nq, k, top_s, top_i, topk_ws_bytes(n, S.nq, k) > 0 ? W.topk : nullptr,
+                               st));
     db->last_items = plan.n_main;
     db->last_rows = plan.R_main;
     db->last_side_items = plan.n_side;
     db->last_side_rows = plan.n_side ? plan.R_side : 0;
     db->last_grid = grid_main + (plan.n_side > 0 ? grid_side : 0);
+    db->last_counters = ctr;
     return SW_OK;
 }
 
@@ -795,6 +915,300 @@ sw_status check_db_args(sw_db* db, const int64_t* h_offsets, int64_t n) {
     if (h_offsets && n > 0 &&
         (h_offsets[0] != db->off_first || h_offsets[n] != db->off_last || offsets_hash(h_offsets, n) != db->off_hash))
         return fail(SW_E_INVALID, "offsets do not match the packed database");
+    return SW_OK;
+}
+
+
+}  // namespace
+
+namespace {
+
+// Host side of packing: the length order, the groups of 128 subjects and where each subject goes.
+struct PackPlan {
+    std::vector<int32_t> len;         // per original subject
+    std::vector<int32_t> order;       // sorted slot -> original subject
+    std::vector<GroupRec> groups;
+    std::vector<int64_t> gdw;         // group base in dwords
+    std::vector<int32_t> perm;        // [G * 128] sorted slot -> original subject, -1 for padding slots
+    std::vector<int64_t> soff;        // sorted slot -> residue offset of the subject
+    std::vector<int32_t> slen;        // [G * 128] sorted slot -> length, 0 for padding slots
+    std::vector<int32_t> ncols;       // per group
+    std::vector<int32_t> pcols;       // per pair
+    int32_t ncols_max = 0;
+    int64_t image_bytes = 0;
+    int G = 0;
+};
+
+sw_status plan_pack(const int64_t* h_offsets, int64_t n, PackPlan* P) {
+    if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
+    if (n > ((int64_t)1 << 31) - 256) return fail(SW_E_UNSUPPORTED, "more than 2^31 subjects");
+    if (n > 0 && !h_offsets) return fail(SW_E_INVALID, "NULL offsets");
+    if (n > 0 && h_offsets[0] < 0) return fail(SW_E_INVALID, "offsets[0] < 0");
+    P->len.resize(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t l = h_offsets[k + 1] - h_offsets[k];
+        if (l < 0) return fail(SW_E_INVALID, "offsets decrease at %lld", (long long)k);
+        if (l > (1 << 24)) return fail(SW_E_UNSUPPORTED, "subject %lld longer than 2^24", (long long)k);
+        P->len[k] = (int32_t)l;
+    }
+    P->order.resize(n);
+    std::iota(P->order.begin(), P->order.end(), 0);
+    std::stable_sort(P->order.begin(), P->order.end(), [&](int32_t a, int32_t b) { return P->len[a] > P->len[b]; });
+    const int G = P->G = (int)((n + kGroupSubjects - 1) / kGroupSubjects);
+    P->groups.resize(G);
+    P->gdw.resize(G);
+    P->ncols.resize(G);
+    int64_t base = 0;
+    for (int g = 0; g < G; ++g) {
+        const int32_t nc = (int32_t)round_up(P->len[P->order[(size_t)g * kGroupSubjects]], kChunkCols);
+        P->groups[g] = GroupRec{base, nc, g * kGroupSubjects};
+        P->gdw[g] = base / 4;
+        P->ncols[g] = nc;
+        P->ncols_max = std::max(P->ncols_max, nc);
+        base += (int64_t)nc * kGroupSubjects;
+    }
+    P->image_bytes = base;
+    P->perm.assign((size_t)G * kGroupSubjects, -1);
+    P->slen.assign((size_t)G * kGroupSubjects, 0);
+    P->soff.resize(n);
+    P->pcols.assign((size_t)G * kGroupPairs, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t o = P->order[i];
+        P->pcols[(size_t)(i / 2)] = std::max<int32_t>(P->pcols[(size_t)(i / 2)], (int32_t)round_up(P->len[o], kChunkCols));
+        P->perm[i] = o;
+        P->soff[i] = h_offsets[o];
+        P->slen[i] = P->len[o];
+    }
+    return SW_OK;
+}
+
+// Device layout of a packed image: interleaved residues, group table, permutation, pair widths,
+// sorted lengths, then what packing alone uses (residue offsets per sorted slot, group bases, an
+// error word), which may hold anything afterwards.
+struct DbLayout { int64_t image, groups, perm, pair_cols, slen, soff, gdw, err, total; };
+
+DbLayout db_layout(int64_t n, int G, int64_t image_bytes) {
+    DbLayout L{};
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { const int64_t at = o; o = round_up(o + std::max<int64_t>(bytes, 1), 256); return at; };
+    L.image = take(std::max<int64_t>(image_bytes, 4));
+    L.groups = take((int64_t)sizeof(GroupRec) * G);
+    L.perm = take(4 * (int64_t)G * kGroupSubjects);
+    L.pair_cols = take(4 * (int64_t)G * kGroupPairs);
+    L.slen = take(4 * (int64_t)G * kGroupSubjects);
+    L.soff = take(8 * std::max<int64_t>(n, 1));
+    L.gdw = take(8 * (int64_t)std::max(G, 1));
+    L.err = take(4);
+    L.total = o;
+    return L;
+}
+
+// sw_db_pack (d_db NULL: the handle allocates the image) and sw_db_pack_into (the caller's buffer).
+sw_status pack_db(const int8_t* d_residues, const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts, void* d_db,
+                  int64_t db_bytes, hipStream_t st, sw_db** out) {
+    if (!out) return fail(SW_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n > 0 && !d_residues) return fail(SW_E_INVALID, "NULL residues");
+    PackPlan P;
+    sw_status so = plan_pack(h_offsets, n, &P);
+    if (so != SW_OK) return so;
+    const DbLayout L = db_layout(n, P.G, P.image_bytes);
+    if (d_db && db_bytes < L.total)
+        return fail(SW_E_SIZE, "image buffer of %lld bytes < %lld needed", (long long)db_bytes, (long long)L.total);
+    if (d_db && (reinterpret_cast<uintptr_t>(d_db) & 255) != 0) return fail(SW_E_INVALID, "image buffer not 256-byte aligned");
+    sw_db* db = new (std::nothrow) sw_db();
+    if (!db) return fail(SW_E_NOMEM, "host allocation failed");
+    auto bail = [&](sw_status s) { sw_db_free(db); return s; };
+    if (hipGetDevice(&db->device) != hipSuccess) return bail(fail(SW_E_HIP, "no current HIP device"));
+    so = apply_opts(db, opts);
+    if (so != SW_OK) return bail(so);
+    if (opts && (opts->alphabet < 0 || opts->alphabet > kMaxAlphabet))
+        return bail(fail(SW_E_INVALID, "alphabet must be 0 (= 20) or 1..%d", kMaxAlphabet));
+    db->alphabet = (opts && opts->alphabet > 0) ? opts->alphabet : 20;
+    db->n = n;
+    db->off_first = n > 0 ? h_offsets[0] : 0;
+    db->off_last = n > 0 ? h_offsets[n] : 0;
+    db->off_hash = n > 0 ? offsets_hash(h_offsets, n) : 0;
+    db->total_res = db->off_last - db->off_first;
+    db->ngroups = P.G;
+    db->ncols = P.ncols;
+    db->pcols = P.pcols;
+    db->ncols_max = P.ncols_max;
+    db->image_bytes = P.image_bytes;
+    db->lens = P.len;
+    db->slot_of.assign(n, 0);
+    for (int64_t i = 0; i < n; ++i) db->slot_of[P.order[i]] = (int32_t)i;
+    db->gbase.resize(P.G);
+    for (int g = 0; g < P.G; ++g) db->gbase[g] = P.groups[g].base;
+    char* base = static_cast<char*>(d_db);
+    if (!d_db) {
+        const hipError_t e = db->image_own.reserve((size_t)L.total);
+        if (e != hipSuccess)
+            return bail(fail(e == hipErrorOutOfMemory ? SW_E_NOMEM : SW_E_HIP, "device allocation: %s", hipGetErrorString(e)));
+        base = db->image_own.as<char>();
+    }
+    db->caller_image = d_db != nullptr;
+    db->d_image = reinterpret_cast<uint8_t*>(base + L.image);
+    db->d_groups = reinterpret_cast<GroupRec*>(base + L.groups);
+    db->d_perm = reinterpret_cast<int32_t*>(base + L.perm);
+    db->d_pair_cols = reinterpret_cast<int32_t*>(base + L.pair_cols);
+    db->d_slen = reinterpret_cast<int32_t*>(base + L.slen);
+    if (P.G > 0) {
+        int64_t* d_soff = reinterpret_cast<int64_t*>(base + L.soff);
+        int64_t* d_gdw = reinterpret_cast<int64_t*>(base + L.gdw);
+        int32_t* d_err = reinterpret_cast<int32_t*>(base + L.err);
+        int32_t zero = 0, herr = 0;
+        hipError_t e = hipSuccess;
+        auto step = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+        step(hipMemcpyAsync(db->d_groups, P.groups.data(), sizeof(GroupRec) * P.G, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(db->d_perm, P.perm.data(), sizeof(int32_t) * P.perm.size(), hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(db->d_pair_cols, P.pcols.data(), sizeof(int32_t) * P.pcols.size(), hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(db->d_slen, P.slen.data(), sizeof(int32_t) * P.slen.size(), hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_soff, P.soff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_gdw, P.gdw.data(), sizeof(int64_t) * P.G, hipMemcpyHostToDevice, st));
+        step(hipMemcpyAsync(d_err, &zero, 4, hipMemcpyHostToDevice, st));
+        step(launch_interleave(d_residues, d_soff, db->d_slen, n, db->alphabet, db->d_groups, d_gdw, P.G,
+                               reinterpret_cast<uint32_t*>(db->d_image), P.image_bytes / 4, d_err, st));
+        step(hipMemcpyAsync(&herr, d_err, 4, hipMemcpyDeviceToHost, st));
+        step(hipStreamSynchronize(st));
+        if (e != hipSuccess) return bail(fail(SW_E_HIP, "packing: %s", hipGetErrorString(e)));
+        if (herr) return bail(fail(SW_E_RESIDUE, "database residue code outside 0..%d", db->alphabet - 1));
+    }
+    *out = db;
+    return SW_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// sw_search and sw_search_ws: the plain form, on the handle's workspace (d_ws NULL) or the caller's.
+sw_status search_one(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets, int64_t n,
+                     const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out, void* d_ws,
+                     int64_t ws_bytes, hipStream_t st) {
+    sw_status s;
+    if ((s = check_db_args(db, h_offsets, n)) != SW_OK) return s;
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (qlen < 0) return fail(SW_E_INVALID, "qlen must be >= 0");
+    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
+    if (n > 0 && !d_scores_out) return fail(SW_E_INVALID, "scores_out is NULL");
+    for (int32_t i = 0; i < qlen; ++i)
+        if (h_query[i] < 0 || h_query[i] >= db->alphabet)
+            return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
+    if (n == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    if (qlen == 0) { HIP_TRY(launch_fill(d_scores_out, n, 0, st)); return SW_OK; }
+    if ((s = ensure_geometry(db)) != SW_OK) return s;
+    Plan* plan = nullptr;
+    if ((s = get_plan(db, qlen, &plan)) != SW_OK) return s;
+    const int64_t qo[2] = {0, qlen};
+    Work W;
+    if ((s = get_work(db, qo, 1, 0, false, plan, d_ws, ws_bytes, &W)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, W, h_query, qo, 1, h_subst, 0, st, &S, nullptr, d_ws ? plan : nullptr)) != SW_OK)
+        return s;
+    return enqueue(db, S, *plan, W, gap_open, gap_extend, d_scores_out, n, 0, nullptr, nullptr, st, true);
+}
+
+}  // namespace
+
+namespace {
+
+// The batch plan for these query lengths (kept while the lengths repeat).
+sw_status plan_for(sw_db* db, const std::vector<int>& qlens, Plan** out) {
+    if (qlens != db->batch_qlens) {
+        if (db->batch_plan.on_device) HIP_TRY(hipDeviceSynchronize());   // a batch in flight may read its items
+        db->batch_qlens.clear();
+        db->batch_plan.release();
+        sw_status s = build_plan(db, qlens, &db->batch_plan);
+        if (s != SW_OK) return s;
+        db->batch_qlens = qlens;
+    }
+    *out = &db->batch_plan;
+    return SW_OK;
+}
+
+// sw_search_batch and sw_search_batch_ws: the batched form, on the handle's workspace (d_ws NULL) or
+// the caller's.
+sw_status search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                       const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* d_scores,
+                       int32_t* d_top_scores, int64_t* d_top_index, void* d_ws, int64_t ws_bytes, hipStream_t st) {
+    sw_status s;
+    if (!db) return fail(SW_E_INVALID, "db is NULL");
+    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
+    if (nq < 0) return fail(SW_E_INVALID, "nq must be >= 0");
+    if (nq > 0 && (!h_qoffsets || !h_queries)) return fail(SW_E_INVALID, "NULL queries or offsets");
+    if (k < 0 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 0..1024 (got %d)", k);
+    if (k > 0 && (!d_top_scores || !d_top_index)) return fail(SW_E_INVALID, "NULL top-k outputs");
+    if (!d_scores && k == 0) return fail(SW_E_INVALID, "no output requested (scores NULL and k == 0)");
+    for (int q = 0; q < nq; ++q) {
+        if (h_qoffsets[q + 1] < h_qoffsets[q]) return fail(SW_E_INVALID, "query offsets decrease at %d", q);
+        if (h_qoffsets[q + 1] - h_qoffsets[q] > (1 << 24)) return fail(SW_E_UNSUPPORTED, "query %d too long", q);
+    }
+    if (nq > 0)
+        for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
+            if (h_queries[i] < 0 || h_queries[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue outside 0..%d at %lld", db->alphabet - 1, (long long)i);
+    if (nq == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    DeviceGuard dg(db->device);
+    const int64_t n = db->n;
+    if (n == 0) {
+        if (k > 0) HIP_TRY(launch_topk(d_scores, 0, 0, nq, k, d_top_scores, d_top_index, st));
+        return SW_OK;
+    }
+    if ((s = ensure_geometry(db)) != SW_OK) return s;
+    std::vector<int> qlens(nq);
+    for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
+    if (qlens != db->batch_qlens) HIP_TRY(hipStreamSynchronize(st));   // the previous batch may still read the plan
+    Plan* plan = nullptr;
+    if ((s = plan_for(db, qlens, &plan)) != SW_OK) return s;
+    Work W;
+    if ((s = get_work(db, h_qoffsets, nq, k, d_scores == nullptr, plan, d_ws, ws_bytes, &W)) != SW_OK) return s;
+    int32_t* scores = d_scores ? d_scores : W.scores;
+    // zero-length queries score 0 everywhere (outside the captured sequence)
+    for (int q = 0; q < nq; ++q)
+        if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
+    Staged S;
+    if ((s = stage_queries(db, W, h_queries, h_qoffsets, nq, h_subst, n, st, &S, nullptr, d_ws ? plan : nullptr)) != SW_OK)
+        return s;
+    GraphEntry& G = db->graph;
+    const bool hit = G.exec && G.gen == db->gen && G.ws == W.scratch16 && G.qlens == qlens && G.go == gap_open &&
+                     G.ge == gap_extend && G.bias == S.bias && G.k == k && G.scores == scores &&
+                     G.top_s == d_top_scores && G.top_i == d_top_index && G.stream == st;
+    if (!hit) {
+        // captured on the library's own stream (the caller's may be the legacy
+        // default stream, which cannot be captured); launched on the caller's
+        G.clear();
+        HIP_TRY(hipStreamBeginCapture(db->cap, hipStreamCaptureModeThreadLocal));
+        s = enqueue(db, S, *plan, W, gap_open, gap_extend, scores, n, k, d_top_scores, d_top_index, db->cap, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(db->cap, &graph);
+        if (s != SW_OK) { if (graph) hipGraphDestroy(graph); return s; }
+        if (e != hipSuccess) return fail(SW_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { hipGraphDestroy(graph); return fail(SW_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
+        G.graph = graph;
+        G.exec = exec;
+        G.qlens = qlens;
+        G.go = gap_open;
+        G.ge = gap_extend;
+        G.bias = S.bias;
+        G.k = k;
+        G.scores = scores;
+        G.top_s = d_top_scores;
+        G.top_i = d_top_index;
+        G.stream = st;
+        G.gen = db->gen;
+        G.ws = W.scratch16;
+    }
+    const int ev = db->timing ? record_timer_start(db, st) : -1;
+    HIP_TRY(hipGraphLaunch(G.exec, st));
+    if (ev >= 0) {
+        HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
+        db->ev_used.push_back(ev);
+    }
     return SW_OK;
 }
 
@@ -835,107 +1249,24 @@ const char* sw_last_error(void) { return g_err.c_str(); }
 sw_status sw_db_pack(const int8_t* d_residues, const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts,
                      sw_stream stream, sw_db** out) {
     g_err.clear();
-    if (!out) return fail(SW_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (n < 0) return fail(SW_E_INVALID, "n must be >= 0");
-    if (n > ((int64_t)1 << 31) - 256) return fail(SW_E_UNSUPPORTED, "more than 2^31 subjects");
-    if (n > 0 && (!h_offsets || !d_residues)) return fail(SW_E_INVALID, "NULL residues or offsets");
-    if (n > 0 && h_offsets[0] < 0) return fail(SW_E_INVALID, "offsets[0] < 0");
-    std::vector<int32_t> len(n);
-    for (int64_t k = 0; k < n; ++k) {
-        const int64_t l = h_offsets[k + 1] - h_offsets[k];
-        if (l < 0) return fail(SW_E_INVALID, "offsets decrease at %lld", (long long)k);
-        if (l > (1 << 24)) return fail(SW_E_UNSUPPORTED, "subject %lld longer than 2^24", (long long)k);
-        len[k] = (int32_t)l;
-    }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    sw_db* db = new (std::nothrow) sw_db();
-    if (!db) return fail(SW_E_NOMEM, "host allocation failed");
-    auto bail = [&](sw_status s) { sw_db_free(db); return s; };
-    if (hipGetDevice(&db->device) != hipSuccess) return bail(fail(SW_E_HIP, "no current HIP device"));
-    sw_status so = apply_opts(db, opts);
-    if (so != SW_OK) return bail(so);
-    if (opts && (opts->alphabet < 0 || opts->alphabet > kMaxAlphabet))
-        return bail(fail(SW_E_INVALID, "alphabet must be 0 (= 20) or 1..%d", kMaxAlphabet));
-    db->alphabet = (opts && opts->alphabet > 0) ? opts->alphabet : 20;
-    db->n = n;
-    db->off_first = n > 0 ? h_offsets[0] : 0;
-    db->off_last = n > 0 ? h_offsets[n] : 0;
-    db->off_hash = n > 0 ? offsets_hash(h_offsets, n) : 0;
-    db->total_res = db->off_last - db->off_first;
+    return pack_db(d_residues, h_offsets, n, opts, nullptr, 0, static_cast<hipStream_t>(stream), out);
+}
 
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
-    db->ngroups = (int)((n + kGroupSubjects - 1) / kGroupSubjects);
-    const int G = db->ngroups;
-    std::vector<GroupRec> groups(G);
-    std::vector<int64_t> gdw(G);
-    std::vector<int32_t> perm((size_t)G * kGroupSubjects, -1);
-    std::vector<int64_t> soff(n);
-    std::vector<int32_t> slen(n);
-    db->ncols.resize(G);
-    int64_t base = 0;
-    for (int g = 0; g < G; ++g) {
-        const int32_t nc = (int32_t)round_up(len[order[(size_t)g * kGroupSubjects]], kChunkCols);
-        groups[g] = GroupRec{base, nc, g * kGroupSubjects};
-        gdw[g] = base / 4;
-        db->ncols[g] = nc;
-        db->ncols_max = std::max(db->ncols_max, nc);
-        base += (int64_t)nc * kGroupSubjects;
-    }
-    db->pcols.assign((size_t)G * kGroupPairs, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        const size_t pi = (size_t)(i / 2);
-        db->pcols[pi] = std::max<int32_t>(db->pcols[pi], (int32_t)round_up(len[order[i]], kChunkCols));
-        perm[i] = order[i];
-        soff[i] = h_offsets[order[i]];
-        slen[i] = len[order[i]];
-    }
-    db->image_bytes = base;
-    db->lens = len;
-    db->slot_of.assign(n, 0);
-    for (int64_t i = 0; i < n; ++i) db->slot_of[order[i]] = (int32_t)i;
-    db->gbase.resize(G);
-    for (int g = 0; g < G; ++g) db->gbase[g] = groups[g].base;
-    if (G > 0) {
-        DevBuf d_soff, d_slen, d_gdw, d_err;
-        hipError_t e = hipSuccess;
-        if ((e = db->image.reserve(std::max<int64_t>(base, 4))) != hipSuccess ||
-            (e = db->groups.reserve(sizeof(GroupRec) * G)) != hipSuccess ||
-            (e = db->perm.reserve(sizeof(int32_t) * perm.size())) != hipSuccess ||
-            (e = db->pair_cols.reserve(sizeof(int32_t) * db->pcols.size())) != hipSuccess ||
-            (e = d_soff.reserve(sizeof(int64_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
-            (e = d_slen.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1))) != hipSuccess ||
-            (e = d_gdw.reserve(sizeof(int64_t) * G)) != hipSuccess || (e = d_err.reserve(4)) != hipSuccess) {
-            d_soff.release(); d_slen.release(); d_gdw.release(); d_err.release();
-            return bail(fail(e == hipErrorOutOfMemory ? SW_E_NOMEM : SW_E_HIP, "device allocation: %s", hipGetErrorString(e)));
-        }
-        int32_t zero = 0, herr = 0;
-        auto step = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-        step(hipMemcpyAsync(db->groups.p, groups.data(), sizeof(GroupRec) * G, hipMemcpyHostToDevice, st));
-        step(hipMemcpyAsync(db->perm.p, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, st));
-        step(hipMemcpyAsync(db->pair_cols.p, db->pcols.data(), sizeof(int32_t) * db->pcols.size(), hipMemcpyHostToDevice, st));
-        step(hipMemcpyAsync(d_soff.p, soff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-        step(hipMemcpyAsync(d_slen.p, slen.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-        {
-            std::vector<int32_t> sl((size_t)G * kGroupSubjects, 0);
-            std::copy(slen.begin(), slen.end(), sl.begin());
-            if (e == hipSuccess) e = db->slen_sorted.reserve(sizeof(int32_t) * sl.size());
-            step(hipMemcpyAsync(db->slen_sorted.p, sl.data(), sizeof(int32_t) * sl.size(), hipMemcpyHostToDevice, st));
-            step(hipStreamSynchronize(st));
-        }
-        step(hipMemcpyAsync(d_gdw.p, gdw.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
-        step(hipMemcpyAsync(d_err.p, &zero, 4, hipMemcpyHostToDevice, st));
-        step(launch_interleave(d_residues, d_soff.as<int64_t>(), d_slen.as<int32_t>(), n, db->alphabet, db->groups.as<GroupRec>(),
-                               d_gdw.as<int64_t>(), G, db->image.as<uint32_t>(), base / 4, d_err.as<int32_t>(), st));
-        step(hipMemcpyAsync(&herr, d_err.p, 4, hipMemcpyDeviceToHost, st));
-        step(hipStreamSynchronize(st));
-        d_soff.release(); d_slen.release(); d_gdw.release(); d_err.release();
-        if (e != hipSuccess) return bail(fail(SW_E_HIP, "packing: %s", hipGetErrorString(e)));
-        if (herr) return bail(fail(SW_E_RESIDUE, "database residue code outside 0..%d", db->alphabet - 1));
-    }
-    *out = db;
+sw_status sw_db_pack_into(const int8_t* d_residues, const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts,
+                          void* d_db, int64_t db_bytes, sw_stream stream, sw_db** out) {
+    g_err.clear();
+    if (!d_db) return fail(SW_E_INVALID, "d_db is NULL");
+    return pack_db(d_residues, h_offsets, n, opts, d_db, db_bytes, static_cast<hipStream_t>(stream), out);
+}
+
+sw_status sw_db_pack_bytes(const int64_t* h_offsets, int64_t n, const sw_pack_opts* opts, int64_t* bytes) {
+    g_err.clear();
+    (void)opts;                       // the image does not depend on the options
+    if (!bytes) return fail(SW_E_INVALID, "bytes is NULL");
+    PackPlan P;
+    sw_status s = plan_pack(h_offsets, n, &P);
+    if (s != SW_OK) return s;
+    *bytes = db_layout(n, P.G, P.image_bytes).total;
     return SW_OK;
 }
 
@@ -958,11 +1289,10 @@ void sw_db_free(sw_db* db) {
     DeviceGuard dg(db->device);
     hipDeviceSynchronize();
     clear_caches(db);
-    db->image.release(); db->groups.release(); db->perm.release(); db->pair_cols.release();
+    db->image_own.release();           // a caller's image stays the caller's
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
-    db->slen_sorted.release(); db->mode_plan.items.release(); db->topk_ws.release();
-    db->scratch16.release(); db->scratch32.release(); db->prof.release(); db->stage.release();
-    db->counters.release(); db->rerun.release(); db->rerun_bits.release(); db->scores_tmp.release();
+    db->mode_plan.release();
+    db->ws_own.release();
     db->hstage.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (db->side) hipStreamDestroy(db->side);
@@ -978,10 +1308,14 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
     if (!db) return fail(SW_E_INVALID, "db is NULL");
     if (n) *n = db->n;
     if (residues) *residues = db->total_res;
-    if (device_bytes)
-        *device_bytes = (int64_t)(db->image.bytes + db->groups.bytes + db->perm.bytes + db->pair_cols.bytes +
-                                  db->scratch16.bytes + db->scratch32.bytes + db->prof.bytes + db->stage.bytes +
-                                  db->rerun.bytes + db->rerun_bits.bytes + db->scores_tmp.bytes);
+    if (device_bytes) {
+        // everything the handle itself allocated: its image, workspace, plan copies, alignment buffers
+        size_t b = db->image_own.bytes + db->ws_own.bytes + db->align_dirs.bytes + db->align_bnd.bytes +
+                   db->align_misc.bytes + db->mode_plan.items.bytes + db->batch_plan.items.bytes +
+                   db->batch_plan.qpairs.bytes + db->multi_plan.items.bytes + db->multi_plan.qpairs.bytes;
+        for (const auto& kv : db->plans) b += kv.second.items.bytes + kv.second.qpairs.bytes;
+        *device_bytes = (int64_t)b;
+    }
     return SW_OK;
 }
 
@@ -989,28 +1323,17 @@ sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_
                     const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out,
                     sw_stream stream) {
     g_err.clear();
-    sw_status s;
-    if ((s = check_db_args(db, h_offsets, n)) != SW_OK) return s;
-    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
-    if (qlen < 0) return fail(SW_E_INVALID, "qlen must be >= 0");
-    if (qlen > 0 && !h_query) return fail(SW_E_INVALID, "query is NULL");
-    if (n > 0 && !d_scores_out) return fail(SW_E_INVALID, "scores_out is NULL");
-    for (int32_t i = 0; i < qlen; ++i)
-        if (h_query[i] < 0 || h_query[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue %d at %d outside 0..%d", h_query[i], i, db->alphabet - 1);
-    if (n == 0) return SW_OK;
-    std::lock_guard<std::mutex> lk(db->mu);
-    DeviceGuard dg(db->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (qlen == 0) { HIP_TRY(launch_fill(d_scores_out, n, 0, st)); return SW_OK; }
-    if ((s = ensure_workspace(db)) != SW_OK) return s;
-    Plan* plan = nullptr;
-    if ((s = get_plan(db, qlen, &plan)) != SW_OK) return s;
-    const int64_t qo[2] = {0, qlen};
-    const StageLayout L = stage_layout(qo, 1);
-    if ((s = reserve_for(db, L, 1)) != SW_OK) return s;
-    Staged S;
-    if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
-    return enqueue(db, S, *plan, gap_open, gap_extend, d_scores_out, n, 0, nullptr, nullptr, st, true);
+    return search_one(h_query, qlen, db, h_offsets, n, h_subst, gap_open, gap_extend, d_scores_out, nullptr, 0,
+                      static_cast<hipStream_t>(stream));
+}
+
+sw_status sw_search_ws(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets, int64_t n,
+                       const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_scores_out,
+                       void* d_workspace, int64_t ws_bytes, sw_stream stream) {
+    g_err.clear();
+    if (!d_workspace) return fail(SW_E_INVALID, "workspace is NULL");
+    return search_one(h_query, qlen, db, h_offsets, n, h_subst, gap_open, gap_extend, d_scores_out, d_workspace,
+                      ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 sw_status sw_topk(const int32_t* d_scores, int64_t n, int32_t k, int32_t* d_top_scores, int64_t* d_top_index,
@@ -1044,89 +1367,38 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
                           const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* d_scores,
                           int32_t* d_top_scores, int64_t* d_top_index, sw_stream stream) {
     g_err.clear();
+    return search_batch(h_queries, h_qoffsets, nq, db, h_subst, gap_open, gap_extend, k, d_scores, d_top_scores,
+                        d_top_index, nullptr, 0, static_cast<hipStream_t>(stream));
+}
+
+sw_status sw_search_batch_ws(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq, sw_db* db,
+                             const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* d_scores,
+                             int32_t* d_top_scores, int64_t* d_top_index, void* d_workspace, int64_t ws_bytes,
+                             sw_stream stream) {
+    g_err.clear();
+    if (!d_workspace) return fail(SW_E_INVALID, "workspace is NULL");
+    return search_batch(h_queries, h_qoffsets, nq, db, h_subst, gap_open, gap_extend, k, d_scores, d_top_scores,
+                        d_top_index, d_workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+sw_status sw_batch_workspace_bytes(sw_db* db, const int64_t* h_qoffsets, int32_t nq, int32_t k, int32_t scores_in_ws,
+                                   int64_t* bytes) {
+    g_err.clear();
     sw_status s;
-    if (!db) return fail(SW_E_INVALID, "db is NULL");
-    if ((s = check_subst_gaps(h_subst, gap_open, gap_extend)) != SW_OK) return s;
-    if (nq < 0) return fail(SW_E_INVALID, "nq must be >= 0");
-    if (nq > 0 && (!h_qoffsets || !h_queries)) return fail(SW_E_INVALID, "NULL queries or offsets");
+    if (!db || !bytes) return fail(SW_E_INVALID, "NULL argument");
+    if (nq < 0 || (nq > 0 && !h_qoffsets)) return fail(SW_E_INVALID, "bad query offsets");
     if (k < 0 || k > 1024) return fail(SW_E_UNSUPPORTED, "k must be in 0..1024 (got %d)", k);
-    if (k > 0 && (!d_top_scores || !d_top_index)) return fail(SW_E_INVALID, "NULL top-k outputs");
-    if (!d_scores && k == 0) return fail(SW_E_INVALID, "no output requested (scores NULL and k == 0)");
-    for (int q = 0; q < nq; ++q) {
+    for (int q = 0; q < nq; ++q)
         if (h_qoffsets[q + 1] < h_qoffsets[q]) return fail(SW_E_INVALID, "query offsets decrease at %d", q);
-        if (h_qoffsets[q + 1] - h_qoffsets[q] > (1 << 24)) return fail(SW_E_UNSUPPORTED, "query %d too long", q);
-    }
-    if (nq > 0)
-        for (int64_t i = h_qoffsets[0]; i < h_qoffsets[nq]; ++i)
-            if (h_queries[i] < 0 || h_queries[i] >= db->alphabet) return fail(SW_E_RESIDUE, "query residue outside 0..%d at %lld", db->alphabet - 1, (long long)i);
-    if (nq == 0) return SW_OK;
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n = db->n;
+    if ((s = ensure_geometry(db)) != SW_OK) return s;
     std::vector<int> qlens(nq);
     for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
-    int32_t* scores = d_scores;
-    if (!scores) {
-        HIP_TRY(db->scores_tmp.reserve((size_t)nq * std::max<int64_t>(n, 1) * sizeof(int32_t), &db->gen));
-        scores = db->scores_tmp.as<int32_t>();
-    }
-    if (n == 0) {
-        if (k > 0) HIP_TRY(launch_topk(scores, 0, 0, nq, k, d_top_scores, d_top_index, st));
-        return SW_OK;
-    }
-    if ((s = ensure_workspace(db)) != SW_OK) return s;
-    // zero-length queries score 0 everywhere (outside the captured sequence)
-    for (int q = 0; q < nq; ++q)
-        if (qlens[q] == 0) HIP_TRY(launch_fill(scores + (int64_t)q * n, n, 0, st));
-    if (qlens != db->batch_qlens) {
-        HIP_TRY(hipStreamSynchronize(st));          // the previous batch may still read the plan buffer
-        db->batch_qlens.clear();
-        if ((s = build_plan(db, qlens, &db->batch_plan)) != SW_OK) return s;
-        db->batch_qlens = qlens;
-    }
-    const StageLayout L = stage_layout(h_qoffsets, nq);
-    if ((s = reserve_for(db, L, nq)) != SW_OK) return s;
-    if ((s = reserve_topk(db, nq, k)) != SW_OK) return s;
-    Staged S;
-    if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, n, st, &S)) != SW_OK) return s;
-    GraphEntry& G = db->graph;
-    const bool hit = G.exec && G.gen == db->gen && G.qlens == qlens && G.go == gap_open && G.ge == gap_extend &&
-                     G.bias == S.bias && G.k == k && G.scores == scores && G.top_s == d_top_scores && G.top_i == d_top_index &&
-                     G.stream == st;
-    if (!hit) {
-        // captured on the library's own stream (the caller's may be the legacy
-        // default stream, which cannot be captured); launched on the caller's
-        G.clear();
-        HIP_TRY(hipStreamBeginCapture(db->cap, hipStreamCaptureModeThreadLocal));
-        s = enqueue(db, S, db->batch_plan, gap_open, gap_extend, scores, n, k, d_top_scores, d_top_index, db->cap,
-                    false);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(db->cap, &graph);
-        if (s != SW_OK) { if (graph) hipGraphDestroy(graph); return s; }
-        if (e != hipSuccess) return fail(SW_E_HIP, "graph capture: %s", hipGetErrorString(e));
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) { hipGraphDestroy(graph); return fail(SW_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
-        G.graph = graph;
-        G.exec = exec;
-        G.qlens = qlens;
-        G.go = gap_open;
-        G.ge = gap_extend;
-        G.bias = S.bias;
-        G.k = k;
-        G.scores = scores;
-        G.top_s = d_top_scores;
-        G.top_i = d_top_index;
-        G.stream = st;
-        G.gen = db->gen;
-    }
-    const int ev = db->timing ? record_timer_start(db, st) : -1;
-    HIP_TRY(hipGraphLaunch(G.exec, st));
-    if (ev >= 0) {
-        HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
-        db->ev_used.push_back(ev);
-    }
+    Plan* plan = nullptr;
+    if ((s = plan_for(db, qlens, &plan)) != SW_OK) return s;
+    const int64_t zero[1] = {0};
+    *bytes = ws_layout(db, nq ? h_qoffsets : zero, nq, k, scores_in_ws != 0, plan).total;
     return SW_OK;
 }
 
@@ -1152,7 +1424,7 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
     std::lock_guard<std::mutex> lk(db->mu);
     DeviceGuard dg(db->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    if ((s = ensure_geometry(db)) != SW_OK) return s;
     std::vector<int> qlens(nq), chunk(h_chunk, h_chunk + nq);
     for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
     // a zero-length query scores 0 on its chunk: fill its whole vector (other chunks are 0 as well)
@@ -1160,12 +1432,12 @@ sw_status sw_search_multi(const int8_t* h_queries, const int64_t* h_qoffsets, in
         if (qlens[q] == 0) HIP_TRY(launch_fill(h_d_scores[q], db->n, 0, st));
     HIP_TRY(hipStreamSynchronize(st));              // the previous call may still read the plan buffer
     if ((s = build_plan(db, qlens, &db->multi_plan, &chunk, nchunks)) != SW_OK) return s;
-    const StageLayout L = stage_layout(h_qoffsets, nq);
-    if ((s = reserve_for(db, L, nq)) != SW_OK) return s;
-    Staged S;
-    if ((s = stage_queries(db, L, h_queries, h_qoffsets, nq, h_subst, 0, st, &S, h_d_scores)) != SW_OK) return s;
     if (db->multi_plan.n_main + db->multi_plan.n_side == 0) return SW_OK;
-    return enqueue(db, S, db->multi_plan, gap_open, gap_extend, nullptr, db->n, 0, nullptr, nullptr, st, true);
+    Work W;
+    if ((s = get_work(db, h_qoffsets, nq, 0, false, &db->multi_plan, nullptr, 0, &W)) != SW_OK) return s;
+    Staged S;
+    if ((s = stage_queries(db, W, h_queries, h_qoffsets, nq, h_subst, 0, st, &S, h_d_scores)) != SW_OK) return s;
+    return enqueue(db, S, db->multi_plan, W, gap_open, gap_extend, nullptr, db->n, 0, nullptr, nullptr, st, true);
 }
 
 sw_status sw_profile_kernels(sw_db* db, int32_t enable) {
@@ -1195,9 +1467,9 @@ sw_status sw_last_stats(sw_db* db, int64_t out[8]) {
     if (!db || !out) return fail(SW_E_INVALID, "NULL argument");
     DeviceGuard dg(db->device);
     int32_t c[kCounters] = {};
-    if (db->counters.p) {
+    if (db->last_counters) {
         HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipMemcpy(c, db->counters.p, sizeof c, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(c, db->last_counters, sizeof c, hipMemcpyDeviceToHost));
     }
     out[0] = db->last_items;
     out[1] = c[1];
@@ -1316,7 +1588,7 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
             const int32_t slot = db->slot_of[sub];
             const int g = slot / kGroupSubjects, w = slot % kGroupSubjects;
             AlignPair& P = pairs[i];
-            P.residues = db->image.as<uint8_t>() + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
+            P.residues = db->d_image + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
             P.n = J.n;
             P.m = J.m;
             P.query = reinterpret_cast<const int8_t*>(mb + o_query + qpos[J.q]);
@@ -1411,7 +1683,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         HIP_TRY(hipStreamSynchronize(st));
         return SW_OK;
     }
-    if ((s = ensure_workspace(db)) != SW_OK) return s;
+    if ((s = ensure_geometry(db)) != SW_OK) return s;
     if (db->wg_mode == 0) {
         int b1 = 0, b2 = 0;
         HIP_TRY(sweep_occupancy_mode16(SW_GLOBAL, 16, &b1));
@@ -1458,35 +1730,22 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     mi.insert(mi.end(), m32.begin(), m32.end());
     if (n_items) HIP_TRY(hipMemcpy(db->mode_plan.items.p, mi.data(), sizeof(WgItem) * n_items, hipMemcpyHostToDevice));
     const int64_t qo[2] = {0, qlen};
-    const StageLayout L = stage_layout(qo, 1);
-    if ((s = reserve_for(db, L, 1)) != SW_OK) return s;
+    Work W;
+    if ((s = get_work(db, qo, 1, 0, false, nullptr, nullptr, 0, &W)) != SW_OK) return s;
     Staged S;
-    if ((s = stage_queries(db, L, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
-    int32_t* ctr = db->counters.as<int32_t>();
-    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, db->prof.as<int16_t>(), ctr, kCounters,
-                           db->rerun_bits.as<uint32_t>(), rerun_words(db, 1), S.max_mp, st));
-    SweepArgs a{};
+    if ((s = stage_queries(db, W, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
+    int32_t* ctr = W.counters;
+    HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, W.prof, ctr, kCounters, W.bits, W.L.bits_words,
+                           S.max_mp, st));
+    SweepArgs a = sweep_args(db, S, W, gap_open, gap_extend, d_scores_out);
     a.items = db->mode_plan.items.as<WgItem>();
     a.n_items = (int32_t)n16;
     a.counter = ctr + 0;
-    a.image = db->image.as<uint8_t>();
-    a.groups = db->groups.as<GroupRec>();
-    a.perm = db->perm.as<int32_t>();
-    a.pair_cols = db->pair_cols.as<int32_t>();
-    a.prof = db->prof.as<int16_t>();
-    a.qd = S.qd;
-    a.go = gap_open;
-    a.ge = gap_extend;
-    a.scratch = db->scratch16.as<uint32_t>();
-    a.slot_words = db->slot_cap * 2;
-    a.slot_base = 0;
-    a.scores = d_scores_out;
-    set_rerun_args(db, a, 1, ctr);
+    set_rerun_args(db, a, W, ctr);
     a.unit_list = 0;
     // every value carries the bias; a pair whose H leaves [128, sat) is recomputed
     a.bias = bias;
     a.sat = db->sat < kSat16 ? std::min<int32_t>(bias + db->sat, kModeTop) : kModeTop;
-    a.slen = db->slen_sorted.as<int32_t>();
     // the 16-bit side launch takes the first slots; the 16-bit bulk launch fills the rest
     const int grid_side = n16s ? std::min<int>((int)n16s, std::max(1, db->wg_mode / 8)) : 0;
     const int grid = std::max(1, std::min<int>(db->wg_mode - grid_side, std::max<int>((int)n16, 1)));
@@ -1511,7 +1770,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         b.items = db->mode_plan.items.as<WgItem>() + n16 + n16s;
         b.n_items = (int32_t)m32.size();
         b.counter = ctr + 4;
-        b.scratch = db->scratch32.as<uint32_t>();
+        b.scratch = W.scratch32;
         b.slot_words = (int64_t)std::max<int32_t>(db->ncols_max, 4) * 4;
         b.rerun = nullptr;
         b.rerun_count = nullptr;
@@ -1532,7 +1791,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         db->ev_used.push_back(ev);
     }
     // exact 32-bit recompute of the pairs that left the range; the count is read on the device
-    SweepArgs r = recompute_args(db, a, ctr);
+    SweepArgs r = recompute_args(db, a, W, ctr);
     r.bias = 0;
     HIP_TRY(launch_sweep_mode(mode, kRerunRows, r, db->wg32, st));
     db->last_items = (int)n16;
@@ -1540,5 +1799,6 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     db->last_side_items = (int)(n16s + m32.size());
     db->last_side_rows = n16s ? db->mode_plan.R_side : m32.empty() ? 0 : R32;
     db->last_grid = grid + grid_side;
+    db->last_counters = ctr;
     return SW_OK;
 }
