@@ -204,15 +204,17 @@ def workload2_queries():
     return qs
 
 
-def workload3_queries(db: Database, nq: int = 256):
-    """``nq`` queries with lengths uniform 50..5,000; each embeds a mutated DB subject."""
+def workload3_queries(db: Database, nq: int = 256, with_sources: bool = False):
+    """``nq`` queries with lengths uniform 50..5,000; each embeds a mutated DB subject
+    (``with_sources``: also return those subjects' indices)."""
     rng = rng_for(3, 2)
-    qs = []
+    qs, sources = [], []
     _, block, _ = _wl2_queries()
     for i in range(nq):
         m = int(rng.integers(50, 5001))
         q = background_residues(rng, m)
-        src = db.subject(int(rng.integers(0, db.n)))
+        sources.append(int(rng.integers(0, db.n)))
+        src = db.subject(sources[-1])
         hom = mutate(rng, src, float(rng.uniform(0.05, 0.4)), 0.01)[:m]
         at = int(rng.integers(0, m - hom.size + 1))
         q[at:at + hom.size] = hom
@@ -221,6 +223,8 @@ def workload3_queries(db: Database, nq: int = 256):
     k = int(np.argmax([q.size for q in qs]))
     if qs[k].size >= SENTINEL_BLOCK + 20:
         qs[k][10:10 + SENTINEL_BLOCK] = block
+    if with_sources:
+        return qs, np.array(sources, dtype=np.int64)
     return qs
 
 
