@@ -342,13 +342,79 @@ def cpu_align_baseline(queries, tops, db, sm, seconds: float):
                       f"{cells:.3e} cells in {dt:.1f} s", "host": host_report()}
 
 
+PAIR_CELL_OPS = 8
+
+
+def pair_bench(args, perfmodel):
+    """One long pair spread over the GPU (sw_pair): two sequences of --pair-len residues with a
+    mutated shared stretch, the tiles of one anti-diagonal per launch."""
+    import torch
+    import paper_2309_09609_amd as sw
+    from inputs import blosum62, synth
+    sm = blosum62()
+    L = args.pair_len
+    rng = synth.rng_for(6, 1)
+    q = synth.background_residues(rng, L)
+    d = synth.background_residues(rng, L)
+    hom = synth.mutate(rng, q[L // 4: L // 4 + L // 2], 0.3, 0.02)[: L // 2]
+    d[L // 5: L // 5 + hom.size] = hom
+    ws = torch.empty(sw.sw_pair_workspace_bytes(L, L), dtype=torch.uint8, device="cuda")
+    score = torch.empty(1, dtype=torch.int32, device="cuda")
+    for i in range(args.warmup):
+        sw.sw_pair(q, d, sm, 10, 2, d_score=score, d_ws=ws)
+        torch.cuda.synchronize()
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        sw.sw_pair(q, d, sm, 10, 2, d_score=score, d_ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    cells = L * L
+    peak = perfmodel.int_valu_lane_ops_per_s()
+    achieved = PAIR_CELL_OPS * cells / (ms * 1e-3)
+    launches = (L + 255) // 256 + (L + 255) // 256 - 1
+    res = {
+        "metric": "GCUPS of one long pair spread over the GPU", "value": round(cells * args.steps / el / 1e9, 2),
+        "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"pair{L // 1000}k", "form": "pair (sw_pair)", "query_len": L, "subject_len": L,
+                   "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
+        # 8 int32 lane-operations per cell (diagonal add, three-input maximum for H, H - Go, two extension
+        # subtractions, two three-input maxima with the floor, the running maximum); one wave per tile and
+        # at most one tile per 256 x 256 block of an anti-diagonal in flight, so the whole-GPU fraction is
+        # bounded by the pair's own wavefront parallelism
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(peak / 1e12, 3),
+                     "unit": "TOP/s (int32 lane-ops)", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_pair_tile", "launches_per_step": launches,
+                     "avg_launch_ms": round(ms / launches, 4), "ops_per_cell": PAIR_CELL_OPS},
+        "extra": {"score": int(score.item()), "event_ms_per_step": round(ms, 3)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        n = min(L, 20_000)
+        t = time.perf_counter()
+        want = oracle.pair(q[:n], d[:n], sm, 10, 2)
+        dt = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": round(n * n / dt / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {n} x {n} residues of the pair ({n * n:.2e} cells, one thread: "
+                                         f"one pair is one serial recurrence in the oracle) in {dt:.1f} s",
+                               "score": int(want), "host": host_report()}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256", "serve10M"])
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "align"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "align", "pair"])
+    ap.add_argument("--pair-len", type=int, default=100_000, help="pair form: residues of each sequence")
     ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
@@ -390,6 +456,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if args.form == "pair":
+        return pair_bench(args, perfmodel)
     sm = blosum62()
     t = time.perf_counter()
     queries, db, desc = workload(args.workload)

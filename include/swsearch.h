@@ -361,6 +361,28 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
                          const int64_t* h_subjects, const int64_t* h_soffsets, const int8_t* h_subst, int32_t gap_open,
                          int32_t gap_extend, sw_alignment* h_out, char* h_ops, int64_t ops_stride, sw_stream stream);
 
+/*
+ * sw_pair - the Smith-Waterman score (Eq. 1-3) of one pair of long sequences,
+ * spread over the whole GPU (intra-task parallelism, Sec. II-B; one-to-one
+ * alignment of long sequences, Sec. III-A).  The matrix is cut into tiles of
+ * 256 query rows by 128 or 256 subject columns; the tiles of one
+ * anti-diagonal are independent and run in one launch (one wave each), so a
+ * pair of m x n residues takes about m/256 + n/256 launches and no
+ * workgroup waits for another.  int32 cells.
+ *   h_query, h_subject : host residue codes 0..alphabet-1 (validated).
+ *   alphabet           : 0 (= 20) or 1..24;  h_subst : host int8[alphabet^2].
+ *   d_score            : device int32, receives S (0 for an empty sequence).
+ *   d_workspace        : device, 256-byte aligned, ws_bytes >= sw_pair_workspace_bytes
+ *                        (about 8 (m + n) bytes plus the sequences); may be NULL when
+ *                        either length is 0.
+ * SW_E_UNSUPPORTED when 127 x min(m, n) could exceed int32.  Asynchronous on
+ * the stream; the workspace must stay untouched until it completes.
+ */
+sw_status sw_pair_workspace_bytes(int64_t qlen, int64_t slen, int64_t* bytes);
+sw_status sw_pair(const int8_t* h_query, int64_t qlen, const int8_t* h_subject, int64_t slen, int32_t alphabet,
+                  const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, int32_t* d_score,
+                  void* d_workspace, int64_t ws_bytes, sw_stream stream);
+
 /* Human-readable name of a status code (static string). */
 const char* sw_status_str(sw_status s);
 /* Description of the most recent error on the calling thread ("" if none). */

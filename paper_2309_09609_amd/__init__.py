@@ -26,7 +26,7 @@ STATUS = {0: "SW_OK", -1: "SW_E_INVALID", -2: "SW_E_RESIDUE", -3: "SW_E_NOMEM", 
 
 # Every entry point declared in include/swsearch.h.
 EXPORTS = ("sw_db_pack", "sw_db_pack_bytes", "sw_db_pack_into", "sw_search_ws", "sw_batch_workspace_bytes",
-           "sw_search_batch_ws", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
+           "sw_search_batch_ws", "sw_pair_workspace_bytes", "sw_pair", "sw_db_tune", "sw_db_free", "sw_db_info", "sw_search", "sw_topk", "sw_search_batch",
            "sw_search_multi", "sw_align", "sw_align_batch", "sw_search_mode", "sw_topk_ws_bytes", "sw_topk_ws", "sw_topk_noalloc",
            "sw_status_str", "sw_last_error", "sw_last_stats", "sw_profile_kernels", "sw_kernel_times")
 
@@ -60,6 +60,10 @@ def load():
     lib.sw_batch_workspace_bytes.argtypes = [P, P, I32, I32, I32, P]
     lib.sw_search_batch_ws.restype = I32
     lib.sw_search_batch_ws.argtypes = [P, P, I32, P, P, I32, I32, I32, P, P, P, P, I64, P]
+    lib.sw_pair_workspace_bytes.restype = I32
+    lib.sw_pair_workspace_bytes.argtypes = [I64, I64, P]
+    lib.sw_pair.restype = I32
+    lib.sw_pair.argtypes = [P, I64, P, I64, I32, P, I32, I32, P, P, I64, P]
     lib.sw_db_tune.restype = I32
     lib.sw_db_tune.argtypes = [P, P]
     lib.sw_db_free.restype = None
@@ -213,6 +217,30 @@ def sw_search_batch_ws(h_queries, h_qoffsets, handle, subst, gap_open, gap_exten
     _check(lib.sw_search_batch_ws(_ptr(q), _ptr(qo), qo.size - 1, handle, _ptr(sm), int(gap_open), int(gap_extend),
                                   int(k), P(d_scores), P(d_top_scores), P(d_top_index), _ptr(d_ws),
                                   d_ws.numel() * d_ws.element_size(), _stream(stream)))
+
+
+def sw_pair_workspace_bytes(qlen, slen) -> int:
+    out = ctypes.c_int64()
+    _check(load().sw_pair_workspace_bytes(int(qlen), int(slen), ctypes.byref(out)))
+    return out.value
+
+
+def sw_pair(query, subject, subst, gap_open=10, gap_extend=2, alphabet=0, d_score=None, d_ws=None, stream=None):
+    """Score of one (long) pair spread over the GPU; returns the device int32 score tensor [1].
+    The workspace comes from torch unless ``d_ws`` is given."""
+    import torch
+    q, d = _host_i8(query), _host_i8(subject)
+    sm = _square(subst)
+    if d_score is None:
+        d_score = torch.empty(1, dtype=torch.int32, device="cuda")
+    if d_ws is None:
+        need = sw_pair_workspace_bytes(q.size, d.size)
+        d_ws = torch.empty(max(need, 1), dtype=torch.uint8, device=d_score.device)
+    _check(load().sw_pair(_ptr(q), q.size, _ptr(d), d.size, int(alphabet), _ptr(sm), int(gap_open), int(gap_extend),
+                          _ptr(d_score), _ptr(d_ws), d_ws.numel(), _stream(stream)))
+    if stream is not None:
+        d_ws.record_stream(stream)
+    return d_score
 
 
 def sw_search(query, handle, h_offsets, n, subst, gap_open, gap_extend, d_scores_out, stream=None):

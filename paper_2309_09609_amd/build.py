@@ -17,8 +17,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libswsearch.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sw_kernels.hip", "sw_align.hip", "sw_noalloc.hip",
-                                                           "sw_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sw_kernels.hip", "sw_align.hip", "sw_pair.hip",
+                                                           "sw_noalloc.hip", "sw_api.cpp")]
 HIP_SOURCES = [s for s in SOURCES if s.endswith(".hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

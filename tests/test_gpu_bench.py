@@ -29,3 +29,14 @@ def test_bench_line_on_the_small_workload():
     assert roof["bound"] == "alu" and 0 < roof["frac"] <= 1 and roof["launches"] >= 1
     assert roof["traffic"] is None                     # measured for the 570k-subject workload only
     assert d["cpu_baseline"]["kind"] == "oracle" and d["cpu_baseline"]["value"] > 0
+
+
+def test_bench_line_of_the_pair_form():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--form", "pair", "--pair-len", "20000",
+                        "--steps", "2", "--warmup", "1"], capture_output=True, text=True, timeout=110)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = json.loads([l for l in r.stdout.splitlines() if l.startswith("{")][0])
+    assert d["config"]["workload"] == "pair20k" and d["value"] > 0
+    assert 0 < d["roofline"]["frac"] <= 1
+    # the GPU score equals the oracle's on the same pair (the baseline leg runs the whole 20k x 20k pair)
+    assert d["cpu_baseline"]["score"] == d["extra"]["score"]
