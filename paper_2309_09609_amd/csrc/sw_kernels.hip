@@ -436,8 +436,15 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
     for (int i = 0; i < W; ++i) bw[i] = ld128(io.bnd, io.rd_lane + 16u * i);
 
     RV rr = resid(c0, c1);
-    uint32_t cur[R];
+    // Profile values are read from LDS two steps before the step that uses them (cur: this step,
+    // nxt: the next), so each read has a whole step of cell updates to complete in, whatever waits the
+    // compiler places; a lone wave (a long subject's chain) would otherwise stall on LDS every few steps.
+    // 32-bit cells and query pairs keep one step of lead (the registers of a second one would lower
+    // their occupancy).
+    constexpr bool kLead2 = std::is_same<C, CellI16>::value && !PACKED;
+    uint32_t cur[R], nxt[R];
     fetch<R, PACKED>(lrow, rr, 0, cur);
+    if constexpr (kLead2) fetch<R, PACKED>(lrow, rr, 1, nxt);
     for (int c = 0; c < nloop; ++c) {
         const RV c3 = res_at(coff + c + 3);
         uint4 nw[W];
@@ -446,9 +453,14 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
         const RV rn = resid(c1, c2);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            uint32_t nxt[R];
-            if (u < 3) fetch<R, PACKED>(lrow, rr, u + 1, nxt);
-            else fetch<R, PACKED>(lrow, rn, 0, nxt);
+            uint32_t nx2[R];
+            if constexpr (kLead2) {
+                if (u < 2) fetch<R, PACKED>(lrow, rr, u + 2, nx2);
+                else fetch<R, PACKED>(lrow, rn, u - 2, nx2);
+            } else {
+                if (u < 3) fetch<R, PACKED>(lrow, rr, u + 1, nxt);
+                else fetch<R, PACKED>(lrow, rn, 0, nxt);
+            }
             T htop, ftop;
             C::col(bw, u, htop, ftop);
             if (COOP) {
@@ -520,7 +532,10 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
                 up_f = C::shift(F);
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+            for (int r = 0; r < R; ++r) {
+                cur[r] = nxt[r];
+                if constexpr (kLead2) nxt[r] = nx2[r];
+            }
         }
         c0 = c1;
         c1 = c2;
