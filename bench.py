@@ -136,10 +136,10 @@ def cpu_baseline(queries, db, sm, seconds: float, mode: str = "local"):
 
 
 def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
-    """Served form: continuous batching vs plain FIFO on one Poisson trace."""
+    """Served form: the serving policies against plain FIFO on one Poisson trace."""
     import torch
     from inputs import synth
-    from paper_2309_09609_amd.serve import GpuEngine, Server, batch_run, fifo_run
+    from paper_2309_09609_amd.serve import GpuEngine, Server, batch_run, fifo_run, paired_run
     warm = 10
     qs = synth.workload5_queries(warm + args.requests + 5)
     cells = lambda q: int(q.size) * total_res  # noqa: E731
@@ -159,9 +159,11 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     print(f"# plain service time {service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
     trace = qs[: warm + args.requests]
     arrivals = synth.poisson_arrivals(rate, len(trace))
-    pols = set(args.policies.split(","))
-    if not {"served", "plain"} <= pols:
-        raise SystemExit("--policies must include served and plain")
+    pols = [p for p in args.policies.split(",") if p]
+    known = {"plain", "paired", "pipelined", "served", "dynamic", "dynamic-q2", "srpt"}
+    if "plain" not in pols or len(set(pols)) < 2 or not set(pols) <= known:
+        raise SystemExit(f"--policies: plain and at least one of {sorted(known - {'plain'})}")
+    headline = args.headline if args.headline in pols else [p for p in pols if p != "plain"][0]
 
     def progress(name):
         step = max(1, args.requests // 5)
@@ -171,64 +173,57 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
                 print(f"# {name}: {done}/{total} requests done", file=sys.stderr, flush=True)
         return cb
 
-    D.tune(lane_pack=args.lane_pack)
-    eng = GpuEngine(D, sm, 10, 2, k=10)
-    srv = Server(eng, nchunks=args.chunks, mem_budget=2 << 30)
-    srv.run(trace[:warm], arrivals[:warm] - arrivals[0])
-    print("# served: warm-up done", file=sys.stderr, flush=True)
-    rep = srv.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells, progress=progress("served"))
-    served = rep.summary()
-    D.tune()
-    print(f"# served: {served}", file=sys.stderr, flush=True)
-    fifo_rep = fifo_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells,
-                        progress=progress("plain FIFO"))
-    fifo = fifo_rep.summary()
-    print(f"# plain FIFO: {fifo}", file=sys.stderr, flush=True)
-    dyn_rep, dyn, dyn_reps = None, None, {}
-    for pol, lp in (("dynamic", 1), ("dynamic-q2", 2)):
-        if pol not in pols:
-            continue
-        D.tune(lane_pack=lp)
-        batch_run(D, trace[:warm], arrivals[:warm] - arrivals[0], sm)
-        r = batch_run(D, trace[warm:], arrivals[warm:] - arrivals[warm], sm, cells_per_query=cells,
-                      progress=progress(pol))
+    def run_policy(pol, tr, arr, **kw):
+        """One policy on a trace; the knobs it runs with are applied first and reset afterwards."""
+        if pol == "plain":
+            return fifo_run(D, tr, arr, sm, **kw)
+        if pol in ("paired", "pipelined"):
+            if pol == "paired":
+                D.tune(lane_pack=2, force_lanes=2)
+            ratio = args.pair_ratio if pol == "paired" else 2.0        # above 1: never pairs
+            r = paired_run(D, tr, arr, sm, ratio=ratio, depth=2, **kw)
+        elif pol == "served":
+            D.tune(lane_pack=args.lane_pack)
+            r = Server(GpuEngine(D, sm, 10, 2, k=10), nchunks=args.chunks, mem_budget=2 << 30).run(tr, arr, **kw)
+        elif pol in ("dynamic", "dynamic-q2"):
+            D.tune(lane_pack=2 if pol == "dynamic-q2" else 1)
+            r = batch_run(D, tr, arr, sm, **kw)
+        else:   # srpt: one request at a time, least remaining work first at every chunk boundary
+            r = Server(GpuEngine(D, sm, 10, 2, k=10), nchunks=args.chunks, mem_budget=2 << 30, max_active=1,
+                       policy="srpt").run(tr, arr, **kw)
         D.tune()
-        dyn_reps[pol] = r
-        print(f"# {pol}: {r.summary()}", file=sys.stderr, flush=True)
-    if dyn_reps:
-        dyn_rep = dyn_reps.get("dynamic-q2", dyn_reps.get("dynamic"))
-        dyn = dyn_rep.summary()
-    if "srpt" in pols:
-        # one request on the GPU at a time, chosen at every chunk boundary by least remaining work:
-        # a short query that arrives overtakes a long one within 1/chunks of a search
-        srv1 = Server(GpuEngine(D, sm, 10, 2, k=10), nchunks=args.chunks, mem_budget=2 << 30, max_active=1,
-                      policy="srpt")
-        srv1.run(trace[:warm], arrivals[:warm] - arrivals[0])
-        r = srv1.run(trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells, progress=progress("srpt"))
-        dyn_reps["srpt"] = r
-        print(f"# srpt: {r.summary()}", file=sys.stderr, flush=True)
+        return r
+
+    reps = {}
+    for pol in pols:
+        run_policy(pol, trace[:warm], arrivals[:warm] - arrivals[0])
+        reps[pol] = run_policy(pol, trace[warm:], arrivals[warm:] - arrivals[warm], cells_per_query=cells,
+                               progress=progress(pol))
+        print(f"# {pol}: {reps[pol].summary()}", file=sys.stderr, flush=True)
+    fifo_rep = reps["plain"]
+    fifo, served = fifo_rep.summary(), reps[headline].summary()
     # every policy must return the same top-10 for every request
-    others = [rep] + list(dyn_reps.values())
     same = all(np.array_equal(fifo_rep.results[i][0], o.results[i][0]) and
-               np.array_equal(fifo_rep.results[i][1], o.results[i][1]) for o in others for i in fifo_rep.results)
+               np.array_equal(fifo_rep.results[i][1], o.results[i][1]) for o in reps.values() for i in fifo_rep.results)
+    forms = {"paired": "served (length-paired FIFO, query pairs, pipelined launches)",
+             "pipelined": "served (FIFO, pipelined launches)", "served": "served (continuous batching)",
+             "dynamic": "served (dynamic batching)", "dynamic-q2": "served (dynamic batching, query pairs)",
+             "srpt": "served (least remaining work first, chunk preemption)"}
     res = {
         "metric": METRIC, "value": round(served["gcups"], 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.requests,
         "warmup": warm, "ms_per_step": round(served["makespan_s"] / args.requests * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int16x2 saturating + int32 recompute", "data": "synthetic",
-        "config": {"workload": "serve10M", "form": "served (continuous batching)", "subjects": db.n,
+        "config": {"workload": "serve10M", "form": forms[headline], "subjects": db.n,
                    "residues": total_res, "requests": args.requests, "arrival_rate_per_s": round(rate, 3),
-                   "load_vs_plain": args.load, "chunks": args.chunks, "mem_budget_bytes": 2 << 30,
-                   "lane_pack": args.lane_pack,
+                   "load_vs_plain": args.load, "pair_ratio": args.pair_ratio, "chunks": args.chunks,
                    "matrix": "BLOSUM62", "gap_open": 10, "gap_extend": 2},
-        "latency": {"served_p50_s": round(served["p50_s"], 4), "served_p99_s": round(served["p99_s"], 4),
-                    "dynamic_batching_p50_s": round(dyn["p50_s"], 4) if dyn else None,
-                    "dynamic_batching_p99_s": round(dyn["p99_s"], 4) if dyn else None,
+        "latency": {"served_policy": headline, "served_p50_s": round(served["p50_s"], 4),
+                    "served_p99_s": round(served["p99_s"], 4),
                     "plain_p50_s": round(fifo["p50_s"], 4), "plain_p99_s": round(fifo["p99_s"], 4),
                     "p99_gain": round(fifo["p99_s"] / served["p99_s"], 3) if served["p99_s"] > 0 else None},
-        "extra": {"served": served, "plain_fifo": fifo, "dynamic_batching": dyn,
-                  "other_policies": {k: v.summary() for k, v in dyn_reps.items()},
-                  "same_top10_all_policies": same,
+        "extra": {"policies": {k: v.summary() for k, v in reps.items()}, "same_top10_all_policies": same,
+                  "plain_service_ms": round(service * 1e3, 2),
                   "pct_int32_cell_peak": round(100 * served["gcups"] / perfmodel.mi355x_peak_gcups(), 2)},
     }
     D.close()
@@ -420,10 +415,16 @@ def main():
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")
     ap.add_argument("--lane-pack", type=int, default=1, choices=[1, 2],
                     help="served form: 2 = requests that share an iteration share lanes two queries at a time")
-    ap.add_argument("--policies", default="served,plain,dynamic-q2",
-                    help="served form: comma list of served, plain (both required), dynamic (batches of waiting "
-                         "requests, subject pairs per lane), dynamic-q2 (the same with query pairs per lane), srpt "
-                         "(one request at a time, least remaining work first at every chunk boundary)")
+    ap.add_argument("--policies", default="plain,paired,pipelined",
+                    help="served form: comma list, run in this order on the same trace: plain (FIFO, one search "
+                         "per request; required), paired (FIFO with length-matched query pairs, pipelined "
+                         "launches), pipelined (FIFO, pipelined launches, no pairs), served (continuous batching "
+                         "over database chunks), dynamic (batches of waiting requests, subject pairs per lane), "
+                         "dynamic-q2 (the same with query pairs per lane), srpt (one request at a time, least "
+                         "remaining work first at every chunk boundary)")
+    ap.add_argument("--headline", default="paired", help="served form: the policy whose figures the line reports")
+    ap.add_argument("--pair-ratio", type=float, default=0.85,
+                    help="served form, paired policy: the shorter query of a pair is at least this share of the longer")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
     ap.add_argument("--mode", default="local", choices=["local", "global", "semiglobal"],
                     help="plain form: alignment mode (global and semi-global run in biased 16-bit cells, exact)")

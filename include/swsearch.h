@@ -231,8 +231,11 @@ sw_status sw_topk_noalloc(const int32_t* d_scores, int64_t n, int32_t k, int32_t
  *                or NULL to keep only the top k (then k must be >= 1).
  *   d_top_scores : device int32[nq * k] or NULL when k == 0.
  *   d_top_index  : device int64[nq * k] or NULL when k == 0.
- * The launch sequence for a given batch shape is captured once as a HIP graph
- * and replayed on later calls with the same shape.
+ * A batch shape (query lengths, penalties, k, output and workspace
+ * addresses, stream) that comes twice in a row is captured as a HIP graph on
+ * the second call and replayed on later calls with that shape; a shape seen
+ * once is enqueued directly.  A new query-length mix waits for the stream's
+ * earlier work (the handle's plan buffer is replaced).
  */
 sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32_t nq,
                           sw_db* db, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
@@ -250,8 +253,11 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
  * sw_search_batch_ws - sw_search_batch on a caller-owned workspace of
  * ws_bytes >= that size (SW_E_SIZE otherwise), 256-byte aligned.  Allocates
  * no device memory; the captured graph of a batch shape is tied to the
- * workspace address (another address captures again).  The workspace must
- * stay untouched until the stream has completed the call.
+ * workspace address (another address captures again).  The plan travels
+ * with the queries into the workspace, in stream order, so the call never
+ * waits for earlier work, and calls may be queued back to back on one
+ * stream (a serving loop keeps the next batch queued while one runs).  The
+ * workspace must stay untouched until the stream has completed the call.
  */
 sw_status sw_batch_workspace_bytes(sw_db* db, const int64_t* h_qoffsets, int32_t nq, int32_t k,
                                    int32_t scores_in_ws, int64_t* bytes);

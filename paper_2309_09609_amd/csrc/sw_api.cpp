@@ -11,8 +11,8 @@
 // launch pulls them from an atomic counter.  The long pairs of a short query
 // run on a second stream with fewer rows per lane.  Pairs whose 16-bit score
 // saturates are appended to a list that a 32-bit launch consumes.  The launch
-// sequence itself allocates nothing, so the batched form captures it once per
-// batch shape as a HIP graph and replays it.
+// sequence itself allocates nothing, so the batched form captures a batch
+// shape that comes twice in a row as a HIP graph and replays it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -155,12 +155,33 @@ struct GraphEntry {
     const void* ws = nullptr;         // workspace base the sequence was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;        // recorded after every launch of exec
+    bool launched = false;
     void clear() {
+        if (exec && launched && done) hipEventSynchronize(done);   // the last launch may still run
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
+        launched = false;
         qlens.clear();
+    }
+};
+
+// The inputs that decide a batched launch sequence; a shape is captured into a graph the second time
+// it comes in a row (one-off shapes, e.g. served batches, are enqueued directly and never wait).
+struct BatchKey {
+    std::vector<int> qlens;
+    int32_t go = 0, ge = 0, k = 0, bias = 0;
+    const void* scores = nullptr;
+    const void* top_s = nullptr;
+    const void* top_i = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t gen = 0;
+    const void* ws = nullptr;
+    bool operator==(const BatchKey& o) const {
+        return qlens == o.qlens && go == o.go && ge == o.ge && k == o.k && bias == o.bias && scores == o.scores &&
+               top_s == o.top_s && top_i == o.top_i && stream == o.stream && gen == o.gen && ws == o.ws;
     }
 };
 
@@ -224,6 +245,7 @@ struct sw_db {
     Plan batch_plan, multi_plan;
     std::vector<int> batch_qlens;
     GraphEntry graph;                 // batched form: last captured shape
+    BatchKey last_eager;              // batched form: the last shape enqueued without a graph
     // tuning knobs and test hooks
     int force_lgB = -1;               // fixed lanes per pair
     int force_R = 0;                  // fixed rows per lane (4, 8, 16)
@@ -556,6 +578,7 @@ void clear_caches(sw_db* db) {
     db->multi_plan.n_main = db->multi_plan.n_side = 0;
     db->batch_qlens.clear();
     db->graph.clear();
+    db->last_eager = BatchKey();
 }
 
 sw_status check_subst_gaps(const int8_t* subst, int32_t go, int32_t ge) {
@@ -1160,7 +1183,9 @@ sw_status search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32
     if ((s = ensure_geometry(db)) != SW_OK) return s;
     std::vector<int> qlens(nq);
     for (int q = 0; q < nq; ++q) qlens[q] = (int)(h_qoffsets[q + 1] - h_qoffsets[q]);
-    if (qlens != db->batch_qlens) HIP_TRY(hipStreamSynchronize(st));   // the previous batch may still read the plan
+    // On the handle's workspace the plan's device copy may still be read by the previous batch; a caller's
+    // workspace receives the plan with the queries, in stream order, so nothing waits.
+    if (!d_ws && qlens != db->batch_qlens) HIP_TRY(hipStreamSynchronize(st));
     Plan* plan = nullptr;
     if ((s = plan_for(db, qlens, &plan)) != SW_OK) return s;
     Work W;
@@ -1173,9 +1198,32 @@ sw_status search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32
     if ((s = stage_queries(db, W, h_queries, h_qoffsets, nq, h_subst, n, st, &S, nullptr, d_ws ? plan : nullptr)) != SW_OK)
         return s;
     GraphEntry& G = db->graph;
+    BatchKey key;
+    key.qlens = qlens;
+    key.go = gap_open;
+    key.ge = gap_extend;
+    key.k = k;
+    key.bias = S.bias;
+    key.scores = scores;
+    key.top_s = d_top_scores;
+    key.top_i = d_top_index;
+    key.stream = st;
+    key.gen = db->gen;
+    key.ws = W.scratch16;
     const bool hit = G.exec && G.gen == db->gen && G.ws == W.scratch16 && G.qlens == qlens && G.go == gap_open &&
                      G.ge == gap_extend && G.bias == S.bias && G.k == k && G.scores == scores &&
                      G.top_s == d_top_scores && G.top_i == d_top_index && G.stream == st;
+    if (!hit && !(key == db->last_eager)) {
+        db->last_eager = key;
+        const int ev = db->timing ? record_timer_start(db, st) : -1;
+        s = enqueue(db, S, *plan, W, gap_open, gap_extend, scores, n, k, d_top_scores, d_top_index, st, false);
+        if (s != SW_OK) return s;
+        if (ev >= 0) {
+            HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
+            db->ev_used.push_back(ev);
+        }
+        return SW_OK;
+    }
     if (!hit) {
         // captured on the library's own stream (the caller's may be the legacy
         // default stream, which cannot be captured); launched on the caller's
@@ -1202,9 +1250,13 @@ sw_status search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int32
         G.stream = st;
         G.gen = db->gen;
         G.ws = W.scratch16;
+        db->last_eager = BatchKey();
     }
+    if (!G.done) HIP_TRY(hipEventCreateWithFlags(&G.done, hipEventDisableTiming));
     const int ev = db->timing ? record_timer_start(db, st) : -1;
     HIP_TRY(hipGraphLaunch(G.exec, st));
+    HIP_TRY(hipEventRecord(G.done, st));
+    G.launched = true;
     if (ev >= 0) {
         HIP_TRY(hipEventRecord(db->ev_pool[ev].second, st));
         db->ev_used.push_back(ev);
@@ -1298,6 +1350,7 @@ void sw_db_free(sw_db* db) {
     if (db->side) hipStreamDestroy(db->side);
     if (db->side2) hipStreamDestroy(db->side2);
     if (db->cap) hipStreamDestroy(db->cap);
+    if (db->graph.done) hipEventDestroy(db->graph.done);
     if (db->ev_fork) hipEventDestroy(db->ev_fork);
     if (db->ev_join) hipEventDestroy(db->ev_join);
     if (db->ev_join2) hipEventDestroy(db->ev_join2);

@@ -1,6 +1,6 @@
-"""GPU: chunked multi-query launches and the continuous-batching server give
-exactly the oracle's scores and top-k, and each request's result is the same
-alone and in the mix (tolerance 0)."""
+"""GPU: chunked multi-query launches, the continuous-batching server and the
+length-paired FIFO give exactly the oracle's scores and top-k, and each
+request's result is the same alone and in the mix (tolerance 0)."""
 import numpy as np
 import pytest
 
@@ -83,4 +83,26 @@ def test_dynamic_batching_matches_the_oracle(gpu, blosum):
         ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 10)
         s, idx = rep.results[i]
         assert (s == ws).all() and (idx == wi).all(), i
+    D.close()
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_paired_fifo_matches_the_oracle(gpu, blosum, depth):
+    """Pairs of similar length share lanes (query pairs), singles run alone, up to `depth` units queued
+    on the stream at once through one caller workspace: every top 10 equals the oracle's."""
+    from paper_2309_09609_amd.serve import paired_run
+    db = synth.small_db(seed=80 + depth, n=2000, lo=20, hi=900, median=300)
+    D = gpu.Database(db.residues, db.offsets, memory="torch", lane_pack=2, force_lanes=2)
+    rng = np.random.default_rng(3 + depth)
+    lens = [int(m) for m in rng.integers(1, 700, 14)] + [300, 290, 0, 1, 1]
+    qs = [synth.small_query(seed=400 + 20 * depth + i, m=m) for i, m in enumerate(lens)]
+    arrivals = np.sort(rng.uniform(0, 0.005, len(qs)))
+    print(f"paired FIFO depth {depth}: {len(qs)} requests, lengths {lens}", flush=True)
+    rep = paired_run(D, qs, arrivals, blosum, 10, 2, k=10, ratio=0.75, depth=depth)
+    assert rep.paired >= 1 and rep.iterations == len(qs) - rep.paired
+    for i, q in enumerate(qs):
+        ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 10)
+        s, idx = rep.results[i]
+        assert (s == ws).all() and (idx == wi).all(), (i, lens[i])
+    assert D.info()["device_bytes"] == 0
     D.close()
