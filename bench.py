@@ -389,6 +389,25 @@ def pair_bench(args, perfmodel):
                      "avg_launch_ms": round(ms / launches, 4), "ops_per_cell": PAIR_CELL_OPS},
         "extra": {"score": int(score.item()), "event_ms_per_step": round(ms, 3)},
     }
+    if args.pair_align and L <= 50_000:
+        # the alignment of the same pair (traceback): the tiled fill against one workgroup for the pair
+        offs = np.array([0, L], np.int64)
+        D = sw.Database(d, offs)
+        times, alns = {}, {}
+        for mode, name in ((2, "tiled"), (1, "one_workgroup"), (2, "tiled")):
+            D.tune(align_tiles=mode)
+            t = time.perf_counter()
+            alns[name] = D.align(q, [0], sm, 10, 2)[0]
+            times[name] = time.perf_counter() - t        # the second tiled call is the one kept (warm)
+            print(f"# align {name}: {times[name] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        D.close()
+        res["extra"]["align"] = {"tiled_ms": round(times["tiled"] * 1e3, 2),
+                                 "one_workgroup_ms": round(times["one_workgroup"] * 1e3, 2),
+                                 "tiled_gcups": round(cells / times["tiled"] / 1e9, 2),
+                                 "speedup": round(times["one_workgroup"] / times["tiled"], 2),
+                                 "same_alignment": alns["tiled"] == alns["one_workgroup"],
+                                 "score_equals_sw_pair": alns["tiled"]["score"] == int(score.item()),
+                                 "ops": len(alns["tiled"]["ops"])}
     if not args.no_cpu_baseline:
         import oracle
         n = min(L, 20_000)
@@ -410,6 +429,8 @@ def main():
     ap.add_argument("--workload", default="sp570k", choices=["sp570k", "small2k", "long10k", "batch256", "serve10M"])
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "align", "pair"])
     ap.add_argument("--pair-len", type=int, default=100_000, help="pair form: residues of each sequence")
+    ap.add_argument("--pair-align", action="store_true",
+                    help="pair form: also align the pair (traceback), tiled fill vs one workgroup (up to 50,000)")
     ap.add_argument("--requests", type=int, default=200, help="served form: measured requests")
     ap.add_argument("--load", type=float, default=0.8, help="served form: arrival rate / plain service rate")
     ap.add_argument("--chunks", type=int, default=8, help="served form: database chunks per request cycle")

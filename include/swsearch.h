@@ -100,7 +100,11 @@ typedef struct {
     int32_t poison;           /* test hook: 1 = every flagged pair's 16-bit scores are written as
                                  -1,000,000,007 before the recompute overwrites them, so a pair the
                                  recompute missed would show; 0 = off. */
-    int32_t reserved;         /* 0 */
+    int32_t align_tiles;      /* tuning, alignments: 0 = pairs whose query and subject both have at least
+                                 2,048 residues fill their matrix as tiles of 256 query rows by 128-256
+                                 subject columns over the whole GPU, the others on one workgroup each;
+                                 1 = every pair on one workgroup; 2 = every pair as tiles.  The
+                                 alignments are the same for every setting. */
 } sw_pack_opts;
 
 /*
@@ -341,6 +345,9 @@ typedef struct {
  * Synchronous: the work runs on `stream` and the call returns when the host
  * buffers are filled.  Device memory: about qlen x subject length bytes per
  * pair, in rounds of pairs that fit 4 GiB (a larger single pair runs alone).
+ * A pair fills its matrix on one workgroup, or as tiles over the whole GPU
+ * (pairs with both sides >= 2,048 residues by default; sw_pack_opts.align_tiles);
+ * the alignment is the same either way.
  */
 sw_status sw_align(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_subjects, int32_t nsub,
                    const int8_t* h_subst, int32_t gap_open, int32_t gap_extend, sw_alignment* h_out, char* h_ops,

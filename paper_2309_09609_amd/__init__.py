@@ -148,20 +148,20 @@ class PackOpts(ctypes.Structure):
     _fields_ = [("max_qlen", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
                 ("rerun_threshold", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
                 ("unit_share", ctypes.c_int32), ("lane_pack", ctypes.c_int32), ("alphabet", ctypes.c_int32),
-                ("rerun_cap", ctypes.c_int32), ("poison", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rerun_cap", ctypes.c_int32), ("poison", ctypes.c_int32), ("align_tiles", ctypes.c_int32)]
 
 
 def sw_db_pack(d_residues, h_offsets, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
-               unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0) -> ctypes.c_void_p:
+               unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, align_tiles=0) -> ctypes.c_void_p:
     """Pack a database; ``d_residues`` is an int8 tensor on the GPU, ``h_offsets`` int64[n+1].
     ``alphabet`` is the residue alphabet size (0 = 20); ``force_lanes``, ``rerun_threshold``,
-    ``rows_per_lane``, ``rerun_cap`` and ``poison`` are tuning/test hooks (see sw_pack_opts)."""
+    ``rows_per_lane``, ``rerun_cap``, ``poison`` and ``align_tiles`` are tuning/test hooks (see sw_pack_opts)."""
     lib = load()
     offs = _host_i64(h_offsets)
     n = offs.size - 1
     h = ctypes.c_void_p()
     opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack),
-                    int(alphabet), int(rerun_cap), int(poison))
+                    int(alphabet), int(rerun_cap), int(poison), int(align_tiles))
     _check(lib.sw_db_pack(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), n, ctypes.byref(opts),
                           _stream(stream), ctypes.byref(h)))
     return h
@@ -176,12 +176,12 @@ def sw_db_pack_bytes(h_offsets) -> int:
 
 
 def sw_db_pack_into(d_residues, h_offsets, d_db, stream=None, force_lanes=0, rerun_threshold=0, rows_per_lane=0,
-                    unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0) -> ctypes.c_void_p:
+                    unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, align_tiles=0) -> ctypes.c_void_p:
     """``sw_db_pack`` into ``d_db``, a caller-owned uint8 tensor of at least ``sw_db_pack_bytes`` bytes."""
     offs = _host_i64(h_offsets)
     h = ctypes.c_void_p()
     opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share), int(lane_pack),
-                    int(alphabet), int(rerun_cap), int(poison))
+                    int(alphabet), int(rerun_cap), int(poison), int(align_tiles))
     _check(load().sw_db_pack_into(ctypes.c_void_p(d_residues.data_ptr()), _ptr(offs), offs.size - 1,
                                   ctypes.byref(opts), _ptr(d_db), d_db.numel() * d_db.element_size(), _stream(stream),
                                   ctypes.byref(h)))
@@ -310,7 +310,8 @@ class Database:
     searches and alignments still use the handle's)."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
-                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, memory="library"):
+                 rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, memory="library",
+                 align_tiles=0):
         import torch
         if memory not in ("library", "torch"):
             raise ValueError("memory must be 'library' or 'torch'")
@@ -332,10 +333,11 @@ class Database:
         if memory == "torch":
             self.image = torch.empty(sw_db_pack_bytes(self.offsets), dtype=torch.uint8, device=d_res.device)
             self.handle = sw_db_pack_into(d_res, self.offsets, self.image, stream, force_lanes, rerun_threshold,
-                                          rows_per_lane, unit_share, lane_pack, alphabet, rerun_cap, poison)
+                                          rows_per_lane, unit_share, lane_pack, alphabet, rerun_cap, poison,
+                                          align_tiles)
         else:
             self.handle = sw_db_pack(d_res, self.offsets, stream, force_lanes, rerun_threshold, rows_per_lane,
-                                     unit_share, lane_pack, alphabet, rerun_cap, poison)
+                                     unit_share, lane_pack, alphabet, rerun_cap, poison, align_tiles)
         del d_res
 
     def close(self):
@@ -376,10 +378,10 @@ class Database:
                 "recomputed": int(out[6]), "rerun_overflow": int(out[7])}
 
     def tune(self, force_lanes=0, rerun_threshold=0, rows_per_lane=0, unit_share=0, lane_pack=0, rerun_cap=0,
-             poison=0):
+             poison=0, align_tiles=0):
         """Change the handle's tuning knobs (results are identical for every setting)."""
         opts = PackOpts(0, int(force_lanes), int(rerun_threshold), int(rows_per_lane), int(unit_share),
-                        int(lane_pack), 0, int(rerun_cap), int(poison))
+                        int(lane_pack), 0, int(rerun_cap), int(poison), int(align_tiles))
         _check(load().sw_db_tune(self.handle, ctypes.byref(opts)))
 
     def profile_kernels(self, enable=True):

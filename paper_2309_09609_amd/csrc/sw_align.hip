@@ -21,6 +21,11 @@
 // step: byte (band p, step t, lane b, row r) at ((p * (n + 63) + t) * 64 + b)
 // * 4 + r.
 //
+// A long pair's fill can instead be spread over tiles of one band by 128 or
+// 256 columns, one anti-diagonal of tiles per launch (k_align_tile): it writes
+// the same bytes and finds the same end cell, in about (bands + column tiles)
+// tile sweeps instead of the one workgroup's many stages.
+//
 // Walk.  One wave per pair copies the 256-byte step records of up to 128
 // steps of the current band into LDS and follows the path through them until
 // it leaves the copied steps; every move keeps or lowers the step index, so
@@ -267,6 +272,199 @@ __global__ __launch_bounds__(64 * kAlignWaves) void k_align_fill(const AlignPair
     }
 }
 
+// Tiled fill for long pairs: the same cells, direction bytes and end cell as
+// k_align_fill, computed by many workgroups.  The pair's matrix is cut into
+// tiles of one band (256 rows) by tn columns; the tiles of one anti-diagonal
+// I + J = d of the tile grid are independent, so launch d runs them all, one
+// wave per tile, and launch order is the only synchronisation.  Lane b of a
+// tile owns the band's rows 4b..4b+3 as in k_align_fill and writes the
+// direction dword of (band step t, lane b) for the columns of its own tile
+// only, so the band layout the walk reads comes out the same.  Between
+// launches: the band's bottom row (H and F per column) in the pair's row
+// buffer, as k_align_fill keeps it; the tile's last column (H and E per row)
+// in hcol/ecol; and corner[I], the row buffer's H at the tile's last column,
+// saved before the tile overwrites it (the next tile of band I+1 needs it as
+// its diagonal).  Each tile writes its first end cell (score desc, row asc,
+// column asc) to ends[3 * (I * nc + J)]; k_align_tile_end reduces them.
+
+__global__ __launch_bounds__(64) void k_align_tile(const AlignPair* pairs, const AlignTile* tiles, const int8_t* subst,
+                                                   int A, int go, int ge, uint8_t* dirs, int32_t* bnd, int32_t* tws,
+                                                   int d, int tile0) {
+    __shared__ uint32_t prof[(kMaxAlphabet + 1) * 64];          // [image byte][lane]: 4 rows' scores
+    __shared__ uint8_t sres[kAlignTileMax];                      // the tile's image bytes (residue code + 1)
+    __shared__ int32_t rowh[kAlignTileMax], rowf[kAlignTileMax]; // the band above: H and F of its last row
+    __shared__ int32_t outh[kAlignTileMax], outf[kAlignTileMax]; // this band's last row
+    __shared__ int8_t sm[kMaxAlphabet * kMaxAlphabet];
+    const AlignTile T = tiles[tile0 + blockIdx.y];
+    const int I = max(0, d - (T.nc - 1)) + (int)blockIdx.x;
+    if (I >= T.nb || I > d) return;                              // uniform over the workgroup
+    const int J = d - I;
+    const AlignPair P = pairs[T.pair];
+    const int b = threadIdx.x;
+    const int m = P.m, n = P.n;
+    const int nsteps = n + 63;
+    const int j0 = J * T.tn;                                     // 0-based first column of the tile
+    const int w = min(T.tn, n - j0);                             // its columns
+    const int row0 = I * kAlignPass + b * kAlignRows;            // 0-based first row of this lane
+    int32_t* hcol = tws + T.ws_off;
+    int32_t* ecol = hcol + m;
+    int32_t* corner = ecol + m;
+    int32_t* ends = corner + T.nb;
+    int32_t* bh = bnd + P.bnd_off;
+    int32_t* bf = bh + ((n + 3) & ~3);
+    uint32_t* dir = reinterpret_cast<uint32_t*>(dirs + P.dir_off);
+    for (int e = b; e < A * A; e += 64) sm[e] = subst[e];
+    bool valid[kAlignRows];
+    int qa[kAlignRows];
+#pragma unroll
+    for (int r = 0; r < kAlignRows; ++r) {
+        valid[r] = row0 + r < m;
+        qa[r] = valid[r] ? P.query[row0 + r] * A : -1;
+    }
+    __syncthreads();
+    // rows past the query score 0 against every residue (as in k_align_fill); they never end an alignment
+    prof[b] = 0x80808080u;
+    for (int c = 0; c < A; ++c) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int r = 0; r < kAlignRows; ++r)
+            if (qa[r] >= 0) v |= (uint32_t)(uint8_t)sm[qa[r] + c] << (8 * r);
+        prof[(c + 1) * 64 + b] = v;
+    }
+    for (int k = b; k < w; k += 64) {
+        const int j = j0 + k;
+        sres[k] = P.residues[(int64_t)(j >> 2) * kChunkBytes + (j & 3)];
+        rowh[k] = I > 0 ? bh[j] : 0;
+        rowf[k] = I > 0 ? bf[j] : 0;
+    }
+    __syncthreads();
+    int H[kAlignRows], E[kAlignRows], bs[kAlignRows], bj[kAlignRows];
+#pragma unroll
+    for (int r = 0; r < kAlignRows; ++r) {
+        H[r] = (J > 0 && valid[r]) ? hcol[row0 + r] : 0;
+        E[r] = (J > 0 && valid[r]) ? ecol[row0 + r] : 0;
+        bs[r] = valid[r] ? 0 : INT_MAX;
+        bj[r] = 0;
+    }
+    // H of the row above this lane's block at the column before the tile (lane 0: the band above's last
+    // row, which the tile before this one in the band saved before overwriting it)
+    int diag = 0;
+    if (J > 0) diag = b == 0 ? corner[I] : (row0 - 1 < m ? hcol[row0 - 1] : 0);
+    int up_h = 0, up_f = 0;                                      // lane b-1's last row at this step's column
+    const int nst = w + 63;
+    // LDS reads run ahead of the step that uses them (the profile word one step, the residue that addresses
+    // it two, the band-above row one), so no step waits on a dependent pair of reads
+    auto colk = [&](int t) { return min(max(t - b, 0), w - 1); };
+    uint32_t pv = prof[(int)sres[colk(0)] * 64 + b];
+    int res2 = sres[colk(1)];
+    int rh = rowh[colk(0)], rf = rowf[colk(0)];
+    for (int t = 0; t < nst; ++t) {
+        const int k = t - b;                                     // 0-based column of this lane in the tile
+        const bool active = k >= 0 && k < w;
+        const uint32_t pv_next = prof[res2 * 64 + b];
+        const int res3 = sres[colk(t + 2)];
+        const int rh_next = rowh[colk(t + 1)], rf_next = rowf[colk(t + 1)];
+        const int htop = b == 0 ? rh : up_h;
+        const int ftop = b == 0 ? rf : up_f;
+        int hu = 0, fu = 0;
+        if (active) {
+            const uint32_t sv = pv;
+            const int j = j0 + k + 1;                            // 1-based column
+            int dg = diag;
+            hu = htop;
+            fu = ftop;
+            uint32_t bits = 0;
+#pragma unroll
+            for (int r = 0; r < kAlignRows; ++r) {
+                const int hl = H[r];
+                const int eo = hl - go, ee = E[r] - ge;
+                const int e = max(eo, ee);                       // Eq. 2
+                const int fo = hu - go, fe = fu - ge;
+                const int f = max(fo, fe);                       // Eq. 3
+                const int hd = dg + (int)(int8_t)(sv >> (8 * r));
+                const int h = max(max(hd, e), max(f, 0));        // Eq. 1
+                const uint32_t src = h == 0 ? 0u : h == hd ? 1u : h == e ? 2u : 3u;
+                bits |= (src | (eo >= ee ? 4u : 0u) | (fo >= fe ? 8u : 0u)) << (8 * r);
+                if (h > bs[r]) { bs[r] = h; bj[r] = j; }
+                dg = hl;
+                H[r] = h;
+                E[r] = e;
+                hu = h;
+                fu = f;
+            }
+            dir[((int64_t)I * nsteps + j0 + t) * 64 + b] = bits;
+            if (b == 63) {
+                outh[k] = hu;
+                outf[k] = fu;
+            }
+            if (k == w - 1) {
+#pragma unroll
+                for (int r = 0; r < kAlignRows; ++r)
+                    if (valid[r]) {
+                        hcol[row0 + r] = H[r];
+                        ecol[row0 + r] = E[r];
+                    }
+            }
+            diag = htop;
+        }
+        up_h = (int)align_shr1((uint32_t)hu);
+        up_f = (int)align_shr1((uint32_t)fu);
+        pv = pv_next;
+        res2 = res3;
+        rh = rh_next;
+        rf = rf_next;
+    }
+    // the tile's first end cell
+    int sc = 0, ci = 0, cj = 0;
+#pragma unroll
+    for (int r = 0; r < kAlignRows; ++r)
+        if (valid[r] && bs[r] > 0 && end_before(bs[r], row0 + r + 1, bj[r], sc, ci, cj)) {
+            sc = bs[r];
+            ci = row0 + r + 1;
+            cj = bj[r];
+        }
+    for (int o = 1; o < 64; o <<= 1) {
+        const int s2 = __shfl_xor(sc, o, 64), i2 = __shfl_xor(ci, o, 64), j2 = __shfl_xor(cj, o, 64);
+        if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
+    }
+    __syncthreads();
+    if (b == 0) corner[I] = rowh[w - 1];                         // for the next tile of this band
+    if (I + 1 < T.nb) {
+        for (int k = b; k < w; k += 64) {
+            bh[j0 + k] = outh[k];
+            bf[j0 + k] = outf[k];
+        }
+    }
+    if (b == 0) {
+        int32_t* o = ends + 3 * ((int64_t)I * T.nc + J);
+        o[0] = sc;
+        o[1] = ci;
+        o[2] = cj;
+    }
+}
+
+// The first end cell over a tiled pair's tiles, into best[3 * pair].
+__global__ __launch_bounds__(64) void k_align_tile_end(const AlignPair* pairs, const AlignTile* tiles,
+                                                       const int32_t* tws, int32_t* best) {
+    const AlignTile T = tiles[blockIdx.x];
+    const int32_t* ends = tws + T.ws_off + 2 * (int64_t)pairs[T.pair].m + T.nb;
+    const int nt = T.nb * T.nc;
+    int sc = 0, ci = 0, cj = 0;
+    for (int x = threadIdx.x; x < nt; x += 64) {
+        const int s2 = ends[3 * x], i2 = ends[3 * x + 1], j2 = ends[3 * x + 2];
+        if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        const int s2 = __shfl_xor(sc, o, 64), i2 = __shfl_xor(ci, o, 64), j2 = __shfl_xor(cj, o, 64);
+        if (s2 > 0 && (sc == 0 || end_before(s2, i2, j2, sc, ci, cj))) { sc = s2; ci = i2; cj = j2; }
+    }
+    if (threadIdx.x == 0) {
+        best[3 * T.pair] = sc;
+        best[3 * T.pair + 1] = ci;
+        best[3 * T.pair + 2] = cj;
+    }
+}
+
 // One wave per pair: walk the direction bytes back from the end cell, through
 // LDS copies of up to kTraceSteps step records of the band it is in, a run of
 // equal moves at a time; the byte of (row rb of the band, 0-based
@@ -385,15 +583,36 @@ constexpr int kFillStaticLds = 1024;             // k_align_fill's own LDS (matr
 // W = waves per workgroup: the most bands of a pair in the launch, at most 16
 // and at most align_waves(., A, lds_max) allows; lds_max = LDS bytes a
 // workgroup may use on the device.
-hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
-                        uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
-                        int lds_max, hipStream_t st) {
+hipError_t launch_align_fill(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
+                             uint8_t* dirs, int32_t* bnd, int32_t* best, int lds_max, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
     const size_t lds = (size_t)W * (A + 1) * kAlignPass;
     if (W < 1 || W > kAlignWaves || lds + kFillStaticLds > (size_t)lds_max) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_align_fill, dim3(npairs), dim3(64 * W), lds, st, pairs, subst, A, go, ge, dirs, bnd, best);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// The tiled fill of ntiled pairs (tiles[i].pair indexes pairs): one launch per anti-diagonal of the
+// largest tile grid, then the end cells.  max_diag_tiles = the most tiles any pair has on one diagonal.
+hipError_t launch_align_tiles(const AlignPair* pairs, const AlignTile* tiles, int ntiled, int ndiag,
+                              int max_diag_tiles, const int8_t* subst, int A, int go, int ge, uint8_t* dirs,
+                              int32_t* bnd, int32_t* tws, int32_t* best, hipStream_t st) {
+    if (ntiled <= 0) return hipSuccess;
+    constexpr int kMaxGridY = 65535;
+    for (int d = 0; d < ndiag; ++d)
+        for (int t0 = 0; t0 < ntiled; t0 += kMaxGridY) {
+            hipLaunchKernelGGL(k_align_tile, dim3(max_diag_tiles, std::min(kMaxGridY, ntiled - t0)), dim3(64), 0, st,
+                               pairs, tiles, subst, A, go, ge, dirs, bnd, tws, d, t0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    hipLaunchKernelGGL(k_align_tile_end, dim3(ntiled), dim3(64), 0, st, pairs, tiles, tws, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_align_trace(const AlignPair* pairs, int npairs, const uint8_t* dirs, const int32_t* best, char* ops,
+                              int64_t ops_stride, int64_t* info, hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_align_trace, dim3(npairs), dim3(64), 0, st, pairs, dirs, best, ops, ops_stride, info);
     return hipGetLastError();
 }

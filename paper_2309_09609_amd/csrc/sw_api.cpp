@@ -36,9 +36,13 @@ hipError_t sweep_occupancy_q2(int R, int* blocks_per_cu);
 hipError_t launch_sweep_mode(int mode, int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t launch_sweep_mode16(int mode, int R, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_occupancy_mode16(int mode, int R, int* blocks_per_cu);
-hipError_t launch_align(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
-                        uint8_t* dirs, int32_t* bnd, int32_t* best, char* ops, int64_t ops_stride, int64_t* info,
-                        int lds_max, hipStream_t st);
+hipError_t launch_align_fill(const AlignPair* pairs, int npairs, int W, const int8_t* subst, int A, int go, int ge,
+                             uint8_t* dirs, int32_t* bnd, int32_t* best, int lds_max, hipStream_t st);
+hipError_t launch_align_tiles(const AlignPair* pairs, const AlignTile* tiles, int ntiled, int ndiag,
+                              int max_diag_tiles, const int8_t* subst, int A, int go, int ge, uint8_t* dirs,
+                              int32_t* bnd, int32_t* tws, int32_t* best, hipStream_t st);
+hipError_t launch_align_trace(const AlignPair* pairs, int npairs, const uint8_t* dirs, const int32_t* best, char* ops,
+                              int64_t ops_stride, int64_t* info, hipStream_t st);
 int align_waves(int m, int A, int lds_max);
 int64_t align_dir_bytes(int m, int64_t n);
 int64_t align_bnd_words(int64_t n);
@@ -225,7 +229,8 @@ struct sw_db {
     // per original subject: length and sorted slot; per group: byte offset in the image (alignments)
     std::vector<int32_t> lens, slot_of;
     std::vector<int64_t> gbase;
-    DevBuf align_dirs, align_bnd, align_misc;   // traceback workspace
+    DevBuf align_dirs, align_bnd, align_misc, align_tws;   // traceback workspace
+    int align_tiles = 0;              // tiled traceback fill: 0 = long pairs, 1 = never, 2 = every pair
     int wg_mode = 0;                  // persistent workgroups of an end-to-end sweep
     Plan mode_plan;
     // launch geometry
@@ -297,6 +302,7 @@ sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
     if (opts->unit_share < 0 || opts->unit_share > 100000) return fail(SW_E_INVALID, "unit_share must be in 0..100000");
     if (opts->rerun_cap < 0) return fail(SW_E_INVALID, "rerun_cap must be >= 0");
     if (opts->poison != 0 && opts->poison != 1) return fail(SW_E_INVALID, "poison must be 0 or 1");
+    if (opts->align_tiles < 0 || opts->align_tiles > 2) return fail(SW_E_INVALID, "align_tiles must be 0, 1 or 2");
     db->force_lgB = fl ? __builtin_ctz(fl) : -1;
     db->force_R = rpl;
     db->unit_share = opts->unit_share > 0 ? opts->unit_share / 1000.0 : 0.25;
@@ -304,6 +310,7 @@ sw_status apply_opts(sw_db* db, const sw_pack_opts* opts) {
     db->lane_pack = opts->lane_pack == 2 ? 2 : 1;
     db->rerun_cap_hook = opts->rerun_cap;
     db->poison = opts->poison;
+    db->align_tiles = opts->align_tiles;
     return SW_OK;
 }
 
@@ -1342,7 +1349,7 @@ void sw_db_free(sw_db* db) {
     hipDeviceSynchronize();
     clear_caches(db);
     db->image_own.release();           // a caller's image stays the caller's
-    db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release();
+    db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release(); db->align_tws.release();
     db->mode_plan.release();
     db->ws_own.release();
     db->hstage.release();
@@ -1595,11 +1602,20 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
     hipStream_t st = static_cast<hipStream_t>(stream);
     int lds_max = 0;                                // LDS a workgroup may use (64 KiB on older parts, 160 KiB on gfx950)
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, db->device));
+    if ((s = ensure_geometry(db)) != SW_OK) return s;      // the side stream
+    // A long pair's fill runs on one workgroup for as long as its many stages take; spread over tiles of one
+    // band by tn columns (one anti-diagonal of tiles per launch) it finishes in about (bands + tiles) tile
+    // sweeps instead.  Which pairs: db->align_tiles (0: both sides of the matrix at least kTileMinSide).
+    constexpr int kTileMinSide = 2048;
+    auto tiled = [&](const Job& J) {
+        return J.n > 0 && (db->align_tiles == 2 || (db->align_tiles == 0 && J.m >= kTileMinSide && J.n >= kTileMinSide));
+    };
+    auto tile_cols = [](int n) { return n >= 4096 ? 256 : 128; };
     size_t j0 = 0;
     while (j0 < jobs.size()) {
         // a round: pairs whose direction bytes fit the budget (at least one pair)
         size_t j1 = j0;
-        int64_t dir_total = 0, bnd_total = 0, stride = 1;
+        int64_t dir_total = 0, bnd_total = 0, stride = 1, tws_total = 0;
         int W = 1;
         std::vector<int32_t> qs_used;
         while (j1 < jobs.size()) {
@@ -1608,18 +1624,27 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
             dir_total += round_up(J.cost, 256);
             bnd_total += align_bnd_words(J.n);
             stride = std::max<int64_t>(stride, (int64_t)J.m + J.n + 1);
-            W = std::max(W, align_waves(J.m, db->alphabet, lds_max));
             qs_used.push_back(J.q);
             ++j1;
         }
+        // the round's pairs filled by one workgroup each first, then the tiled ones
+        std::stable_partition(jobs.begin() + j0, jobs.begin() + j1, [&](const Job& J) { return !tiled(J); });
+        int nfill = 0;
+        for (size_t j = j0; j < j1; ++j)
+            if (!tiled(jobs[j])) {
+                W = std::max(W, align_waves(jobs[j].m, db->alphabet, lds_max));
+                ++nfill;
+            }
         std::sort(qs_used.begin(), qs_used.end());
         qs_used.erase(std::unique(qs_used.begin(), qs_used.end()), qs_used.end());
         const int np = (int)(j1 - j0);
-        // misc: pairs | best (3 int32 each) | info (4 int64 each) | matrix | queries | ops
+        const int ntiled = np - nfill;
+        // misc: pairs | best (3 int32 each) | info (4 int64 each) | tiles | matrix | queries | ops
         const size_t o_pairs = 0;
         const size_t o_best = round_up(sizeof(AlignPair) * np, 256);
         const size_t o_info = o_best + round_up(12 * (size_t)np, 256);
-        const size_t o_sm = o_info + round_up(32 * (size_t)np, 256);
+        const size_t o_tiles = o_info + round_up(32 * (size_t)np, 256);
+        const size_t o_sm = o_tiles + round_up(sizeof(AlignTile) * std::max(ntiled, 1), 256);
         const size_t o_query = o_sm + 1024;
         std::vector<int64_t> qpos(nq, -1);
         size_t qbytes = 0;
@@ -1629,12 +1654,10 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
         }
         const size_t o_ops = o_query + qbytes;
         const size_t misc = o_ops + (size_t)np * stride;
-        HIP_TRY(db->align_dirs.reserve((size_t)std::max<int64_t>(dir_total, 256)));
-        HIP_TRY(db->align_bnd.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bnd_total, 64)));
-        HIP_TRY(db->align_misc.reserve(misc));
-        char* mb = db->align_misc.as<char>();
         std::vector<AlignPair> pairs(np);
+        std::vector<AlignTile> tiles;
         int64_t dir_off = 0, bnd_off = 0;
+        int ndiag = 0, max_diag_tiles = 0;
         for (int i = 0; i < np; ++i) {
             const Job& J = jobs[j0 + i];
             const int64_t sub = h_subjects[J.k];
@@ -1644,21 +1667,55 @@ sw_status sw_align_batch(const int8_t* h_queries, const int64_t* h_qoffsets, int
             P.residues = db->d_image + db->gbase[g] + (int64_t)(w >> 1) * 8 + (w & 1) * 4;
             P.n = J.n;
             P.m = J.m;
-            P.query = reinterpret_cast<const int8_t*>(mb + o_query + qpos[J.q]);
             P.dir_off = dir_off;
             P.bnd_off = bnd_off;
             dir_off += round_up(J.cost, 256);
             bnd_off += align_bnd_words(J.n);
+            if (i >= nfill && J.n > 0) {
+                AlignTile T;
+                T.pair = i;
+                T.nb = (J.m + 255) / 256;
+                T.tn = tile_cols(J.n);
+                T.nc = (J.n + T.tn - 1) / T.tn;
+                T.ws_off = tws_total;
+                tws_total += round_up(2 * (int64_t)J.m + T.nb + 3 * (int64_t)T.nb * T.nc, 64);
+                ndiag = std::max(ndiag, T.nb + T.nc - 1);
+                max_diag_tiles = std::max(max_diag_tiles, std::min(T.nb, T.nc));
+                tiles.push_back(T);
+            }
         }
+        HIP_TRY(db->align_dirs.reserve((size_t)std::max<int64_t>(dir_total, 256)));
+        HIP_TRY(db->align_bnd.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(bnd_total, 64)));
+        HIP_TRY(db->align_misc.reserve(misc));
+        HIP_TRY(db->align_tws.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(tws_total, 64)));
+        char* mb = db->align_misc.as<char>();
+        for (int i = 0; i < np; ++i) pairs[i].query = reinterpret_cast<const int8_t*>(mb + o_query + qpos[jobs[j0 + i].q]);
         HIP_TRY(hipMemcpyAsync(mb + o_pairs, pairs.data(), sizeof(AlignPair) * np, hipMemcpyHostToDevice, st));
+        if (!tiles.empty())
+            HIP_TRY(hipMemcpyAsync(mb + o_tiles, tiles.data(), sizeof(AlignTile) * tiles.size(), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(mb + o_sm, h_subst, (size_t)db->alphabet * db->alphabet, hipMemcpyHostToDevice, st));
         for (int32_t q : qs_used)
             HIP_TRY(hipMemcpyAsync(mb + o_query + qpos[q], h_queries + h_qoffsets[q], (size_t)(h_qoffsets[q + 1] - h_qoffsets[q]),
                                    hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_align(reinterpret_cast<AlignPair*>(mb + o_pairs), np, W, reinterpret_cast<int8_t*>(mb + o_sm),
-                             db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(), db->align_bnd.as<int32_t>(),
-                             reinterpret_cast<int32_t*>(mb + o_best), mb + o_ops, stride,
-                             reinterpret_cast<int64_t*>(mb + o_info), lds_max, st));
+        const AlignPair* d_pairs = reinterpret_cast<AlignPair*>(mb + o_pairs);
+        const int8_t* d_sm = reinterpret_cast<int8_t*>(mb + o_sm);
+        int32_t* d_best = reinterpret_cast<int32_t*>(mb + o_best);
+        // the one-workgroup fills on the side stream while the tiled ones run on the caller's
+        const bool fork = nfill > 0 && !tiles.empty();
+        const hipStream_t fs = fork ? db->side : st;
+        if (fork) {
+            HIP_TRY(hipEventRecord(db->ev_fork, st));
+            HIP_TRY(hipStreamWaitEvent(db->side, db->ev_fork, 0));
+        }
+        HIP_TRY(launch_align_fill(d_pairs, nfill, W, d_sm, db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
+                                  db->align_bnd.as<int32_t>(), d_best, lds_max, fs));
+        if (fork) HIP_TRY(hipEventRecord(db->ev_join, db->side));
+        HIP_TRY(launch_align_tiles(d_pairs, reinterpret_cast<AlignTile*>(mb + o_tiles), (int)tiles.size(), ndiag,
+                                   max_diag_tiles, d_sm, db->alphabet, gap_open, gap_extend, db->align_dirs.as<uint8_t>(),
+                                   db->align_bnd.as<int32_t>(), db->align_tws.as<int32_t>(), d_best, st));
+        if (fork) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));
+        HIP_TRY(launch_align_trace(d_pairs, np, db->align_dirs.as<uint8_t>(), d_best, mb + o_ops, stride,
+                                   reinterpret_cast<int64_t*>(mb + o_info), st));
         std::vector<int32_t> best(3 * (size_t)np);
         std::vector<int64_t> info(4 * (size_t)np);
         std::vector<char> ops((size_t)np * stride);

@@ -103,4 +103,13 @@ struct AlignPair {
     int64_t bnd_off;          // int32 offset of the pair's boundary row (H then F, n rounded up to 4 words each)
 };
 
+// A pair whose fill is spread over tiles of one band (256 query rows) by tn subject columns.
+struct AlignTile {
+    int32_t pair;             // index of the pair in the round's AlignPair array
+    int32_t nb, nc;           // bands and column tiles
+    int32_t tn;               // tile width, a multiple of 64, <= kAlignTileMax
+    int64_t ws_off;           // int32 offset in the tile workspace: hcol[m] | ecol[m] | corner[nb] | ends[3 nb nc]
+};
+constexpr int kAlignTileMax = 256;
+
 }  // namespace sw
