@@ -473,6 +473,44 @@ def test_full_size_workload2_every_score(gpu, blosum):
     D.close()
 
 
+@pytest.fixture(scope="module")
+def workload2_scores(gpu, blosum):
+    """Every query of the 570k-subject workload searched in the benchmark's launch configuration (one
+    query per launch sequence); the score rows stay on the host."""
+    import torch
+    db = synth.sp570k()
+    qs = synth.workload2_queries()
+    D = gpu.Database(db.residues, db.offsets)
+    rows = []
+    for k, q in enumerate(qs):
+        out = D.search(q, blosum, 10, 2)
+        torch.cuda.synchronize()
+        rows.append(out.cpu().numpy().copy())
+    D.close()
+    say(f"workload2: {len(qs)} queries searched")
+    return db, qs, rows
+
+
+def test_full_size_workload2_sample_for_every_query(workload2_scores, blosum):
+    """All 20 queries on the parity sample (every 1000th subject, every planted homolog, the sentinels and
+    every subject longer than 3,000 residues)."""
+    db, qs, rows = workload2_scores
+    idx = synth.parity_sample(db)
+    for k, q in enumerate(qs):
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2, idx=idx)
+        assert_equal_scores(rows[k][idx], want, f"workload2 query {k} (m={q.size}) sample")
+    say(f"workload2: {idx.size} sampled subjects equal for all {len(qs)} queries")
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_full_size_workload2_short_queries_every_score(workload2_scores, blosum, k):
+    """Every one of the 570,000 scores of the 2nd..5th shortest queries (the shortest is checked in all
+    three modes above)."""
+    db, qs, rows = workload2_scores
+    want = oracle.scores(qs[k], db.residues, db.offsets, blosum, 10, 2)
+    assert_equal_scores(rows[k], want, f"workload2 query {k} (m={qs[k].size}), all subjects")
+
+
 def test_extended_alphabet(gpu):
     """24-letter alphabet (B, Z, X, * after the 20 residues) with the full BLOSUM62."""
     import torch
