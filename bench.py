@@ -130,9 +130,12 @@ def cpu_baseline(queries, db, sm, seconds: float, mode: str = "local"):
     # the same oracle on one thread, over a quarter of the time
     cells1, dt1, _ = run(1, seconds / 4, block // 8)
     desc = ", ".join(f"query {qi} (m={m}) vs {done} subjects" for qi, m, done in parts)
-    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+    full = sum(int(q.size) for q in queries) * int(lengths.sum())     # one step of the workload
+    gcups = cells / dt / 1e9
+    return {"value": round(gcups, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
             "sample": f"{desc}: {cells:.3e} cells in {dt:.1f} s",
-            "single_thread_gcups": round(cells1 / dt1 / 1e9, 4), "host": host_report()}
+            "single_thread_gcups": round(cells1 / dt1 / 1e9, 4),
+            "extrapolated_step_s": round(full / (gcups * 1e9), 1), "host": host_report()}
 
 
 def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
