@@ -143,7 +143,7 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     import torch
     from inputs import synth
     from paper_2309_09609_amd.serve import GpuEngine, Server, batch_run, fifo_run, paired_run
-    warm = 10
+    warm = args.serve_warmup
     qs = synth.workload5_queries(warm + args.requests + 5)
     cells = lambda q: int(q.size) * total_res  # noqa: E731
     # plain service rate from a few searches
@@ -448,6 +448,7 @@ def main():
                          "dynamic-q2 (the same with query pairs per lane), srpt (one request at a time, least "
                          "remaining work first at every chunk boundary)")
     ap.add_argument("--headline", default="paired", help="served form: the policy whose figures the line reports")
+    ap.add_argument("--serve-warmup", type=int, default=10, help="served form: warm-up requests before the trace")
     ap.add_argument("--pair-ratio", type=float, default=0.85,
                     help="served form, paired policy: the shorter query of a pair is at least this share of the longer")
     ap.add_argument("--knobs", default="", help="batched form: JSON tuning knobs instead of autotuning")
