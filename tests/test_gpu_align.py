@@ -120,7 +120,18 @@ def test_invalid_requests(gpu, blosum):
     with pytest.raises(gpu.SwError):      # operation buffer too small for query + subject
         gpu.sw_align(synth.small_query(seed=93, m=10), D.handle, np.array([longest], np.int64), blosum, 10, 2,
                      longest=0)
+    for bad in (-1, 3):                   # the tiled-fill setting is 0, 1 or 2; a refused setting changes nothing
+        with pytest.raises(gpu.SwError):
+            D.tune(align_tiles=bad)
+    q = synth.small_query(seed=94, m=40)
+    assert D.align(q, [0, 1], blosum, 10, 2) == [oracle_alignment(q, db, k, blosum) for k in (0, 1)]
     D.close()
+
+
+def oracle_alignment(q, db, k, sm, go=10, ge=2):
+    d = db.residues[db.offsets[k]:db.offsets[k + 1]]
+    a = oracle.align(q, d, sm, go, ge)
+    return {"subject": k, **{key: a[key] for key in ("score", "q_begin", "q_end", "s_begin", "s_end", "ops")}}
 
 
 def test_alignments_with_the_extended_alphabet(gpu):
