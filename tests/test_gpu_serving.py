@@ -96,10 +96,10 @@ def test_paired_fifo_matches_the_oracle(gpu, blosum, depth):
     rng = np.random.default_rng(3 + depth)
     lens = [int(m) for m in rng.integers(1, 700, 14)] + [300, 290, 0, 1, 1]
     qs = [synth.small_query(seed=400 + 20 * depth + i, m=m) for i, m in enumerate(lens)]
-    arrivals = np.sort(rng.uniform(0, 0.005, len(qs)))
+    arrivals = np.zeros(len(qs))            # all waiting at once: the pairs formed do not depend on timing
     print(f"paired FIFO depth {depth}: {len(qs)} requests, lengths {lens}", flush=True)
     rep = paired_run(D, qs, arrivals, blosum, 10, 2, k=10, ratio=0.75, depth=depth)
-    assert rep.paired >= 1 and rep.iterations == len(qs) - rep.paired
+    assert rep.paired >= 2 and rep.iterations == len(qs) - rep.paired
     for i, q in enumerate(qs):
         ws, wi = oracle.topk(oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), 10)
         s, idx = rep.results[i]
