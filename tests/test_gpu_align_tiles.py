@@ -119,3 +119,27 @@ def test_tiled_fill_extended_alphabet_and_high_scores(gpu):
     assert got[1]["score"] >= 33000
     _compare(got, q, db, [0, 1], sm, 10, 2, "tiles alphabet 24")
     D.close()
+
+
+def test_full_size_top10_alignments(gpu, blosum):
+    """The benchmark's traceback workload: every query of the 570k-subject workload searched, its top 10
+    aligned in one call (the 60 pairs with both sides >= 2,048 residues tiled, the rest on one workgroup
+    each), every alignment equal to the oracle's operation for operation."""
+    import torch
+    db = synth.sp570k()
+    qs = synth.workload2_queries()
+    D = gpu.Database(db.residues, db.offsets)
+    tops = []
+    for q in qs:
+        scores = D.search(q, blosum, 10, 2)
+        _, ti = gpu.topk(scores, 10)
+        torch.cuda.synchronize()
+        tops.append(ti.cpu().numpy().tolist())
+    got = D.align_batch(qs, tops, blosum, 10, 2)
+    lens = np.diff(db.offsets)
+    tiled = sum(1 for q, t in zip(qs, tops) for k in t if q.size >= 2048 and lens[k] >= 2048)
+    print(f"top-10 alignments of {len(qs)} queries, {tiled} pairs tiled", flush=True)
+    assert tiled > 0
+    for q, t, g in zip(qs, tops, got):
+        _compare(g, q, db, t, blosum, 10, 2, f"top10 m={q.size}")
+    D.close()

@@ -511,6 +511,25 @@ def test_full_size_workload2_short_queries_every_score(workload2_scores, blosum,
     assert_equal_scores(rows[k], want, f"workload2 query {k} (m={qs[k].size}), all subjects")
 
 
+@pytest.mark.parametrize("mode", ["global", "semiglobal"])
+def test_full_size_workload2_modes_sample_for_every_query(gpu, blosum, mode):
+    """End-to-end modes at full size: all 20 queries on the parity sample, which holds every subject
+    longer than 3,000 residues (in global mode the groups of the longest run in 32-bit cells beside the
+    16-bit launch, and out-of-range pairs are recomputed)."""
+    import torch
+    db = synth.sp570k()
+    qs = synth.workload2_queries()
+    idx = synth.parity_sample(db)
+    D = gpu.Database(db.residues, db.offsets)
+    for k, q in enumerate(qs):
+        out = D.search(q, blosum, 10, 2, mode=mode)
+        torch.cuda.synchronize()
+        want = oracle.scores(q, db.residues, db.offsets, blosum, 10, 2, idx=idx, mode=mode)
+        assert_equal_scores(out.cpu().numpy()[idx], want, f"workload2 {mode} query {k} (m={q.size}) sample")
+    say(f"workload2 {mode}: {idx.size} sampled subjects equal for all {len(qs)} queries")
+    D.close()
+
+
 def test_extended_alphabet(gpu):
     """24-letter alphabet (B, Z, X, * after the 20 residues) with the full BLOSUM62."""
     import torch
