@@ -15,7 +15,8 @@ the oracle recomputes what it can in seconds (tolerance 0, Eq. 1-3):
 * the 10,000,000-subject serving database: every 10,000th subject for each of
   32 requests, and every one of the 10,000,000 scores of each request equal
   alone (one plain search) and in the served mix (all 32 admitted together,
-  two queries per lane).
+  two queries per lane); the length-paired FIFO's top 10 of each request
+  equal to the top 10 of its full score row.
 """
 import sys
 
@@ -159,9 +160,20 @@ def test_serve10M_alone_and_in_the_mix(gpu, blosum):
     eng = Keeping(D, blosum, 10, 2, k=10)
     mix = Server(eng, nchunks=8, mem_budget=4 << 30).run(qs, np.zeros(len(qs)))
     assert mix.max_active == len(qs)
+    wants = []
     for i in range(len(qs)):
         assert torch.equal(eng.kept[i], alone[i]), f"request {i}: mix differs from alone"
         ws, wi = _topk_of_row(alone[i].cpu().numpy(), 10)
+        wants.append((ws, wi))
         m_s, m_i = mix.results[i]
         assert (m_s == ws).all() and (m_i == wi).all(), i
+    # the length-paired FIFO on the same requests, all waiting at once (query pairs, queued launches)
+    from paper_2309_09609_amd.serve import paired_run
+    D.tune(lane_pack=2, force_lanes=2)
+    rep = paired_run(D, qs, np.zeros(len(qs)), blosum, 10, 2, k=10)
+    say(f"serve10M paired FIFO: {rep.paired} pairs of {len(qs)} requests")
+    assert rep.paired > 0
+    for i, (ws, wi) in enumerate(wants):
+        p_s, p_i = rep.results[i]
+        assert (p_s == ws).all() and (p_i == wi).all(), f"paired FIFO request {i}"
     D.close()
