@@ -169,6 +169,10 @@ sw_status sw_db_info(const sw_db* db, int64_t* n, int64_t* residues, int64_t* de
  *   gap_open, gap_extend : Go, Ge >= 0.
  *   d_scores_out : device int32[n]; receives S for each subject in the
  *                original database order.
+ * The work is enqueued on `stream`.  The first search of a query length plans
+ * it on the host and copies the plan to the handle's device memory with a
+ * synchronous copy (later searches of that length reuse it); sw_search_ws
+ * sends the plan with the query, in stream order, instead.
  */
 sw_status sw_search(const int8_t* h_query, int32_t qlen, sw_db* db, const int64_t* h_offsets,
                     int64_t n, const int8_t* h_subst, int32_t gap_open, int32_t gap_extend,
