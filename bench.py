@@ -138,6 +138,18 @@ def cpu_baseline(queries, db, sm, seconds: float, mode: str = "local"):
             "extrapolated_step_s": round(full / (gcups * 1e9), 1), "host": host_report()}
 
 
+SERVE_POLICIES = ("plain", "paired", "pipelined", "served", "dynamic", "dynamic-q2", "srpt")
+
+
+def served_policies(args):
+    """(policies in order, headline policy) of the served form; SystemExit for a list without plain FIFO
+    and at least one other known policy."""
+    pols = [p for p in args.policies.split(",") if p]
+    if "plain" not in pols or len(set(pols)) < 2 or not set(pols) <= set(SERVE_POLICIES):
+        raise SystemExit(f"--policies: plain and at least one of {[p for p in SERVE_POLICIES if p != 'plain']}")
+    return pols, args.headline if args.headline in pols else [p for p in pols if p != "plain"][0]
+
+
 def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     """Served form: the serving policies against plain FIFO on one Poisson trace."""
     import torch
@@ -162,11 +174,7 @@ def serve_bench(args, sw, D, db, sm, total_res, perfmodel):
     print(f"# plain service time {service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
     trace = qs[: warm + args.requests]
     arrivals = synth.poisson_arrivals(rate, len(trace))
-    pols = [p for p in args.policies.split(",") if p]
-    known = {"plain", "paired", "pipelined", "served", "dynamic", "dynamic-q2", "srpt"}
-    if "plain" not in pols or len(set(pols)) < 2 or not set(pols) <= known:
-        raise SystemExit(f"--policies: plain and at least one of {sorted(known - {'plain'})}")
-    headline = args.headline if args.headline in pols else [p for p in pols if p != "plain"][0]
+    pols, headline = served_policies(args)
 
     def progress(name):
         step = max(1, args.requests // 5)
@@ -471,6 +479,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "copies": 3}))
         return
+    if args.form == "served":
+        served_policies(args)                  # a bad list fails before the 10M-subject workload is built
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(a search would shard the database across GPUs).", file=sys.stderr)

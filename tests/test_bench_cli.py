@@ -46,3 +46,15 @@ def test_traffic_figure_only_for_the_profiled_kernel_source():
     assert got is None or got == doc["hbm_bytes_per_launch_avg"]
     assert bench.measured_traffic(argparse.Namespace(form="plain", workload="sp570k", mode="global")) is None
     assert bench.measured_traffic(argparse.Namespace(form="batched", workload="sp570k", mode="local")) is None
+
+
+def test_served_policies_are_checked_before_any_work():
+    for bad in ("paired", "plain", "plain,bogus", "plain,plain"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--form", "served", "--policies", bad],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode != 0 and "--policies" in r.stderr, bad
+    import bench
+    ns = argparse.Namespace(policies="plain,pipelined,paired", headline="paired")
+    assert bench.served_policies(ns) == (["plain", "pipelined", "paired"], "paired")
+    ns = argparse.Namespace(policies="plain,served", headline="paired")
+    assert bench.served_policies(ns) == (["plain", "served"], "served")
