@@ -262,10 +262,13 @@ sw_status sw_search_batch(const int8_t* h_queries, const int64_t* h_qoffsets, in
  * ws_bytes >= that size (SW_E_SIZE otherwise), 256-byte aligned.  Allocates
  * no device memory; the captured graph of a batch shape is tied to the
  * workspace address (another address captures again).  The plan travels
- * with the queries into the workspace, in stream order, so the call never
- * waits for earlier work, and calls may be queued back to back on one
- * stream (a serving loop keeps the next batch queued while one runs).  The
- * workspace must stay untouched until the stream has completed the call.
+ * with the queries into the workspace, in stream order, so the call does not
+ * wait for earlier work, and calls may be queued back to back on one stream
+ * (a serving loop keeps the next batch queued while one runs).  Queries are
+ * staged through a ring of four pinned host buffers per handle: a call waits
+ * only until the staging copy of the call four before it on the handle has
+ * run.  The workspace must stay untouched until the stream has completed the
+ * call.
  */
 sw_status sw_batch_workspace_bytes(sw_db* db, const int64_t* h_qoffsets, int32_t nq, int32_t k,
                                    int32_t scores_in_ws, int64_t* bytes);

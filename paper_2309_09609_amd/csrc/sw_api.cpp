@@ -100,6 +100,8 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+constexpr int kStageRing = 4;         // pinned staging buffers per handle
+
 // Pinned staging buffer; the event marks completion of the last copy out of it.
 struct HostPinned {
     void* p = nullptr;
@@ -245,7 +247,10 @@ struct sw_db {
     // workspace of searches without a caller workspace (laid out by WsLayout)
     uint64_t gen = 1;                 // bumped on every workspace reallocation
     DevBuf ws_own;
-    HostPinned hstage;
+    // pinned staging of the queries (and, on a caller's workspace, the plan), a ring so that a call
+    // reuses a buffer only once the copy of the call kStageRing before it has run
+    HostPinned hstage[kStageRing];
+    int hstage_next = 0;
     std::map<int, Plan> plans;        // plain searches: query length -> plan
     Plan batch_plan, multi_plan;
     std::vector<int> batch_qlens;
@@ -636,7 +641,8 @@ sw_status ensure_geometry(sw_db* db) {
         if (!db->ev_fork) HIP_TRY(hipEventCreateWithFlags(&db->ev_fork, hipEventDisableTiming));
         if (!db->ev_join) HIP_TRY(hipEventCreateWithFlags(&db->ev_join, hipEventDisableTiming));
         if (!db->ev_join2) HIP_TRY(hipEventCreateWithFlags(&db->ev_join2, hipEventDisableTiming));
-        if (!db->hstage.done) HIP_TRY(hipEventCreateWithFlags(&db->hstage.done, hipEventDisableTiming));
+        for (HostPinned& h : db->hstage)
+            if (!h.done) HIP_TRY(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
         undo.done = true;
     }
     return SW_OK;
@@ -722,6 +728,7 @@ struct Work {
     int32_t* scores = nullptr;
     const WgItem* items = nullptr;
     const int2* qpairs = nullptr;
+    HostPinned* host = nullptr;       // the pinned staging buffer of this call
 };
 
 Work carve(void* base, const WsLayout& L) {
@@ -756,7 +763,10 @@ sw_status get_work(sw_db* db, const int64_t* h_qoffsets, int nq, int k, bool wit
         HIP_TRY(db->ws_own.reserve((size_t)L.total, &db->gen));
         *out = carve(db->ws_own.p, L);
     }
-    HIP_TRY(db->hstage.reserve(L.st.total));
+    HostPinned& hs = db->hstage[db->hstage_next];
+    db->hstage_next = (db->hstage_next + 1) % kStageRing;
+    HIP_TRY(hs.reserve(L.st.total));
+    out->host = &hs;
     if (plan) {
         if (caller) {
             out->items = reinterpret_cast<const WgItem*>(out->stage + L.st.off_items);
@@ -826,7 +836,7 @@ sw_status stage_queries(sw_db* db, const Work& W, const int8_t* h_queries, const
                         const int8_t* subst, int64_t score_row_stride, hipStream_t st, Staged* out,
                         int32_t* const* per_query_out = nullptr, const Plan* with_plan = nullptr) {
     const StageLayout& L = W.L.st;
-    char* h = static_cast<char*>(db->hstage.p);
+    char* h = static_cast<char*>(W.host->p);
     int64_t prof_off = 0;
     QDesc* qd = reinterpret_cast<QDesc*>(h);
     int64_t* qo = reinterpret_cast<int64_t*>(h + L.off_qoff);
@@ -850,8 +860,8 @@ sw_status stage_queries(sw_db* db, const Work& W, const int8_t* h_queries, const
             memcpy(h + L.off_pairs, with_plan->h_pairs.data(), with_plan->h_pairs.size() * sizeof(int2));
     }
     HIP_TRY(hipMemcpyAsync(W.stage, h, L.total, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(db->hstage.done, st));
-    db->hstage.pending = true;
+    HIP_TRY(hipEventRecord(W.host->done, st));
+    W.host->pending = true;
     const char* d = W.stage;
     out->qd = reinterpret_cast<const QDesc*>(d);
     out->qoff = reinterpret_cast<const int64_t*>(d + L.off_qoff);
@@ -1352,7 +1362,7 @@ void sw_db_free(sw_db* db) {
     db->align_dirs.release(); db->align_bnd.release(); db->align_misc.release(); db->align_tws.release();
     db->mode_plan.release();
     db->ws_own.release();
-    db->hstage.release();
+    for (HostPinned& h : db->hstage) h.release();
     for (auto& e : db->ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     if (db->side) hipStreamDestroy(db->side);
     if (db->side2) hipStreamDestroy(db->side2);

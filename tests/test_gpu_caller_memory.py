@@ -90,3 +90,36 @@ def test_workspace_and_image_sizes_are_checked(gpu, blosum):
     torch.cuda.synchronize()
     _eq(out.cpu().numpy(), oracle.scores(q, db.residues, db.offsets, blosum, 10, 2), "explicit ws")
     gpu.load().sw_db_free(h)
+
+
+def test_batched_calls_queued_back_to_back(gpu, blosum):
+    """Seven sw_search_batch_ws calls of different query-length mixes queued on one stream without a wait
+    in between (more calls than the library's pinned staging buffers), each on its own workspace; the
+    host query array is overwritten as soon as each call returns.  Every score and top 5 equals the oracle's."""
+    import torch
+    db = synth.small_db(seed=520, n=1800, lo=0, hi=900, median=250)
+    D = gpu.Database(db.residues, db.offsets, memory="torch", lane_pack=2)
+    mixes = [[144], [300, 280], [1], [700, 650], [90, 0], [512], [200, 210]]
+    calls, want = [], []
+    stream = torch.cuda.current_stream()
+    for c, lens in enumerate(mixes):
+        qs = [synth.small_query(seed=530 + 10 * c + i, m=m) for i, m in enumerate(lens)]
+        want.append([oracle.scores(q, db.residues, db.offsets, blosum, 10, 2) for q in qs])
+        qo = np.zeros(len(qs) + 1, np.int64)
+        qo[1:] = np.cumsum([q.size for q in qs])
+        flat = np.concatenate(qs) if qo[-1] else np.zeros(0, np.int8)
+        ws = torch.empty(gpu.sw_batch_workspace_bytes(D.handle, qo, 5, False), dtype=torch.uint8, device="cuda")
+        scores = torch.empty((len(qs), db.n), dtype=torch.int32, device="cuda")
+        ts = torch.empty((len(qs), 5), dtype=torch.int32, device="cuda")
+        ti = torch.empty((len(qs), 5), dtype=torch.int64, device="cuda")
+        gpu.sw_search_batch_ws(flat, qo, D.handle, blosum, 10, 2, 5, scores, ts, ti, ws, stream)
+        flat[:] = 0                                   # the call has staged its own copy
+        calls.append((scores, ts, ti, ws))
+    torch.cuda.synchronize()
+    for c, (scores, ts, ti, _) in enumerate(calls):
+        for i, w in enumerate(want[c]):
+            _eq(scores[i].cpu().numpy(), w, f"call {c} query {i}")
+            ws_, wi_ = oracle.topk(w, 5)
+            assert (ts[i].cpu().numpy() == ws_).all() and (ti[i].cpu().numpy() == wi_).all(), (c, i)
+    assert D.info()["device_bytes"] == 0
+    D.close()
