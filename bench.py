@@ -608,6 +608,18 @@ def main():
     res["extra"]["pack_s"] = round(pack_s, 3)
     if args.form == "plain":
         res["extra"]["topk"] = topk_timing(sw, out, 10)
+        # latency of one query at a time (after the timed steps): from the call to its scores on the device
+        lat = []
+        for q in queries:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            D.search(q, sm, 10, 2, out=out, mode=args.mode)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - a) * 1e3)
+        lat = np.asarray(lat)
+        res["extra"]["query_latency_ms"] = {"p50": round(float(np.percentile(lat, 50)), 3),
+                                            "p99": round(float(np.percentile(lat, 99)), 3),
+                                            "max": round(float(lat.max()), 3), "queries": int(lat.size)}
     if args.form == "plain" and not args.no_batched_compare and args.mode == "local":
         # the same queries in the batched form: one graph launch for all of them
         from paper_2309_09609_amd import tune as tuner
@@ -627,8 +639,10 @@ def main():
         bg = cells_step * args.steps / (tb1 - tb0) / 1e9
         # same scores as the plain form (the last plain step left query 19's scores in `out`)
         same = bool(torch.equal(bs[-1], out))
+        # every query of a batch completes with the batch: its latency is the batch's time
         res["extra"]["batched_same_queries"] = {"gcups": round(bg, 2), "gain_vs_plain": round(bg / gcups, 3),
                                                 "ms_per_step": round((tb1 - tb0) / args.steps * 1e3, 3),
+                                                "query_latency_ms": round((tb1 - tb0) / args.steps * 1e3, 3),
                                                 "knobs": tb["knobs"], "scores_equal_plain": same}
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -29,6 +29,8 @@ def test_bench_line_on_the_small_workload():
     assert roof["bound"] == "alu" and 0 < roof["frac"] <= 1 and roof["launches"] >= 1
     assert roof["traffic"] is None                     # measured for the 570k-subject workload only
     assert d["cpu_baseline"]["kind"] == "oracle" and d["cpu_baseline"]["value"] > 0
+    lat = d["extra"]["query_latency_ms"]
+    assert 0 < lat["p50"] <= lat["p99"] <= lat["max"] and lat["queries"] == d["config"]["queries"]
 
 
 def test_bench_line_of_the_pair_form():
