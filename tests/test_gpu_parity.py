@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from inputs import blosum62, synth
+from inputs import synth
 from refs import identity_matrix
 
 pytestmark = pytest.mark.gpu

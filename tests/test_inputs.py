@@ -1,5 +1,4 @@
 """Inputs: BLOSUM62 transcription checks, alphabet, synthetic workload recipe."""
-import json
 import os
 
 import numpy as np
