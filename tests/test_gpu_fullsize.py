@@ -9,7 +9,8 @@ the oracle recomputes what it can in seconds (tolerance 0, Eq. 1-3):
   every query (every 1,000th, the planted homologs, the three sentinels, every
   subject longer than 3,000, and the subject each query was built from), all
   570,000 scores of the 8 shortest queries, and every query's top 10 against
-  the oracle's top 10 of the GPU's own score row;
+  the oracle's top 10 of the GPU's own score row; the same batch with two
+  subjects per lane instead, every 4th query on the sampled subjects;
 * 64 queries of 500..5,000 against 10,000 subjects of 3,000..35,000: every
   500th subject and the planted homologs, for every query;
 * the 10,000,000-subject serving database: every 10,000th subject for each of
@@ -105,6 +106,32 @@ def test_batch256_top10_and_recompute(batch256):
     assert (b["S"][k, db.sentinels] > 32767).all()
     st = b["stats"]
     assert st["rerun_pairs"] >= 3 and st["recomputed"] == st["rerun_pairs"]
+
+
+def test_batch256_subject_pairs(gpu, blosum):
+    """The same batch with two subjects per lane (one query per lane, lane_pack 1): every 4th query on
+    the sampled subjects, every query's top 10 against the oracle's top 10 of the GPU's own row."""
+    import torch
+    db = synth.sp570k()
+    qs, sources = synth.workload3_queries(db, with_sources=True)
+    knobs = dict(rows_per_lane=16, unit_share=250, lane_pack=1)
+    say(f"batch256, subject pairs: {len(qs)} queries x {db.n} subjects, knobs {knobs}")
+    D = gpu.Database(db.residues, db.offsets, **knobs)
+    scores, ts, ti = D.search_batch(qs, blosum, 10, 2, k=10)
+    torch.cuda.synchronize()
+    S, ts, ti = scores.cpu().numpy(), ts.cpu().numpy(), ti.cpu().numpy()
+    st = D.stats()
+    del scores
+    D.close()
+    idx = np.unique(np.concatenate([synth.parity_sample(db), sources]))
+    for qi in range(0, len(qs), 4):
+        want = oracle.scores(qs[qi], db.residues, db.offsets, blosum, 10, 2, idx=idx)
+        _eq(S[qi, idx], want, f"batch256 subject pairs, query {qi}")
+    for qi in range(len(qs)):
+        ws, wi = _topk_of_row(S[qi], 10)
+        assert (ts[qi] == ws).all() and (ti[qi] == wi).all(), qi
+    assert st["rerun_pairs"] >= 3 and st["recomputed"] == st["rerun_pairs"]
+    say(f"batch256, subject pairs: {idx.size} subjects x {len(range(0, len(qs), 4))} queries equal")
 
 
 # ------------------------------------------------------------------ 64 queries x 10,000 long subjects
