@@ -12,6 +12,7 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -408,7 +409,8 @@ class Database:
         import torch
         subst = self.matrix(subst)
         if out is None:
-            out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+            with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+                out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
         # the handle was packed from self.offsets: no need for the library's O(n) offsets check per call
         if mode == "local" and self.memory == "torch":
             q = _host_i8(query)
@@ -451,11 +453,13 @@ class Database:
         qo[1:] = np.cumsum([q.size for q in qs])
         cat = np.concatenate(qs) if qs else np.zeros(0, np.int8)
         nq = len(qs)
-        scores = torch.empty((nq, self.n), dtype=torch.int32, device=self.device) if keep_scores else None
-        ts = ti = None
-        if k > 0:
-            ts = torch.empty((nq, k), dtype=torch.int32, device=self.device)
-            ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        # outputs come from the pool of the stream the search runs on
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            scores = torch.empty((nq, self.n), dtype=torch.int32, device=self.device) if keep_scores else None
+            ts = ti = None
+            if k > 0:
+                ts = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+                ti = torch.empty((nq, k), dtype=torch.int64, device=self.device)
         if self.memory == "torch":
             ws = self.workspace(qo, k, scores is None, stream)
             sw_search_batch_ws(cat, qo, self.handle, subst, gap_open, gap_extend, k, scores, ts, ti, ws, stream)
@@ -533,8 +537,9 @@ def topk(scores, k, stream=None):
     vector uses the two-launch form with a workspace from torch's allocator."""
     import torch
     lib = load()
-    ts = torch.empty(k, dtype=torch.int32, device=scores.device)
-    ti = torch.empty(k, dtype=torch.int64, device=scores.device)
+    with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+        ts = torch.empty(k, dtype=torch.int32, device=scores.device)
+        ti = torch.empty(k, dtype=torch.int64, device=scores.device)
     need = ctypes.c_int64()
     _check(lib.sw_topk_ws_bytes(scores.numel(), int(k), ctypes.byref(need)))
     ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=scores.device) if need.value > 0 else None
