@@ -308,7 +308,9 @@ class Database:
     ``memory="torch"``: torch allocates both (the image through
     ``sw_db_pack_into``, workspaces for ``sw_search_ws`` / ``sw_search_batch_ws``);
     the handle then holds no device memory of its own (global and semi-global
-    searches and alignments still use the handle's)."""
+    searches and alignments still use the handle's).  Searches through one
+    Database share its workspace: queue them on one stream, or let one finish
+    before starting the next on another stream."""
 
     def __init__(self, residues, offsets, device="cuda", stream=None, force_lanes=0, rerun_threshold=0,
                  rows_per_lane=0, unit_share=0, lane_pack=0, alphabet=0, rerun_cap=0, poison=0, memory="library",
