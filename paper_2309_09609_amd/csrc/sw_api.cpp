@@ -48,7 +48,7 @@ int64_t align_dir_bytes(int m, int64_t n);
 int64_t align_bnd_words(int64_t n);
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words, int max_mp,
-                          hipStream_t st);
+                          hipStream_t st, int add = 0);
 hipError_t launch_interleave(const int8_t* res, const int64_t* soff, const int32_t* slen, int64_t n, int A,
                              const GroupRec* groups, const int64_t* gdw, int ngroups, uint32_t* image,
                              int64_t total_dw, int32_t* err, hipStream_t st);
@@ -1806,27 +1806,42 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     if ((s = ensure_geometry(db)) != SW_OK) return s;
     if (db->wg_mode == 0) {
         int b1 = 0, b2 = 0;
+        int b3 = 0;
         HIP_TRY(sweep_occupancy_mode16(SW_GLOBAL, 16, &b1));
         HIP_TRY(sweep_occupancy_mode16(SW_SEMIGLOBAL, 16, &b2));
-        const int b = std::min(std::min(b1, b2), kMaxWgPerCu);
+        HIP_TRY(sweep_occupancy_mode16(kModeGlobalOffset, 16, &b3));
+        const int b = std::min(std::min(std::min(b1, b2), b3), kMaxWgPerCu);
         if (b < 1) return fail(SW_E_HIP, "16-bit end-to-end sweep cannot be resident");
         db->wg_mode = std::min(db->cus * b, db->wg16);     // within the 16-bit boundary slots
     }
     // 16-bit cells hold values in [128 - bias, kModeTop - bias).  Semi-global H never falls below the
-    // gap run down the query, -(Go + (m - 1) Ge), so its bias is just large enough for that (at most the
-    // middle of the range), which leaves the most room above for high scores; global H can fall further
-    // (gap runs along both sequences) and keeps the middle.
+    // gap run down the query, g(m) = -(Go + (m - 1) Ge), so its bias is just large enough for that (at
+    // most the middle of the range), which leaves the most room above for high scores.  Global mode with
+    // Ge <= Go runs on column-offset cells H' = H - g(j) (g(j) the row-0 gap run to column j): every H'
+    // is at least g(m) too, whatever the subject's length, so it takes the same bias; the profile then
+    // carries SM + Ge, E extends for free and opens at Go - Ge, and a score is H'[m][n] + g(n).  Global
+    // mode with Ge > Go keeps plain cells at the middle of the range, and so do long queries: their own
+    // bias is high, and their long similar subjects are lifted by -g(n) as well, so high scorers leave
+    // the range and go to the serial 32-bit recompute, where plain cells run the longest subjects in
+    // 32 bits beside the 16-bit launch.  Offset cells are used while the query's bias stays within 2/5
+    // of the middle one (queries up to about 3,100 residues at 10/2): there the 32-bit chain of a long
+    // subject, which they remove, is the longer path (measured on the 570,000-subject workload).
+    const int64_t offset_bias = 128 + (int64_t)gap_open + (int64_t)(qlen - 1) * gap_extend;
+    const bool offset = mode == SW_GLOBAL && gap_extend <= gap_open && 5 * offset_bias <= 2 * (int64_t)kModeBias;
     int32_t bias = kModeBias;
-    if (mode == SW_SEMIGLOBAL)
+    if (mode == SW_SEMIGLOBAL || offset)
         bias = (int32_t)std::min<int64_t>(kModeBias, 128 + (int64_t)gap_open + (int64_t)(qlen - 1) * gap_extend);
     // A query whose column-0 border (the gap run down its length) falls below the range runs wholly in
-    // 32-bit cells; in global mode so do the longest subjects, whose row-0 border does (a prefix of the
-    // length-sorted groups).
+    // 32-bit cells; with plain global cells so do the longest subjects, whose row-0 border does (a prefix
+    // of the length-sorted groups).
     const int64_t lowest = 128 - (int64_t)bias;
     int g_split = 0;                              // groups [0, g_split) run in 32-bit cells
     if (gap_run(qlen, gap_open, gap_extend) < lowest) g_split = db->ngroups;
-    else if (mode == SW_GLOBAL)
+    else if (mode == SW_GLOBAL && !offset)
         while (g_split < db->ngroups && gap_run(db->ncols[g_split], gap_open, gap_extend) < lowest) ++g_split;
+    const bool use_offset = offset && g_split == 0;
+    const int mode16 = use_offset ? kModeGlobalOffset : mode;      // the 16-bit kernels' form
+    const int32_t sm_shift = use_offset ? gap_extend : 0;
     // 16-bit plan at 16 rows per lane; the long pairs of a short query go to a side list at 4 or 8 rows
     std::vector<WgItem> mi, si, m32, s32;
     if (g_split < db->ngroups) {
@@ -1856,8 +1871,9 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
     if ((s = stage_queries(db, W, h_query, qo, 1, h_subst, 0, st, &S)) != SW_OK) return s;
     int32_t* ctr = W.counters;
     HIP_TRY(launch_profile(S.sm_q, db->alphabet, S.qd, S.nq, S.qoff, W.prof, ctr, kCounters, W.bits, W.L.bits_words,
-                           S.max_mp, st));
+                           S.max_mp, st, sm_shift));
     SweepArgs a = sweep_args(db, S, W, gap_open, gap_extend, d_scores_out);
+    a.sm_shift = sm_shift;
     a.items = db->mode_plan.items.as<WgItem>();
     a.n_items = (int32_t)n16;
     a.counter = ctr + 0;
@@ -1881,7 +1897,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         b.n_items = (int32_t)n16s;
         b.counter = ctr + 3;
         b.slot_base = grid;
-        HIP_TRY(launch_sweep_mode16(mode, db->mode_plan.R_side, b, grid_side, db->side));
+        HIP_TRY(launch_sweep_mode16(mode16, db->mode_plan.R_side, b, grid_side, db->side));
         HIP_TRY(hipEventRecord(db->ev_join, db->side));
     }
     if (!m32.empty()) {
@@ -1901,7 +1917,7 @@ sw_status sw_search_mode(int32_t mode, const int8_t* h_query, int32_t qlen, sw_d
         HIP_TRY(hipEventRecord(db->ev_join2, db->side2));
     }
     const int ev = db->timing ? record_timer_start(db, st) : -1;
-    if (n16 > 0) HIP_TRY(launch_sweep_mode16(mode, 16, a, grid, st));
+    if (n16 > 0) HIP_TRY(launch_sweep_mode16(mode16, 16, a, grid, st));
     // the recompute reads the side launches' rerun entries and reuses the 32-bit slots; the timed
     // region of the sweep ends when all three launches have
     if (n16s) HIP_TRY(hipStreamWaitEvent(st, db->ev_join, 0));

@@ -61,6 +61,10 @@ struct QDesc {
     int32_t mp;           // profile row stride (multiple of kProfRowAlign, >= m)
 };
 
+// Form of the 16-bit end-to-end sweep beside SW_GLOBAL (1) and SW_SEMIGLOBAL (2): global scores on
+// column-offset cells (Ge <= Go).
+constexpr int kModeGlobalOffset = 3;
+
 struct SweepArgs {
     const WgItem* items;
     const int32_t* n_items_dev;   // if non-null, the item count is read here (rerun launches)
@@ -91,6 +95,8 @@ struct SweepArgs {
                                   // end-to-end modes: the middle of the 16-bit range)
     const int2* qpairs;           // query-pair sweep: item.q indexes these (query a, query b or -1)
     const int32_t* slen;          // end-to-end modes: subject length per sorted slot (0 for padding slots)
+    int32_t sm_shift;             // global mode on column-offset cells: the profile holds SM + sm_shift on
+                                  // real residues; 32-bit cells subtract it again
 };
 
 // One (query, subject) pair of an alignment launch.

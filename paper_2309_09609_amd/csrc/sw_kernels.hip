@@ -210,6 +210,16 @@ struct CellI32 {
 #define SW_MBLKN(r, c, n) SWA(r, n) SWD(r, c) SWF(r) SWE(r) SWH SWG0(r) SWI
 #define SW_MLAST(r, c, rp) SWF(r) SWD(r, c) SWH SWE(r) SWM(rp, r) SWN(rp, r) SWG0(r) SWI
 
+// Global mode on column-offset cells (H' = H - g(j), Ge <= Go): E extends for free and opens at
+// Go - Ge, so E' = max(E, H' - (Go - Ge)) (%[es] holds H' - (Go - Ge), %[goe] is Go - Ge); F, the
+// diagonal and the folds as above.  The last row waits one state before its maximum reads F.
+#define SWX(r) "v_pk_sub_u16 %[es], %[h" #r "], %[goe] clamp\n"
+#define SWG3(r) "v_pk_max_i16 %[e" #r "], %[e" #r "], %[es]\n"
+#define SW_XBLK(r, c, n, k2, sel2) SWA(r, n) SWD(r, c) SWH SWX(r) SWE(r) SWP(k2, sel2) SWG3(r) SWI
+#define SW_XBLKS(r, c, n, k2, sel2, rp) SW_XBLK(r, c, n, k2, sel2) SWM(rp, r) SWN(rp, r)
+#define SW_XBLKN(r, c, n) SWA(r, n) SWD(r, c) SWH SWX(r) SWE(r) SWG3(r) SWI
+#define SW_XLAST(r, c, rp) "s_nop 0\n" SWD(r, c) SWH SWX(r) SWE(r) SWM(rp, r) SWN(rp, r) SWG3(r) SWI
+
 #define SW_HE(i) [h##i] "+v"(H[i]), [e##i] "+v"(E[i])
 #define SW_AB(i) [a##i] "v"(pa[i]), [b##i] "v"(pb[i])
 #define SW_W(i) [w##i] "v"(w[i])
@@ -308,6 +318,36 @@ __device__ __forceinline__ void rows16_pair_mode(s2* H, s2* E, s2& S, s2& lmin, 
     }
 }
 
+// Global mode on column-offset cells, subject-pair form, R = 16, 8 or 4 rows.
+#define SW_XMINS [dt] "v"(diag), [go] "s"(go), [ge] "s"(ge), [goe] "s"(goe), [s0] "s"(s0), [s1] "s"(s1)
+template <int R>
+__device__ __forceinline__ void rows16_pair_xmode(s2* H, s2* E, s2& S, s2& lmin, s2& F, s2 diag, const uint32_t* pa,
+                                                  const uint32_t* pb, u2 go, u2 ge, u2 goe) {
+    s2 d0, d1, hgo, es, fs, sm;
+    const uint32_t s0 = 0x05040100u, s1 = 0x07060302u;
+    if constexpr (R == 16) {
+        asm(SW_PRO SW_XBLK(0, 0, 1, 1, s0) SW_XBLKS(1, 1, 0, 1, s1, 0) SW_XBLK(2, 0, 1, 2, s0)
+                SW_XBLKS(3, 1, 0, 2, s1, 2) SW_XBLK(4, 0, 1, 3, s0) SW_XBLKS(5, 1, 0, 3, s1, 4) SW_XBLK(6, 0, 1, 4, s0)
+                    SW_XBLKS(7, 1, 0, 4, s1, 6) SW_XBLK(8, 0, 1, 5, s0) SW_XBLKS(9, 1, 0, 5, s1, 8)
+                        SW_XBLK(10, 0, 1, 6, s0) SW_XBLKS(11, 1, 0, 6, s1, 10) SW_XBLK(12, 0, 1, 7, s0)
+                            SW_XBLKS(13, 1, 0, 7, s1, 12) SW_XBLKN(14, 0, 1) SW_XLAST(15, 1, 14)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_HE(8), SW_HE(9),
+              SW_HE(10), SW_HE(11), SW_HE(12), SW_HE(13), SW_HE(14), SW_HE(15), SW_MOUTS
+            : SW_XMINS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3), SW_AB(4), SW_AB(5), SW_AB(6), SW_AB(7));
+    } else if constexpr (R == 8) {
+        asm(SW_PRO SW_XBLK(0, 0, 1, 1, s0) SW_XBLKS(1, 1, 0, 1, s1, 0) SW_XBLK(2, 0, 1, 2, s0)
+                SW_XBLKS(3, 1, 0, 2, s1, 2) SW_XBLK(4, 0, 1, 3, s0) SW_XBLKS(5, 1, 0, 3, s1, 4) SW_XBLKN(6, 0, 1)
+                    SW_XLAST(7, 1, 6)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_HE(4), SW_HE(5), SW_HE(6), SW_HE(7), SW_MOUTS
+            : SW_XMINS, SW_AB(0), SW_AB(1), SW_AB(2), SW_AB(3));
+    } else {
+        static_assert(R == 4, "rows per lane must be 4, 8 or 16");
+        asm(SW_PRO SW_XBLK(0, 0, 1, 1, s0) SW_XBLKS(1, 1, 0, 1, s1, 0) SW_XBLKN(2, 0, 1) SW_XLAST(3, 1, 2)
+            : SW_HE(0), SW_HE(1), SW_HE(2), SW_HE(3), SW_MOUTS
+            : SW_XMINS, SW_AB(0), SW_AB(1));
+    }
+}
+
 // ------------------------------------------------------------ one pass of one wave
 // Where a pass reads and writes.  The image resource covers the group's chunk
 // rows; the boundary resource covers the wave's slot for this unit, laid out
@@ -389,6 +429,8 @@ struct EndCtx {
     bool top;                 // pass 0: row 0 is the border
     bool last;                // the last pass: it holds the query's last row
     int bias;                 // 16-bit cells: the bias every value carries
+    int smshift;              // 32-bit cells: subtracted from every profile value (the profile of column-offset
+                              // global cells carries SM + smshift)
     __device__ int border(int k) const { return k <= 0 ? 0 : -(go + (k - 1) * ext); }
     // a value as a biased 16-bit cell, clamped to [0, 0x7FFF] (a clamped value fails the range check)
     __device__ short enc(int v) const { v += bias; return (short)(v < 0 ? 0 : v > 0x7FFF ? 0x7FFF : v); }
@@ -484,7 +526,7 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const T sv = C::sm(cur[r >> 1], cur[R / 2 + (r >> 1)], r);
-                        const T hd = T{dg.x + sv.x, dg.y + sv.y};
+                        const T hd = T{dg.x + sv.x - ec.smshift, dg.y + sv.y - ec.smshift};
                         const T h = T{max(max(hd.x, E[r].x), F.x), max(max(hd.y, E[r].y), F.y)};
                         dg = H[r];
                         H[r] = h;
@@ -573,15 +615,22 @@ __device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, i
     const int nloop = (nsteps + 3) >> 2;
     const bool first_lane = (b == 0);
 
+    // Column-offset global cells: column 0 is not offset, but as the diagonal of column 1 it reads
+    // g(i) + Go - Ge (the diagonal into column 1 gains Go, of which the profile adds Ge), and
+    // E'[i][1] = E[i][1] - g(1) = g(i).
+    constexpr bool kOff = MODE == kModeGlobalOffset;
+    const int dshift = kOff ? ec.go - ec.ext : 0;
+    const u2 goe = C::gapv(ec.go - ec.ext);
     T H[R], E[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const short hb = ec.enc(ec.border(min(ec.row0 + r + 1, ec.m)));   // H[i][0]; padded rows repeat row m's
+        const int hv = ec.border(min(ec.row0 + r + 1, ec.m));              // H[i][0]; padded rows repeat row m's
+        const short hb = ec.enc(hv + dshift);
         H[r] = T{hb, hb};
-        const short e = usub16(hb, ec.go);                                   // E[i][1]
+        const short e = kOff ? ec.enc(hv) : usub16(hb, ec.go);              // E[i][1]
         E[r] = T{e, e};
     }
-    const short hb0 = ec.enc(ec.border(min(ec.row0, ec.m)));
+    const short hb0 = ec.enc(ec.border(min(ec.row0, ec.m)) + dshift);
     T diag = T{hb0, hb0};          // H[row above][0]
     T up_h = diag, up_f = C::zero();   // what lane b-1 hands over before its first column
     const int rcap = ec.m - 1 - ec.row0;
@@ -617,7 +666,8 @@ __device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, i
             }
             const int col = 4 * c + u - (COOP ? b : 0);
             if (first_lane && ec.top) {
-                // row 0: the gap-run border (global; padded columns repeat the last real one) or 0
+                // row 0: the gap-run border (plain global cells; padded columns repeat the last real one), or
+                // 0 (semi-global, and column-offset global cells, where it is g(j) - g(j))
                 const short ta = ec.enc(MODE == 1 ? ec.border(min(col + 1, ec.na)) : 0);
                 const short tb = ec.enc(MODE == 1 ? ec.border(min(col + 1, ec.nb)) : 0);
                 htop = T{ta, tb};
@@ -626,14 +676,17 @@ __device__ __forceinline__ void sweep_pass_mode16(const PassIO& io, int ncols, i
             T F = ftop;
             // a cooperating lane starts b steps late and keeps the border until its first column (the
             // asm block runs under the lane mask)
-            if (!COOP || col >= 0) rows16_pair_mode<R>(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge);
+            if (!COOP || col >= 0) {
+                if constexpr (kOff) rows16_pair_xmode<R>(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge, goe);
+                else rows16_pair_mode<R>(H, E, lmax, lmin, F, diag, cur, cur + R / 2, go, ge);
+            }
             if (cap) {
                 T hc = H[0];
 #pragma unroll
                 for (int r = 1; r < R; ++r)
                     if (r == rcap) hc = H[r];
                 if (col >= 0) {                     // a lane before its first column captures nothing
-                    if (MODE == 1) {
+                    if (MODE == 1 || kOff) {
                         if (col == ec.na - 1) S.x = hc.x;
                         if (col == ec.nb - 1) S.y = hc.y;
                     } else {
@@ -776,6 +829,7 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         ec.go = a.go;
         ec.ge = a.ge;
         ec.ext = min(a.go, a.ge);
+        ec.smshift = a.sm_shift;
         const int slot0 = g * kGroupSubjects + 2 * su;
         ec.na = valid ? a.slen[slot0] : 0;
         ec.nb = valid ? a.slen[slot0 + 1] : 0;
@@ -879,8 +933,11 @@ __device__ __forceinline__ void run_unit(const SweepArgs& a, int g, int k, int l
         const int slot0 = g * kGroupSubjects + 2 * su;
         const int o0 = a.perm[slot0], o1 = a.perm[slot0 + 1];
         int32_t* out = Qa.out ? Qa.out : a.scores + Qa.out_off;
-        if (o0 >= 0) out[o0] = poisoned ? kPoison : C::lo(S) - ub;
-        if (o1 >= 0) out[o1] = poisoned ? kPoison : C::hi(S) - ub;
+        // column-offset global cells hold H'[m][n] = H[m][n] - g(n)
+        const int ra = MODE == kModeGlobalOffset ? ec.border(ec.na) : 0;
+        const int rb = MODE == kModeGlobalOffset ? ec.border(ec.nb) : 0;
+        if (o0 >= 0) out[o0] = poisoned ? kPoison : C::lo(S) - ub + ra;
+        if (o1 >= 0) out[o1] = poisoned ? kPoison : C::hi(S) - ub + rb;
         if (flag) append_rerun(a, g, qa, su);
     }
 }
@@ -1005,7 +1062,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
 // on the same stream).
 // The blocks of query 0 also clear the recompute's flag bits.
 __global__ void k_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff,
-                          int16_t* prof, int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words) {
+                          int16_t* prof, int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words,
+                          int add) {
     const int q = blockIdx.y;
     if (q == 0 && blockIdx.x == 0 && threadIdx.x < ncounters) counters[threadIdx.x] = 0;
     if (q == 0)
@@ -1020,7 +1078,7 @@ __global__ void k_profile(const int8_t* stage, int A, const QDesc* qd, int nq, c
         const int d = (int)(e / Q.mp);
         const int i = (int)(e - (int64_t)d * Q.mp);
         int16_t v = kPadScore;
-        if (d >= 1 && d <= A && i < Q.m) v = sm[query[i] * A + (d - 1)];
+        if (d >= 1 && d <= A && i < Q.m) v = (int16_t)(sm[query[i] * A + (d - 1)] + add);
         prof[Q.prof_off + e] = v;
     }
 }
@@ -1249,6 +1307,10 @@ static const void* mode16_kernel(int mode, int R) {
         return R == 16 ? (const void*)k_sweep<CellI16, 16, 2>
              : R == 8  ? (const void*)k_sweep<CellI16, 8, 2>
              : R == 4  ? (const void*)k_sweep<CellI16, 4, 2> : nullptr;
+    if (mode == 3)
+        return R == 16 ? (const void*)k_sweep<CellI16, 16, 3>
+             : R == 8  ? (const void*)k_sweep<CellI16, 8, 3>
+             : R == 4  ? (const void*)k_sweep<CellI16, 4, 3> : nullptr;
     return nullptr;
 }
 
@@ -1285,11 +1347,11 @@ hipError_t sweep_occupancy(bool i16, int R, int* blocks_per_cu) {
 
 hipError_t launch_profile(const int8_t* stage, int A, const QDesc* qd, int nq, const int64_t* qoff, int16_t* prof,
                           int32_t* counters, int ncounters, uint32_t* bits, int64_t nbits_words, int max_mp,
-                          hipStream_t st) {
+                          hipStream_t st, int add) {
     const int64_t work = std::max<int64_t>((int64_t)kNRes * max_mp, nbits_words);
     const int bx = (int)std::min<int64_t>((work + 255) / 256, 1024);
     hipLaunchKernelGGL(k_profile, dim3(bx, std::max(nq, 1)), dim3(256), 0, st, stage, A, qd, nq, qoff, prof,
-                       counters, ncounters, bits, nbits_words);
+                       counters, ncounters, bits, nbits_words, add);
     return hipGetLastError();
 }
 

@@ -106,11 +106,10 @@ def test_mode_range_and_argument_errors(gpu, blosum):
 
 @pytest.mark.parametrize("mode", ["global", "semiglobal"])
 def test_mode_scores_beyond_the_16bit_range(gpu, blosum, mode):
-    """Global 16-bit cells hold values within about +-15,700 of the middle of
-    their range; semi-global cells start just above the lowest value the query
-    allows (-(Go + (m - 1) Ge)) and reach higher.  A 33,000-point self alignment
-    leaves either range, a 22,000-point one only the global range; both go to the
-    32-bit recompute, exactly."""
+    """16-bit cells start just above the lowest value the query allows
+    (-(Go + (m - 1) Ge)): semi-global H, and global H - g(j) on column-offset
+    cells, never fall below it.  A 33,000-point self alignment leaves the range
+    and goes to the 32-bit recompute, exactly; a 22,000-point one stays in it."""
     W = 17
     rng = np.random.default_rng(44)
     subs = [np.full(3000, W, np.int8), np.concatenate([np.full(1000, W, np.int8), synth.background_residues(rng, 300)])]
@@ -122,10 +121,7 @@ def test_mode_scores_beyond_the_16bit_range(gpu, blosum, mode):
     _check(gpu, D, db, np.full(3000, W, np.int8), blosum, 10, 2, mode, f"{mode} W-run 3000")
     assert D.stats()["rerun_pairs"] >= 1
     _check(gpu, D, db, np.full(2000, W, np.int8), blosum, 10, 2, mode, f"{mode} W-run 2000")
-    if mode == "global":
-        assert D.stats()["rerun_pairs"] >= 1
-    else:
-        assert D.stats()["rerun_pairs"] == 0
+    assert D.stats()["rerun_pairs"] == 0
     _check(gpu, D, db, synth.small_query(seed=45, m=300), blosum, 10, 2, mode, f"{mode} short query")
     D.close()
 
@@ -143,11 +139,12 @@ def test_mode_forced_recompute(gpu, blosum, mode, lanes):
     D.close()
 
 
-@pytest.mark.parametrize("mode", ["global", "semiglobal"])
-def test_modes_with_the_longest_group_in_32bit_cells(gpu, blosum, mode):
-    """Global mode: subjects whose row-0 border leaves the 16-bit range (a gap run
-    of more than ~7,800 residues at 10/2) form the first length-sorted group and
-    run in 32-bit cells beside the 16-bit launch of the other groups."""
+@pytest.mark.parametrize("mode,go,ge", [("global", 3, 5), ("global", 10, 2), ("semiglobal", 10, 2)])
+def test_modes_with_the_longest_group_in_32bit_cells(gpu, blosum, mode, go, ge):
+    """Global mode on plain cells (Ge > Go): subjects whose row-0 border leaves the
+    16-bit range form the first length-sorted group and run in 32-bit cells beside
+    the 16-bit launch of the other groups.  With Ge <= Go the column-offset cells
+    hold the same subjects in 16 bits."""
     rng = np.random.default_rng(46)
     lens = [20000, 9000, 8000] + list(rng.integers(1, 900, 400))
     subs = [synth.background_residues(rng, int(L)) for L in lens]
@@ -156,11 +153,30 @@ def test_modes_with_the_longest_group_in_32bit_cells(gpu, blosum, mode):
     db = synth.Database(np.concatenate(subs), offs)
     D = gpu.Database(db.residues, db.offsets)
     for m in (90, 700, 900):
-        _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, 10, 2, mode, f"{mode} m={m}")
+        _check(gpu, D, db, synth.small_query(seed=m, m=m), blosum, go, ge, mode, f"{mode} {go}/{ge} m={m}")
         st = D.stats()
         assert st["items"] + st["side_items"] > 0
-        if mode == "global":
+        if mode == "global" and ge > go:
             assert st["side_items"] > 0
+    D.close()
+
+
+def test_global_offset_cells_and_the_32bit_fallback(gpu, blosum):
+    """Global scores with Ge <= Go: short queries against subjects up to 12,000
+    residues on column-offset 16-bit cells; a query of 8,000 residues, whose own
+    gap run leaves any 16-bit range, wholly in 32-bit cells; Ge > Go on plain cells."""
+    rng = np.random.default_rng(48)
+    lens = [12000, 9000, 7000] + list(rng.integers(0, 700, 120))
+    subs = [synth.background_residues(rng, int(L)) for L in lens]
+    subs[5] = synth.small_query(seed=49, m=300)                   # equal to the second query below
+    offs = np.zeros(len(subs) + 1, np.int64)
+    offs[1:] = np.cumsum([x.size for x in subs])
+    db = synth.Database(np.concatenate(subs), offs)
+    D = gpu.Database(db.residues, db.offsets)
+    for m, seed in ((1, 50), (300, 49), (2000, 51), (8000, 52)):
+        q = synth.small_query(seed=seed, m=m)
+        for go, ge in ((10, 2), (5, 5), (2, 7)):
+            _check(gpu, D, db, q, blosum, go, ge, "global", f"global m={m} {go}/{ge}")
     D.close()
 
 

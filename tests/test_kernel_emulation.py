@@ -306,3 +306,102 @@ def test_mode16_out_of_range_pairs_are_flagged(mode):
         assert (~ok).any()
         wrong = got != want
         assert not (wrong & ok).any()
+
+
+# ------------------------------------------------------------------ global mode, column-offset cells
+def emulate_global_offset16(q, subjects, sm, go, ge, bias):
+    """The 16-bit global sweep on column-offset cells (Ge <= Go): every cell holds H'[i][j] = H[i][j] - g(j),
+    g the row-0 gap run, so that the row-0 border is 0 and a long subject's border no longer leaves the
+    range.  Then the diagonal gains Ge (the profile carries SM + Ge on real residues, 0 on padding), E
+    extends for free and opens at Go - Ge, F is unchanged; column 0 as a diagonal reads g(i) + Go - Ge,
+    E'[i][1] = g(i).  Returns (H'[m][n] + g(n), in_range) per subject."""
+    assert ge <= go
+    sm = np.asarray(sm, np.int32)
+    m = q.size
+    Q, D = _pad_batch(q, subjects)
+    nsub, width = D.shape
+    P = _scores(sm, Q, D)
+    real = (Q[:, None, None] >= 0) & (D[None, :, :] >= 0)
+    P = np.where(real, P + ge, 0)
+    lens = np.array([s.size for s in subjects])
+    enc = lambda v: np.clip(np.asarray(v, np.int64) + bias, 0, 0x7FFF).astype(np.uint16)  # noqa: E731
+    rows = Q.size
+    H = np.stack([np.full(nsub, enc(_border(min(i + 1, m), go, ge) + go - ge), np.uint16) for i in range(rows)])
+    E = np.stack([np.full(nsub, enc(_border(min(i + 1, m), go, ge)), np.uint16) for i in range(rows)])
+    hm = enc(_border(m, go, ge))
+    S = np.where(lens == 0, hm, 0).astype(np.uint16)
+    lmin = np.full(nsub, hm, np.uint16)
+    lmax = np.zeros(nsub, np.uint16)
+    top = np.full(nsub, enc(0), np.uint16)
+    for j in range(width):
+        diag = np.full(nsub, enc(go - ge), np.uint16) if j == 0 else top
+        F = sub_u16_clamp(top, go)
+        for i in range(rows):
+            hd = add_i16_clamp(diag, P[i, :, j])
+            h = f16max(hd, E[i], F)
+            hge = sub_u16_clamp(h, go - ge)
+            hgo = sub_u16_clamp(h, go)
+            fs = sub_u16_clamp(F, ge)
+            E[i] = max_i16(E[i], hge)
+            F = max_i16(fs, hgo)
+            lmax = f16max(lmax, h)
+            lmin = f16min(lmin, h)
+            if i == m - 1:
+                S = np.where(j == lens - 1, h, S)
+            diag = H[i].copy()
+            H[i] = h
+    in_range = (lmin >= MODE_LO) & (lmax < MODE_TOP)
+    out = S.astype(np.int64) - bias + np.array([_border(n, go, ge) for n in lens])
+    return out, in_range
+
+
+def _offset_bias(m, go, ge):
+    return min(MODE_BIAS, 128 + go + (m - 1) * ge)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_global_offset16_equals_oracle(seed):
+    """In-range pairs equal the oracle's global score, including subjects far longer than the query whose
+    row-0 gap run alone would leave the range of plain biased cells."""
+    rng = np.random.default_rng(60 + seed)
+    sm = blosum62()
+    q = synth.background_residues(rng, int(rng.integers(1, 50)))
+    subs = [synth.background_residues(rng, int(L)) for L in rng.integers(0, 90, 30)]
+    subs[1] = q.copy()
+    subs[2] = np.zeros(0, np.int8)
+    for go, ge in ((10, 2), (3, 3), (11, 1), (0, 0)):
+        got, ok = emulate_global_offset16(q, subs, sm, go, ge, _offset_bias(q.size, go, ge))
+        want = np.array([oracle.pair_mode(q, s, sm, go, ge, "global") for s in subs])
+        assert ok.all(), (go, ge)
+        assert (got == want).all(), (go, ge, np.nonzero(got != want), got, want)
+
+
+def test_global_offset16_long_subjects_stay_in_range():
+    """A 20-residue query against subjects of up to 9,000 residues: the gap runs along the subjects reach
+    -18,000, below what plain biased cells hold, while the offset cells stay in range and exact."""
+    rng = np.random.default_rng(70)
+    sm = blosum62()
+    q = synth.background_residues(rng, 20)
+    subs = [synth.background_residues(rng, L) for L in (1, 19, 20, 21, 500, 9000)]
+    bias = _offset_bias(q.size, 10, 2)
+    assert _border(9000, 10, 2) + MODE_BIAS < MODE_LO          # out of range for the plain cells
+    got, ok = emulate_global_offset16(q, subs, sm, 10, 2, bias)
+    want = np.array([oracle.pair_mode(q, s, sm, 10, 2, "global") for s in subs])
+    assert ok.all()
+    assert (got == want).all(), (got, want)
+
+
+def test_global_offset16_out_of_range_pairs_are_flagged():
+    """Runs of +127 matches drive H' above the range (it never falls below g(m), which the bias covers,
+    -128 mismatches included); every pair whose score the offset cells do not reproduce is flagged."""
+    rng = np.random.default_rng(71)
+    sm = identity_matrix(127, -128)
+    q = np.full(260, 4, np.int8)
+    subs = [np.full(int(L), 4, np.int8) for L in (0, 3, 60, 250, 260, 400)]
+    subs += [rng.integers(0, 20, int(L)).astype(np.int8) for L in (10, 90, 200)]
+    for go, ge in ((10, 2), (300, 60)):
+        got, ok = emulate_global_offset16(q, subs, sm, go, ge, _offset_bias(q.size, go, ge))
+        want = np.array([oracle.pair_mode(q, s, sm, go, ge, "global") for s in subs])
+        assert (got[ok] == want[ok]).all()
+        assert (~ok).any()
+        assert not ((got != want) & ok).any()
