@@ -310,9 +310,11 @@ enum { SW_LOCAL = 0, SW_GLOBAL = 1, SW_SEMIGLOBAL = 2 };
  *                  against any stretch of the subject).
  * Scores may be negative.  Cells are 16-bit with a bias and a check that
  * every H of a pair stayed in the exact range; pairs that left it are
- * recomputed in 32-bit cells, and in SW_GLOBAL subjects whose row-0 gap run
- * leaves the range run in 32-bit cells from the start, so every score is
- * exact.  SW_E_UNSUPPORTED if Go + (qlen + longest subject) * max(Go, Ge)
+ * recomputed in 32-bit cells, so every score is exact.  SW_GLOBAL with
+ * Ge <= Go and a query of at most about 3,100 residues (at 10/2) stores
+ * H[i][j] - g(j) in its cells, which keeps every subject's row-0 gap run in
+ * range; otherwise subjects whose row-0 gap run leaves the range run in 32-bit
+ * cells from the start.  SW_E_UNSUPPORTED if Go + (qlen + longest subject) * max(Go, Ge)
  * could leave +-2^29.  Other arguments and errors as for sw_search;
  * sw_last_stats reports the 16-bit launch (out[0], out[2]) and, in out[4] and
  * out[5], the launches beside it (long pairs of a short query at 4 or 8 rows
