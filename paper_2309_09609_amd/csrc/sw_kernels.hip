@@ -589,7 +589,9 @@ __device__ __forceinline__ void sweep_pass(const PassIO& io, int ncols, int B, i
 }
 
 // End-to-end modes in 16-bit cells (subject pairs, R rows per lane).  Values
-// carry the bias ec.bias (the middle of the 16-bit range), so that
+// carry the bias ec.bias (the middle of the 16-bit range for plain global
+// cells, just above -g(m) for semi-global and column-offset global cells, which
+// hold H - g(j) and never fall below g(m)), so that
 // H = max(hd, E, F) is one v_pk_maximum3_f16 as in the local sweep; there is
 // no floor, and a subtraction that saturates at 0 only stands for a value
 // below the range.  lmin and lmax fold every H: while all of a pair's H stay
@@ -1055,8 +1057,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_sweep_q2(SweepArgs a) {
 }
 
 // ------------------------------------------------------------ query profile
-// prof[d][i] = SM(Q[i], d - 1) for image codes d = 1..A and i < m; kPadScore
-// for d = 0 (padding), d > A and past m.  One staging buffer holds the A x A
+// prof[d][i] = SM(Q[i], d - 1) + add for image codes d = 1..A and i < m
+// (add = Ge for column-offset global cells, else 0); kPadScore for d = 0
+// (padding), d > A and past m.  One staging buffer holds the A x A
 // matrix (in a kMaxAlphabet^2-byte region) followed by the query codes.
 // Thread 0 also zeroes the launch counters (they are consumed by later kernels
 // on the same stream).
